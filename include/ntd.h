@@ -1,0 +1,136 @@
+/*
+ * ntd.h -- C ABI of the MI355X (gfx950) library for the nested, twisted
+ * frequency-filtering preconditioned conjugate gradient method of
+ * Aggarwal, Kakkar and Kumar, arXiv:1909.09771 ("NTD").
+ *
+ * Problem (Sec. 1, eq. diffeqn): -div(kappa grad u) = f on a structured
+ * nx x ny x nz grid, u = 0 on Dirichlet faces, du/dn = 0 on Neumann faces,
+ * discretised by the 7-point finite-difference stencil.  The matrix A is the
+ * nested block tridiagonal matrix of Sec. 2 (planes -> lines -> points).
+ *
+ * Layout of every grid vector: FP64, x fastest, C-contiguous [nz][ny][nx],
+ * unknown p = i + nx*(j + ny*k).  Unless a comment says "host", every pointer
+ * is a DEVICE pointer on the current HIP device and stays owned by the caller.
+ * `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *
+ * Error behaviour: every entry point returns an int status (NTD_OK = 0 or one
+ * of the codes below); nothing throws across the ABI and nothing aborts.  On
+ * an error the output buffers are unspecified unless stated otherwise.
+ *
+ * Threading: a handle must not be used from two host threads or two streams
+ * at the same time; distinct handles are independent.
+ */
+#ifndef NTD_H
+#define NTD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ntd_handle ntd_handle;
+
+/* Status codes. */
+#define NTD_OK 0
+#define NTD_EINVAL 1       /* bad argument: size, pointer, workspace, kappa or t not finite > 0, ... */
+#define NTD_ENOMEM 2       /* host-side allocation failed */
+#define NTD_ENOTSPD 3      /* a pivot of the factorization is not positive and finite */
+#define NTD_EBREAKDOWN 4   /* PCG: p'Ap <= 0 or not finite */
+#define NTD_ENOCONV 5      /* PCG: maxit reached before the tolerance */
+#define NTD_EHIP 6         /* a HIP runtime call failed */
+
+/* Boundary type of a face; faces are ordered x-, x+, y-, y+, z-, z+. */
+#define NTD_BC_DIRICHLET 0
+#define NTD_BC_NEUMANN 1
+
+/* Arithmetic of the preconditioner.  FP64: factors and sweeps in double.
+ * MIXED: factors rounded to float after an FP64 setup and sweeps in float,
+ * except the twist (meeting) row of every line, whose pivot and update stay in
+ * double; CG vectors, SpMV, dot products and residual updates are always FP64. */
+#define NTD_PREC_FP64 0
+#define NTD_PREC_MIXED 1
+
+/* Approximate Schur block of a neighbour block (Sec. 2.1).
+ * NEWTON: 2b - b P b with b = diag((Pt^{-1} w)./w), w = coupling .* t (the
+ *   paper's formula), plus a diagonal compensation at the plane level so that
+ *   B t = A t holds exactly although the inner plane solve is approximate.
+ * DIAG: the diagonal b itself (classical tangential filtering); filter-exact
+ *   without compensation.  Both give an SPD B whenever every pivot is > 0. */
+#define NTD_SCHUR_NEWTON 0
+#define NTD_SCHUR_DIAG 1
+
+/* Largest supported line length nx (one wavefront solves one line). */
+#define NTD_MAX_NX 1024
+
+/* Bytes of device workspace that ntd_setup needs for this grid and precision.
+ * Returns 0 for invalid sizes. */
+size_t ntd_workspace_bytes(int nx, int ny, int nz, int prec);
+
+/* Assemble A from kappa and the face types, then factor B (Sec. 2.1: the
+ * level-3 plane recurrence, the level-2 line recurrence of every plane, the
+ * level-1 twisted pivots of every line).
+ *   kappa     [N] device, finite and > 0
+ *   bc        [6] HOST, NTD_BC_* per face; at least one Dirichlet face
+ *   t         [N] device filter vector, finite and > 0, or NULL for t = 1
+ *             (the rowsum filter, eq. rowsum); B depends only on its direction
+ *   prec      NTD_PREC_*; schur NTD_SCHUR_*
+ *   workspace device buffer of >= ntd_workspace_bytes() bytes, 256-byte
+ *             aligned, owned by the caller and used by the handle until
+ *             ntd_destroy; its contents need no initialisation
+ * Synchronises `stream`.  On success *out receives a new handle; on failure
+ * *out = NULL (NTD_ENOTSPD if a pivot is not positive). */
+int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const double *t,
+              int prec, int schur, void *workspace, size_t workspace_bytes, void *stream,
+              ntd_handle **out);
+
+/* z = B^{-1} r (Sec. 2.2, Algorithms 1-7: level-3 twisted block sweeps over
+ * planes, each plane block solved by level-2 sweeps over lines, each line by
+ * the exact twisted tridiagonal solve).  r and z are [N] device FP64 and must
+ * not overlap.  Stream-ordered, asynchronous. */
+int ntd_apply_precond(ntd_handle *h, const double *r, double *z, void *stream);
+
+/* y = A x with the assembled 7-point bands.  [N] device FP64, no overlap.
+ * Stream-ordered, asynchronous. */
+int ntd_spmv(ntd_handle *h, const double *x, double *y, void *stream);
+
+/* *result (HOST) = x . y over the N entries, FP64, fixed summation order
+ * (bitwise reproducible run to run).  Synchronises `stream`. */
+int ntd_dot(ntd_handle *h, const double *x, const double *y, double *result, void *stream);
+
+/* Preconditioned CG for A x = b (Sec. 1; stopping rule of Sec. 3): x0 = 0,
+ * iterate until ||r||/||b|| <= tol on the recursively updated residual and the
+ * true residual ||b - A x||/||b|| confirms it.  b, x [N] device FP64.
+ * *iters (HOST) = products with A taken in the loop; *relres (HOST) = final
+ * true relative residual.  Returns NTD_ENOCONV after maxit iterations (x then
+ * holds the last iterate) and NTD_EBREAKDOWN if p'Ap <= 0.  Synchronises. */
+int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int maxit, int *iters,
+                  double *relres, void *stream);
+
+/* Copy an internal array of the handle into dst ([N] device FP64), for tests
+ * and diagnostics.  which: 0..3 = bands d, ax, ay, az of A; 4 = e1 (x-band of
+ * the line blocks T); 5 = 1/pivot of T; 6 = f2 (y-band of the plane blocks P);
+ * 7 = diagonal of T; 8 = diagonal of P; 9 = x-band of P. Stream-ordered. */
+int ntd_export(const ntd_handle *h, int which, double *dst, void *stream);
+
+/* Replace the factors of the handle by given FP64 ones (e1, pivots M -- not
+ * their inverse --, f2; [N] device each), e.g. those of a reference setup, so
+ * that the apply can be checked on its own.  MIXED handles re-round them to
+ * float.  Stream-ordered. */
+int ntd_load_factors(ntd_handle *h, const double *e1, const double *pivots, const double *f2,
+                     void *stream);
+
+/* Device bytes the handle keeps in use inside its workspace. */
+size_t ntd_footprint_bytes(const ntd_handle *h);
+
+/* Release the host-side state of the handle (not the caller's workspace). */
+int ntd_destroy(ntd_handle *h);
+
+/* Static text for a status code. */
+const char *ntd_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NTD_H */

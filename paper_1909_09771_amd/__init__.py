@@ -1,0 +1,205 @@
+"""MI355X (gfx950) library for the nested, twisted frequency-filtering
+preconditioned conjugate gradient method of arXiv:1909.09771.
+
+This module is argument marshalling only: every step (assembly, factorization,
+preconditioner apply, SpMV, reductions, PCG) runs in the HIP kernels of
+libntd.so behind the C ABI of include/ntd.h.  PyTorch provides device memory
+and the current HIP stream.  There is no CPU fallback: if libntd.so is missing
+or no GPU is present the calls raise.
+
+Grid vectors are float64 CUDA tensors of shape (nz, ny, nx), C-contiguous.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libntd.so")
+
+OK, EINVAL, ENOMEM, ENOTSPD, EBREAKDOWN, ENOCONV, EHIP = range(7)
+PREC = {"fp64": 0, "mixed": 1}
+SCHUR = {"newton": 0, "diag": 1}
+EXPORTS = {"d": 0, "ax": 1, "ay": 2, "az": 3, "e1": 4, "minv": 5, "f2": 6, "dT": 7, "dP": 8,
+           "xP": 9}
+MAX_NX = 1024
+
+_lib = None
+
+
+class NTDError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__("%s: %s (status %d)" % (what, strerror(status), status))
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """Load libntd.so (built in-tree by build.py); raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libntd.so is not built: run paper_1909_09771_amd/build.py "
+                               "(or __graft_entry__.build()) first")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, D, Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        L.ntd_workspace_bytes.argtypes = [I, I, I, I]
+        L.ntd_workspace_bytes.restype = Z
+        L.ntd_setup.argtypes = [I, I, I, P, P, P, I, I, P, Z, P, ctypes.POINTER(P)]
+        L.ntd_setup.restype = I
+        L.ntd_apply_precond.argtypes = [P, P, P, P]
+        L.ntd_apply_precond.restype = I
+        L.ntd_spmv.argtypes = [P, P, P, P]
+        L.ntd_spmv.restype = I
+        L.ntd_dot.argtypes = [P, P, P, ctypes.POINTER(D), P]
+        L.ntd_dot.restype = I
+        L.ntd_pcg_solve.argtypes = [P, P, P, D, I, ctypes.POINTER(I), ctypes.POINTER(D), P]
+        L.ntd_pcg_solve.restype = I
+        L.ntd_export.argtypes = [P, I, P, P]
+        L.ntd_export.restype = I
+        L.ntd_load_factors.argtypes = [P, P, P, P, P]
+        L.ntd_load_factors.restype = I
+        L.ntd_footprint_bytes.argtypes = [P]
+        L.ntd_footprint_bytes.restype = Z
+        L.ntd_destroy.argtypes = [P]
+        L.ntd_destroy.restype = I
+        L.ntd_strerror.argtypes = [I]
+        L.ntd_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return lib().ntd_strerror(int(status)).decode()
+
+
+def workspace_bytes(nx: int, ny: int, nz: int, prec: str = "mixed") -> int:
+    return int(lib().ntd_workspace_bytes(nx, ny, nz, PREC[prec]))
+
+
+def _stream_ptr(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_vec(t: torch.Tensor, shape, device, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must be a contiguous float64 tensor of shape %s" % (name, shape))
+    if t.device != device:
+        raise ValueError("%s is on %s, the solver on %s" % (name, t.device, device))
+
+
+class Solver:
+    """A factored preconditioner B for one grid, kappa field, boundary set and filter.
+
+    kappa: float64 CUDA tensor (nz, ny, nx), > 0.  bc: six ints (x-, x+, y-, y+,
+    z-, z+), 0 = Dirichlet, 1 = Neumann.  t: optional filter vector (> 0), default
+    ones.  prec: "fp64" or "mixed".  schur: "newton" or "diag".
+    """
+
+    def __init__(self, kappa: torch.Tensor, bc, t: torch.Tensor | None = None,
+                 prec: str = "mixed", schur: str = "diag"):
+        if kappa.dim() != 3:
+            raise ValueError("kappa must have shape (nz, ny, nx)")
+        self.shape = tuple(kappa.shape)
+        self.device = kappa.device
+        nz, ny, nx = self.shape
+        _check_vec(kappa, self.shape, self.device, "kappa")
+        if t is not None:
+            _check_vec(t, self.shape, self.device, "t")
+        self.prec, self.schur = prec, schur
+        L = lib()
+        nbytes = int(L.ntd_workspace_bytes(nx, ny, nz, PREC[prec]))
+        if nbytes == 0:
+            raise NTDError(EINVAL, "ntd_workspace_bytes(%d, %d, %d)" % (nx, ny, nz))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        bc_arr = (ctypes.c_int * 6)(*[int(v) for v in bc])
+        h = ctypes.c_void_p()
+        st = L.ntd_setup(nx, ny, nz, _dptr(kappa), bc_arr, _dptr(t) if t is not None else None,
+                         PREC[prec], SCHUR[schur], _dptr(self.workspace), nbytes,
+                         _stream_ptr(self.device), ctypes.byref(h))
+        if st != OK:
+            raise NTDError(st, "ntd_setup")
+        self._h = h
+
+    # -- the hot path -------------------------------------------------------
+    def apply(self, r: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """z = B^{-1} r (stream-ordered)."""
+        _check_vec(r, self.shape, self.device, "r")
+        z = torch.empty_like(r) if out is None else out
+        _check_vec(z, self.shape, self.device, "out")
+        st = lib().ntd_apply_precond(self._h, _dptr(r), _dptr(z), _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_apply_precond")
+        return z
+
+    def spmv(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        _check_vec(x, self.shape, self.device, "x")
+        y = torch.empty_like(x) if out is None else out
+        _check_vec(y, self.shape, self.device, "out")
+        st = lib().ntd_spmv(self._h, _dptr(x), _dptr(y), _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_spmv")
+        return y
+
+    def dot(self, x: torch.Tensor, y: torch.Tensor) -> float:
+        _check_vec(x, self.shape, self.device, "x")
+        _check_vec(y, self.shape, self.device, "y")
+        res = ctypes.c_double(0.0)
+        st = lib().ntd_dot(self._h, _dptr(x), _dptr(y), ctypes.byref(res),
+                           _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_dot")
+        return res.value
+
+    def pcg(self, b: torch.Tensor, tol: float = 1e-8, maxit: int = 200,
+            x: torch.Tensor | None = None):
+        """Solve A x = b; returns (x, iterations, true relative residual, status).
+        status is OK, ENOCONV or EBREAKDOWN; other failures raise."""
+        _check_vec(b, self.shape, self.device, "b")
+        x = torch.empty_like(b) if x is None else x
+        _check_vec(x, self.shape, self.device, "x")
+        it = ctypes.c_int(0)
+        rr = ctypes.c_double(0.0)
+        st = lib().ntd_pcg_solve(self._h, _dptr(b), _dptr(x), float(tol), int(maxit),
+                                 ctypes.byref(it), ctypes.byref(rr), _stream_ptr(self.device))
+        if st not in (OK, ENOCONV, EBREAKDOWN):
+            raise NTDError(st, "ntd_pcg_solve")
+        return x, it.value, rr.value, st
+
+    # -- inspection ---------------------------------------------------------
+    def export(self, which: str) -> torch.Tensor:
+        out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        st = lib().ntd_export(self._h, EXPORTS[which], _dptr(out), _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_export")
+        return out
+
+    def load_factors(self, e1: torch.Tensor, pivots: torch.Tensor, f2: torch.Tensor):
+        for n, v in (("e1", e1), ("pivots", pivots), ("f2", f2)):
+            _check_vec(v, self.shape, self.device, n)
+        st = lib().ntd_load_factors(self._h, _dptr(e1), _dptr(pivots), _dptr(f2),
+                                    _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_load_factors")
+
+    @property
+    def footprint_bytes(self) -> int:
+        return int(lib().ntd_footprint_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ntd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

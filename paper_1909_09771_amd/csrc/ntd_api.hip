@@ -1,0 +1,322 @@
+// ntd_api.hip -- host side of the C ABI declared in include/ntd.h: argument
+// validation, the layout of the caller's workspace, kernel launches and the
+// PCG driver loop.  Nothing here allocates device memory: every device array
+// lives in the workspace the caller passes to ntd_setup.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "ntd.h"
+#include "ntd_internal.h"
+
+using ntd::Scalars;
+
+struct ntd_handle {
+    int nx, ny, nz, prec, schur, epl;
+    long long N, nxy;
+    size_t used;
+    double *d, *ax, *ay, *az;                 // bands of A
+    double *e1, *mv, *f2, *dT, *dP, *xP;      // factors (FP64) and setup state
+    double *r, *z, *p, *q;                    // PCG vectors
+    float *e1f, *mvf, *f2f, *g3f, *Zf;        // MIXED: float copies and the sweep intermediate
+    void *scratch;                            // plane-sized scratch
+    double *partials;
+    Scalars *sc;
+    int *flag;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// Walks the workspace: identical for sizing (base == nullptr) and carving.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    template <typename T>
+    T *take(size_t count) {
+        size_t o = off;
+        off = align_up(off + count * sizeof(T));
+        return base ? (T *)(base + o) : nullptr;
+    }
+};
+
+bool grid_ok(int nx, int ny, int nz) {
+    if (nx < 1 || ny < 1 || nz < 1) return false;
+    if (nx > NTD_MAX_NX || ntd::epl_for(nx) == 0) return false;
+    long long N = (long long)nx * ny * nz;
+    return N <= 0x7fffffffLL;
+}
+
+size_t layout(ntd_handle *h, void *ws, int nx, int ny, int nz, int prec) {
+    const long long N = (long long)nx * ny * nz, nxy = (long long)nx * ny;
+    Carver c(ws);
+    double **f64[] = {&h->d, &h->ax, &h->ay, &h->az, &h->e1, &h->mv, &h->f2,
+                      &h->dT, &h->dP, &h->xP, &h->r, &h->z, &h->p, &h->q};
+    for (double **a : f64) *a = c.take<double>(N);
+    h->e1f = h->mvf = h->f2f = h->g3f = h->Zf = nullptr;
+    if (prec == NTD_PREC_MIXED) {
+        float **f32[] = {&h->e1f, &h->mvf, &h->f2f, &h->g3f, &h->Zf};
+        for (float **a : f32) *a = c.take<float>(N);
+    }
+    h->scratch = c.take<double>(6 * nxy);
+    h->partials = c.take<double>(ntd::kMaxBlocks + ntd::kApplySlots);
+    h->sc = c.take<Scalars>(1);
+    h->flag = c.take<int>(4);
+    return c.off;
+}
+
+#define CK(expr)                                 \
+    do {                                         \
+        if ((expr) != hipSuccess) return NTD_EHIP; \
+    } while (0)
+
+inline hipStream_t S(void *s) { return (hipStream_t)s; }
+
+ntd::Grid grid_of(const ntd_handle *h) {
+    ntd::Grid g;
+    g.nx = h->nx; g.ny = h->ny; g.nz = h->nz; g.nxy = h->nxy; g.N = h->N;
+    return g;
+}
+
+// z = B^{-1} r; partials (if not null) receive the 6 per-wave partials of r.z.
+int apply_internal(ntd_handle *h, const double *r, double *z, double *partials, hipStream_t s) {
+    if (h->prec == NTD_PREC_FP64) {
+        ntd::ApplyArgs<double> a;
+        a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
+        a.e1 = h->e1; a.mv = h->mv; a.f2 = h->f2; a.g3 = h->az; a.mv64 = h->mv;
+        a.r = r; a.Z = z; a.zout = z; a.scratch = (double *)h->scratch; a.partials = partials;
+        CK(ntd::launch_apply_f64(a, h->epl, s));
+    } else {
+        ntd::ApplyArgs<float> a;
+        a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
+        a.e1 = h->e1f; a.mv = h->mvf; a.f2 = h->f2f; a.g3 = h->g3f; a.mv64 = h->mv;
+        a.r = r; a.Z = h->Zf; a.zout = z; a.scratch = (float *)h->scratch; a.partials = partials;
+        CK(ntd::launch_apply_f32(a, h->epl, s));
+    }
+    return NTD_OK;
+}
+
+int cast_factors(ntd_handle *h, hipStream_t s) {
+    if (h->prec != NTD_PREC_MIXED) return NTD_OK;
+    CK(ntd::launch_cast_f32(h->e1f, h->e1, h->N, s));
+    CK(ntd::launch_cast_f32(h->mvf, h->mv, h->N, s));
+    CK(ntd::launch_cast_f32(h->f2f, h->f2, h->N, s));
+    CK(ntd::launch_cast_f32(h->g3f, h->az, h->N, s));
+    return NTD_OK;
+}
+
+int read_scalars(const ntd_handle *h, Scalars *out, hipStream_t s) {
+    CK(hipMemcpyAsync(out, h->sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    return NTD_OK;
+}
+
+// ||v||^2 into sc->result and onto the host.
+int norm2(ntd_handle *h, const double *v, double *out, hipStream_t s) {
+    int np = 0;
+    CK(ntd::launch_dot(v, v, h->N, h->partials, &np, s));
+    CK(ntd::launch_finalize(h->partials, np, h->sc, ntd::kOpResult, s));
+    Scalars hs;
+    int st = read_scalars(h, &hs, s);
+    if (st != NTD_OK) return st;
+    *out = hs.result;
+    return NTD_OK;
+}
+
+// True relative residual ||b - A x|| / bn, using q as scratch.
+int true_relres(ntd_handle *h, const double *b, const double *x, double bn, double *out,
+                hipStream_t s) {
+    ntd::Grid g = grid_of(h);
+    CK(ntd::launch_spmv(g, h->d, h->ax, h->ay, h->az, x, h->q, nullptr, nullptr, s));
+    CK(ntd::launch_residual(h->q, b, h->q, h->N, s));
+    double rr = 0.0;
+    int st = norm2(h, h->q, &rr, s);
+    if (st != NTD_OK) return st;
+    *out = sqrt(rr) / bn;
+    return NTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ntd_workspace_bytes(int nx, int ny, int nz, int prec) {
+    if (!grid_ok(nx, ny, nz) || (prec != NTD_PREC_FP64 && prec != NTD_PREC_MIXED)) return 0;
+    ntd_handle tmp;
+    return layout(&tmp, nullptr, nx, ny, nz, prec);
+}
+
+int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const double *t,
+              int prec, int schur, void *workspace, size_t workspace_bytes, void *stream,
+              ntd_handle **out) {
+    if (out) *out = nullptr;
+    if (!out || !kappa || !bc || !workspace) return NTD_EINVAL;
+    if (!grid_ok(nx, ny, nz)) return NTD_EINVAL;
+    if (prec != NTD_PREC_FP64 && prec != NTD_PREC_MIXED) return NTD_EINVAL;
+    if (schur != NTD_SCHUR_NEWTON && schur != NTD_SCHUR_DIAG) return NTD_EINVAL;
+    int ndir = 0;
+    for (int f = 0; f < 6; ++f) {
+        if (bc[f] != NTD_BC_DIRICHLET && bc[f] != NTD_BC_NEUMANN) return NTD_EINVAL;
+        ndir += bc[f] == NTD_BC_DIRICHLET;
+    }
+    if (ndir == 0) return NTD_EINVAL;  // pure Neumann: A is singular
+    if (((uintptr_t)workspace) % kAlign) return NTD_EINVAL;
+    if (workspace_bytes < ntd_workspace_bytes(nx, ny, nz, prec)) return NTD_EINVAL;
+
+    ntd_handle *h = (ntd_handle *)calloc(1, sizeof(ntd_handle));
+    if (!h) return NTD_ENOMEM;
+    h->nx = nx; h->ny = ny; h->nz = nz; h->prec = prec; h->schur = schur;
+    h->epl = ntd::epl_for(nx);
+    h->N = (long long)nx * ny * nz;
+    h->nxy = (long long)nx * ny;
+    h->used = layout(h, workspace, nx, ny, nz, prec);
+    hipStream_t s = S(stream);
+    int st = NTD_OK;
+    int hflag = 0;
+    ntd::Grid g = grid_of(h);
+    ntd::SetupArgs a;
+#define FAIL(code) do { st = (code); goto fail; } while (0)
+#define HK(expr) do { if ((expr) != hipSuccess) FAIL(NTD_EHIP); } while (0)
+    HK(hipMemsetAsync(h->flag, 0, 4 * sizeof(int), s));
+    HK(hipMemsetAsync(h->sc, 0, sizeof(Scalars), s));
+    HK(ntd::launch_check_positive(kappa, t, h->N, h->flag, s));
+    HK(hipMemcpyAsync(&hflag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HK(hipStreamSynchronize(s));
+    if (hflag & ntd::kFlagBadInput) FAIL(NTD_EINVAL);
+    HK(ntd::launch_assemble(g, kappa, bc, h->d, h->ax, h->ay, h->az, s));
+    a.nx = nx; a.ny = ny; a.nz = nz; a.schur = schur;
+    a.d = h->d; a.ax = h->ax; a.ay = h->ay; a.az = h->az; a.t = t;
+    a.dP = h->dP; a.xP = h->xP; a.f2 = h->f2; a.dT = h->dT; a.e1 = h->e1; a.mv = h->mv;
+    a.scratch = (double *)h->scratch; a.flag = h->flag;
+    HK(ntd::launch_setup(a, h->epl, s));
+    HK(hipMemcpyAsync(&hflag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HK(hipStreamSynchronize(s));
+    if (hflag & ntd::kFlagNotSPD) FAIL(NTD_ENOTSPD);
+    if ((st = cast_factors(h, s)) != NTD_OK) goto fail;
+    HK(hipStreamSynchronize(s));
+    *out = h;
+    return NTD_OK;
+fail:
+    free(h);
+    return st;
+#undef FAIL
+#undef HK
+}
+
+int ntd_apply_precond(ntd_handle *h, const double *r, double *z, void *stream) {
+    if (!h || !r || !z || r == z) return NTD_EINVAL;
+    return apply_internal(h, r, z, nullptr, S(stream));
+}
+
+int ntd_spmv(ntd_handle *h, const double *x, double *y, void *stream) {
+    if (!h || !x || !y || x == y) return NTD_EINVAL;
+    ntd::Grid g = grid_of(h);
+    CK(ntd::launch_spmv(g, h->d, h->ax, h->ay, h->az, x, y, nullptr, nullptr, S(stream)));
+    return NTD_OK;
+}
+
+int ntd_dot(ntd_handle *h, const double *x, const double *y, double *result, void *stream) {
+    if (!h || !x || !y || !result) return NTD_EINVAL;
+    hipStream_t s = S(stream);
+    int np = 0;
+    CK(ntd::launch_dot(x, y, h->N, h->partials, &np, s));
+    CK(ntd::launch_finalize(h->partials, np, h->sc, ntd::kOpResult, s));
+    Scalars hs;
+    int st = read_scalars(h, &hs, s);
+    if (st != NTD_OK) return st;
+    *result = hs.result;
+    return NTD_OK;
+}
+
+int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int maxit, int *iters,
+                  double *relres, void *stream) {
+    if (!h || !b || !x || b == x || !iters || !relres) return NTD_EINVAL;
+    if (!(tol > 0.0) || maxit < 1) return NTD_EINVAL;
+    hipStream_t s = S(stream);
+    const long long N = h->N;
+    ntd::Grid g = grid_of(h);
+    *iters = 0;
+    *relres = 0.0;
+    int st;
+    double bb = 0.0;
+    CK(hipMemsetAsync(h->sc, 0, sizeof(Scalars), s));
+    if ((st = norm2(h, b, &bb, s)) != NTD_OK) return st;
+    const double bn = sqrt(bb);
+    CK(ntd::launch_fill(x, 0.0, N, s));
+    CK(ntd::launch_copy(h->r, b, N, s));
+    if (bn == 0.0) {
+        CK(hipStreamSynchronize(s));
+        return NTD_OK;
+    }
+    if ((st = apply_internal(h, h->r, h->z, h->partials, s)) != NTD_OK) return st;
+    CK(ntd::launch_finalize(h->partials, 6, h->sc, ntd::kOpRhoInit, s));
+    CK(ntd::launch_copy(h->p, h->z, N, s));
+    int it = 0, status = NTD_OK, np = 0;
+    Scalars hs;
+    for (;;) {
+        if (it >= maxit) { status = NTD_ENOCONV; break; }
+        CK(ntd::launch_spmv(g, h->d, h->ax, h->ay, h->az, h->p, h->q, h->partials, &np, s));
+        CK(ntd::launch_finalize(h->partials, np, h->sc, ntd::kOpAlpha, s));
+        CK(ntd::launch_axpy2_norm(x, h->r, h->p, h->q, h->sc, N, h->partials, &np, s));
+        CK(ntd::launch_finalize(h->partials, np, h->sc, ntd::kOpRR, s));
+        if ((st = read_scalars(h, &hs, s)) != NTD_OK) return st;
+        if (hs.flag & 1) { status = NTD_EBREAKDOWN; break; }
+        ++it;
+        if (sqrt(hs.rr) / bn <= tol) {
+            double tr = 0.0;
+            if ((st = true_relres(h, b, x, bn, &tr, s)) != NTD_OK) return st;
+            if (tr <= tol) break;
+        }
+        if ((st = apply_internal(h, h->r, h->z, h->partials, s)) != NTD_OK) return st;
+        CK(ntd::launch_finalize(h->partials, 6, h->sc, ntd::kOpBeta, s));
+        CK(ntd::launch_xpay(h->p, h->z, h->sc, N, s));
+    }
+    *iters = it;
+    if ((st = true_relres(h, b, x, bn, relres, s)) != NTD_OK) return st;
+    return status;
+}
+
+int ntd_export(const ntd_handle *h, int which, double *dst, void *stream) {
+    if (!h || !dst) return NTD_EINVAL;
+    const double *src[] = {h->d, h->ax, h->ay, h->az, h->e1, h->mv, h->f2, h->dT, h->dP, h->xP};
+    if (which < 0 || which >= (int)(sizeof(src) / sizeof(src[0]))) return NTD_EINVAL;
+    CK(hipMemcpyAsync(dst, src[which], sizeof(double) * h->N, hipMemcpyDeviceToDevice,
+                      S(stream)));
+    return NTD_OK;
+}
+
+int ntd_load_factors(ntd_handle *h, const double *e1, const double *pivots, const double *f2,
+                     void *stream) {
+    if (!h || !e1 || !pivots || !f2) return NTD_EINVAL;
+    hipStream_t s = S(stream);
+    CK(ntd::launch_copy(h->e1, e1, h->N, s));
+    CK(ntd::launch_recip(h->mv, pivots, h->N, s));
+    CK(ntd::launch_copy(h->f2, f2, h->N, s));
+    return cast_factors(h, s);
+}
+
+size_t ntd_footprint_bytes(const ntd_handle *h) { return h ? h->used : 0; }
+
+int ntd_destroy(ntd_handle *h) {
+    free(h);
+    return NTD_OK;
+}
+
+const char *ntd_strerror(int status) {
+    switch (status) {
+    case NTD_OK: return "ok";
+    case NTD_EINVAL: return "invalid argument";
+    case NTD_ENOMEM: return "host allocation failed";
+    case NTD_ENOTSPD: return "factorization pivot not positive";
+    case NTD_EBREAKDOWN: return "PCG breakdown (p'Ap <= 0)";
+    case NTD_ENOCONV: return "PCG did not converge within maxit";
+    case NTD_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,15 @@
+// ntd_apply_f64.hip -- instantiation of the preconditioner apply in double.
+#include "ntd_sweep.h"
+
+namespace ntd {
+
+hipError_t launch_apply_f64(const ApplyArgs<double> &a, int epl, hipStream_t s) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return apply_impl<double, E>(a, s);
+        NTD_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ntd
