@@ -60,7 +60,8 @@ typedef struct ntd_handle ntd_handle;
 #define NTD_SCHUR_NEWTON 0
 #define NTD_SCHUR_DIAG 1
 
-/* Largest supported line length nx (one wavefront solves one line). */
+/* Largest supported line length nx (one wavefront solves one line).  The
+ * grid must also satisfy 8*nx*ny*nz < 2^31 (32-bit byte offsets). */
 #define NTD_MAX_NX 1024
 
 /* Bytes of device workspace that ntd_setup needs for this grid and precision.
@@ -89,6 +90,12 @@ int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const 
  * the exact twisted tridiagonal solve).  r and z are [N] device FP64 and must
  * not overlap.  Stream-ordered, asynchronous. */
 int ntd_apply_precond(ntd_handle *h, const double *r, double *z, void *stream);
+
+/* Same as ntd_apply_precond, synchronous, and ms[0..2] (HOST) receive the
+ * durations in milliseconds of its three launches (lower level-3 sweep of the
+ * two half chains, twist plane, upper level-3 sweep), measured with HIP events
+ * on `stream`.  For benchmarking. */
+int ntd_apply_profile(ntd_handle *h, const double *r, double *z, float *ms, void *stream);
 
 /* y = A x with the assembled 7-point bands.  [N] device FP64, no overlap.
  * Stream-ordered, asynchronous. */

@@ -50,6 +50,8 @@ def lib() -> ctypes.CDLL:
         L.ntd_setup.restype = I
         L.ntd_apply_precond.argtypes = [P, P, P, P]
         L.ntd_apply_precond.restype = I
+        L.ntd_apply_profile.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_float), P]
+        L.ntd_apply_profile.restype = I
         L.ntd_spmv.argtypes = [P, P, P, P]
         L.ntd_spmv.restype = I
         L.ntd_dot.argtypes = [P, P, P, ctypes.POINTER(D), P]
@@ -138,6 +140,17 @@ class Solver:
         if st != OK:
             raise NTDError(st, "ntd_apply_precond")
         return z
+
+    def apply_profile(self, r: torch.Tensor, out: torch.Tensor):
+        """z = B^{-1} r (synchronous); returns the durations in ms of the three
+        launches (lower level-3 sweep, twist plane, upper level-3 sweep)."""
+        _check_vec(r, self.shape, self.device, "r")
+        _check_vec(out, self.shape, self.device, "out")
+        ms = (ctypes.c_float * 3)()
+        st = lib().ntd_apply_profile(self._h, _dptr(r), _dptr(out), ms, _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_apply_profile")
+        return float(ms[0]), float(ms[1]), float(ms[2])
 
     def spmv(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         _check_vec(x, self.shape, self.device, "x")

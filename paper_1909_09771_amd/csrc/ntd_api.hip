@@ -47,8 +47,9 @@ struct Carver {
 bool grid_ok(int nx, int ny, int nz) {
     if (nx < 1 || ny < 1 || nz < 1) return false;
     if (nx > NTD_MAX_NX || ntd::epl_for(nx) == 0) return false;
+    // the sweeps address FP64 arrays with 32-bit byte offsets
     long long N = (long long)nx * ny * nz;
-    return N <= 0x7fffffffLL;
+    return N * 8 < 0x7fffffffLL;
 }
 
 size_t layout(ntd_handle *h, void *ws, int nx, int ny, int nz, int prec) {
@@ -82,20 +83,22 @@ ntd::Grid grid_of(const ntd_handle *h) {
     return g;
 }
 
-// z = B^{-1} r; partials (if not null) receive the 6 per-wave partials of r.z.
-int apply_internal(ntd_handle *h, const double *r, double *z, double *partials, hipStream_t s) {
+// z = B^{-1} r; partials (if not null) receive the 6 per-wave partials of r.z;
+// ev (if not null, 4 events) brackets the three launches.
+int apply_internal(ntd_handle *h, const double *r, double *z, double *partials, hipStream_t s,
+                   hipEvent_t *ev = nullptr) {
     if (h->prec == NTD_PREC_FP64) {
         ntd::ApplyArgs<double> a;
         a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
         a.e1 = h->e1; a.mv = h->mv; a.f2 = h->f2; a.g3 = h->az; a.mv64 = h->mv;
         a.r = r; a.Z = z; a.zout = z; a.scratch = (double *)h->scratch; a.partials = partials;
-        CK(ntd::launch_apply_f64(a, h->epl, s));
+        CK(ntd::launch_apply_f64(a, h->epl, s, ev));
     } else {
         ntd::ApplyArgs<float> a;
         a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
         a.e1 = h->e1f; a.mv = h->mvf; a.f2 = h->f2f; a.g3 = h->g3f; a.mv64 = h->mv;
         a.r = r; a.Z = h->Zf; a.zout = z; a.scratch = (float *)h->scratch; a.partials = partials;
-        CK(ntd::launch_apply_f32(a, h->epl, s));
+        CK(ntd::launch_apply_f32(a, h->epl, s, ev));
     }
     return NTD_OK;
 }
@@ -210,6 +213,21 @@ fail:
 int ntd_apply_precond(ntd_handle *h, const double *r, double *z, void *stream) {
     if (!h || !r || !z || r == z) return NTD_EINVAL;
     return apply_internal(h, r, z, nullptr, S(stream));
+}
+
+int ntd_apply_profile(ntd_handle *h, const double *r, double *z, float *ms, void *stream) {
+    if (!h || !r || !z || r == z || !ms) return NTD_EINVAL;
+    hipStream_t s = S(stream);
+    hipEvent_t ev[4];
+    int made = 0, st = NTD_OK;
+    for (; made < 4; ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess) { st = NTD_EHIP; break; }
+    if (st == NTD_OK) st = apply_internal(h, r, z, nullptr, s, ev);
+    if (st == NTD_OK && hipEventSynchronize(ev[3]) != hipSuccess) st = NTD_EHIP;
+    for (int i = 0; st == NTD_OK && i < 3; ++i)
+        if (hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]) != hipSuccess) st = NTD_EHIP;
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    return st;
 }
 
 int ntd_spmv(ntd_handle *h, const double *x, double *y, void *stream) {

@@ -3,9 +3,9 @@
 
 namespace ntd {
 
-hipError_t launch_apply_f64(const ApplyArgs<double> &a, int epl, hipStream_t s) {
+hipError_t launch_apply_f64(const ApplyArgs<double> &a, int epl, hipStream_t s, hipEvent_t *ev) {
     switch (epl) {
-#define NTD_CASE(E) case E: return apply_impl<double, E>(a, s);
+#define NTD_CASE(E) case E: return apply_impl<double, E>(a, s, ev);
         NTD_EPL_LIST(NTD_CASE)
 #undef NTD_CASE
     default: return hipErrorInvalidValue;

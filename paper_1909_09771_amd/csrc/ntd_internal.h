@@ -69,8 +69,8 @@ struct SetupArgs {
 
 // Host-side launchers (defined in the .hip files).
 int epl_for(int nx);  // elements per lane of a half-wave chain, 0 if unsupported
-hipError_t launch_apply_f64(const ApplyArgs<double> &a, int epl, hipStream_t s);
-hipError_t launch_apply_f32(const ApplyArgs<float> &a, int epl, hipStream_t s);
+hipError_t launch_apply_f64(const ApplyArgs<double> &a, int epl, hipStream_t s, hipEvent_t *ev);
+hipError_t launch_apply_f32(const ApplyArgs<float> &a, int epl, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_setup(const SetupArgs &a, int epl, hipStream_t s);
 
 hipError_t launch_check_positive(const double *kappa, const double *t, long long N, int *flag,

@@ -13,10 +13,17 @@
 //     the chain from element nx-1 down to j+1, EPL consecutive chain positions
 //     per lane.  Each of the two recurrences of the twisted tridiagonal solve
 //     is an affine map x_c = a_c x_{c-1} + b_c along a chain, evaluated as a
-//     lane-local composition plus a 32-lane inclusive scan of affine maps.
+//     lane-local composition plus a 32-lane scan of affine maps built from DPP
+//     row shifts, a row broadcast and readlane.
 // The level-3 twist plane and the switch from the lower to the upper level-3
 // sweep are kernel boundaries (lower halves, twist plane, upper halves), so no
 // workgroup ever waits for another.
+//
+// Memory access: a chain step is latency-bound, so every input of line m+1 is
+// issued while line m is solved, through raw buffer loads with a uniform
+// per-line byte offset and per-lane 32-bit element offsets.  Slots outside a
+// chain use an offset past the end of every buffer: their loads return 0 and
+// their stores are dropped, so no load or store needs a branch.
 #pragma once
 
 #include "ntd_internal.h"
@@ -29,9 +36,44 @@ constexpr int kApplyThreads = 128;  // two wavefronts: the two level-2 half chai
 constexpr int kSetupThreads = 256;  // two chain wavefronts + two helpers for plane-wide work
 
 // ---------------------------------------------------------------------------
+// Buffer I/O.
+// ---------------------------------------------------------------------------
+
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
+
+constexpr unsigned kOOB = 0x80000000u;  // beyond every buffer: load -> 0, store dropped
+
+// Raw buffer over [p, p + 2 GiB); gfx9 resource word 3.
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, 0x7fffffff,
+                                             0x00020000);
+}
+
+__device__ __forceinline__ float bload(float *, rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ double bload(double *, rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(double,
+                              __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ void bstore(float v, rsrc_t r, unsigned vo, unsigned so) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ void bstore(double v, rsrc_t r, unsigned vo, unsigned so) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)vo, (int)so, 0);
+}
+
+// ---------------------------------------------------------------------------
 // Level 1: one line per wavefront.
 // ---------------------------------------------------------------------------
 
+// Lane layout of one line: lanes 0-31 hold chain A (elements 0..j, j = ca-1 the
+// twist element), lanes 32-63 chain B (elements n-1 down to j+1), EPL
+// consecutive chain positions per lane.  Both chains are right-aligned in their
+// half so that the twist element always sits in lane 31, slot EPL-1, and the
+// end of chain B (element j+1) in lane 63, slot EPL-1; the unused positions are
+// at the start of each half.
 struct LineGeom {
     int n;     // line length (nx)
     int ca;    // chain A length: elements 0..j (j = ca - 1 is the twist element)
@@ -39,36 +81,68 @@ struct LineGeom {
     int half;  // 0: this lane holds chain A, 1: chain B
     int hl;    // lane index inside the half, 0..31
     int cnt;   // length of this lane's chain
-    __device__ explicit LineGeom(int n_) : n(n_) {
+    int skip;  // unused positions at the start of this half
+    __device__ LineGeom(int n_, int epl) : n(n_) {
         ca = (n_ + 1) / 2;
         cb = n_ - ca;
         int lane = threadIdx.x & 63;
         half = lane >> 5;
         hl = lane & 31;
         cnt = half ? cb : ca;
+        skip = 32 * epl - cnt;
     }
-    __device__ __forceinline__ int pos(int s, int epl) const { return hl * epl + s; }
-    __device__ __forceinline__ bool ok(int c) const { return c < cnt; }
+    // chain position of slot s (negative: unused slot)
+    __device__ __forceinline__ int pos(int s, int epl) const { return hl * epl + s - skip; }
+    __device__ __forceinline__ bool ok(int c) const { return c >= 0; }
     __device__ __forceinline__ int elem(int c) const { return half ? n - 1 - c : c; }
 };
 
-template <typename T, int EPL>
-__device__ __forceinline__ T pick(const T (&v)[EPL], int s) {
-    T r = v[0];
+// Per-lane byte offsets, inside a line, of the element of each slot (o4 for
+// 4-byte, o8 for 8-byte arrays) and of its left neighbour e-1 (p4, p8); kOOB
+// where the slot is outside the chain or the neighbour does not exist.
+template <int EPL>
+struct Slots {
+    unsigned o4[EPL], o8[EPL], p4[EPL], p8[EPL];
+    __device__ explicit Slots(const LineGeom &G) {
 #pragma unroll
-    for (int q = 1; q < EPL; ++q)
-        if (q == s) r = v[q];
-    return r;
+        for (int s = 0; s < EPL; ++s) {
+            const int c = G.pos(s, EPL);
+            const bool ok = G.ok(c);
+            const int e = G.elem(c);
+            o4[s] = ok ? 4u * e : kOOB;
+            o8[s] = ok ? 8u * e : kOOB;
+            p4[s] = (ok && e > 0) ? 4u * (e - 1) : kOOB;
+            p8[s] = (ok && e > 0) ? 8u * (e - 1) : kOOB;
+        }
+    }
+    __device__ __forceinline__ bool valid(int s) const { return o4[s] != kOOB; }
+    __device__ __forceinline__ unsigned off(float *, int s) const { return o4[s]; }
+    __device__ __forceinline__ unsigned off(double *, int s) const { return o8[s]; }
+    __device__ __forceinline__ unsigned offm1(float *, int s) const { return p4[s]; }
+    __device__ __forceinline__ unsigned offm1(double *, int s) const { return p8[s]; }
+};
+
+template <typename T, int EPL>
+__device__ __forceinline__ void bload_line(const Slots<EPL> &S, rsrc_t r, unsigned so,
+                                           T (&v)[EPL]) {
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) v[s] = bload((T *)nullptr, r, S.off((T *)nullptr, s), so);
 }
 
 template <typename T, int EPL>
-__device__ __forceinline__ void put(T (&v)[EPL], int s, T x) {
+__device__ __forceinline__ void bstore_line(const Slots<EPL> &S, rsrc_t r, unsigned so,
+                                            const T (&v)[EPL]) {
 #pragma unroll
-    for (int q = 0; q < EPL; ++q)
-        if (q == s) v[q] = x;
+    for (int s = 0; s < EPL; ++s) bstore(v[s], r, S.off((T *)nullptr, s), so);
 }
 
-// Load v[s] = src[element of slot s] (0 outside the chain).
+template <typename T, int EPL>
+__device__ __forceinline__ void zero_line(T (&v)[EPL]) {
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) v[s] = T(0);
+}
+
+// Pointer-based line access (setup only).
 template <typename T, int EPL>
 __device__ __forceinline__ void load_line(const LineGeom &G, const T *__restrict__ src,
                                           T (&v)[EPL]) {
@@ -89,87 +163,154 @@ __device__ __forceinline__ void store_line(const LineGeom &G, T *__restrict__ ds
     }
 }
 
-// Coefficients of the line solve T^{-1} y with T = (M + L1)(I + M^{-1} U1):
-// mv = 1/M at the slot's element, cp = coupling to the chain predecessor
-// (chain A: e1[e-1]; chain B: e1[e]), cn = coupling toward the twist
-// (chain A: e1[e]; chain B: e1[e-1]); mvj = FP64 1/M of the twist element.
+// ---------------------------------------------------------------------------
+// Cross-lane primitives: DPP moves inside the 16-lane rows, row broadcast and
+// readlane across rows.  `old` is what a lane keeps when its source lane does
+// not exist (the identity of the operation being scanned).
+// ---------------------------------------------------------------------------
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp(float old, float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                 __builtin_bit_cast(int, src), CTRL,
+                                                                 ROW_MASK, 0xF, false));
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp(double old, double src) {
+    const unsigned long long o = __builtin_bit_cast(unsigned long long, old);
+    const unsigned long long s = __builtin_bit_cast(unsigned long long, src);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)s,
+                                                              CTRL, ROW_MASK, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32),
+                                                              (int)(unsigned)(s >> 32), CTRL,
+                                                              ROW_MASK, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ float rdlane(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+__device__ __forceinline__ double rdlane(double v, int lane) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// DPP controls (GFX9 encoding).
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0x108;
+constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138, kRowBcast15 = 0x142;
+
+// Inclusive scan of affine maps x -> A x + B over the 32 lanes of each half,
+// forward (lane hl composes lanes 0..hl).  Four in-row steps, then row 1
+// (row 3) takes the composite of row 0 (row 2) through lane 15 (47).
+template <typename T>
+__device__ __forceinline__ void scan_fwd32(T &A, T &B) {
+#define NTD_FWD_STEP(CTRL, RM)                                            \
+    {                                                                     \
+        const T Ap = dpp<CTRL, RM>(T(1), A), Bp = dpp<CTRL, RM>(T(0), B); \
+        B = A * Bp + B;                                                   \
+        A = A * Ap;                                                       \
+    }
+    NTD_FWD_STEP(kRowShr1, 0xF)
+    NTD_FWD_STEP(kRowShr2, 0xF)
+    NTD_FWD_STEP(kRowShr4, 0xF)
+    NTD_FWD_STEP(kRowShr8, 0xF)
+    {
+        const T Bp = dpp<kRowBcast15, 0xA>(T(0), B);
+        B = A * Bp + B;
+    }
+#undef NTD_FWD_STEP
+}
+
+// Same, backward (lane hl composes lanes hl..31): four in-row steps, then rows
+// 0 and 2 take the composite of rows 1 and 3 read from lanes 16 and 48.
+template <typename T>
+__device__ __forceinline__ void scan_bwd32(T &U, T &G, int lane) {
+#define NTD_BWD_STEP(CTRL)                                        \
+    {                                                             \
+        const T Un = dpp<CTRL>(T(1), U), Gn = dpp<CTRL>(T(0), G); \
+        G = U * Gn + G;                                           \
+        U = U * Un;                                               \
+    }
+    NTD_BWD_STEP(kRowShl1)
+    NTD_BWD_STEP(kRowShl2)
+    NTD_BWD_STEP(kRowShl4)
+    NTD_BWD_STEP(kRowShl8)
+#undef NTD_BWD_STEP
+    const T g16 = rdlane(G, 16), g48 = rdlane(G, 48);
+    const T gn = lane < 32 ? g16 : g48;
+    if (((lane >> 4) & 1) == 0) G = U * gn + G;
+}
+
+// Everything one line step reads from memory, loaded one step ahead: 1/M and
+// the x-band e1 at the slot's element (e0) and its left neighbour (em1), the
+// FP64 1/M of the twist row, the y-coupling f to the neighbour line, the
+// lower-sweep result w (upper sweeps), and raw inputs a*, d0 of the caller's
+// right-hand side and output (combined only when used, so that the loads stay
+// in flight).
 template <typename T, int EPL>
-struct LineCoef {
-    T mv[EPL], cp[EPL], cn[EPL];
+struct LineIn {
+    T mv[EPL], e0[EPL], em1[EPL];
+    T f[EPL], w[EPL];
+    T a0[EPL], a1[EPL], a2[EPL], a3[EPL];
+    double d0[EPL];
     double mvj;
 };
 
+// Factor buffers of the plane being solved: so* are byte offsets of the plane.
+template <typename T>
+struct PlaneFac {
+    rsrc_t e1, mv, f2, W;
+    const double *mv64;  // FP64 1/M, pointer to the plane's first element
+    unsigned soT;        // byte offset of the plane in e1/mv/f2
+    unsigned soW;        // byte offset of the plane in W
+};
+
 template <typename T, int EPL>
-__device__ __forceinline__ void load_coef(const LineGeom &G, const T *__restrict__ e1,
-                                          const T *__restrict__ mv,
-                                          const double *__restrict__ mv64,
-                                          LineCoef<T, EPL> &C) {
+__device__ __forceinline__ void load_coef(const Slots<EPL> &S, const LineGeom &G,
+                                          const PlaneFac<T> &F, int m, LineIn<T, EPL> &C) {
+    const unsigned so = F.soT + (unsigned)(m * G.n) * (unsigned)sizeof(T);
 #pragma unroll
     for (int s = 0; s < EPL; ++s) {
-        int c = G.pos(s, EPL);
-        bool ok = G.ok(c);
-        int e = G.elem(c);
-        C.mv[s] = ok ? mv[e] : T(0);
-        if (G.half == 0) {
-            C.cp[s] = (ok && e > 0) ? e1[e - 1] : T(0);
-            C.cn[s] = ok ? e1[e] : T(0);
-        } else {
-            C.cp[s] = ok ? e1[e] : T(0);
-            C.cn[s] = ok ? e1[e - 1] : T(0);
-        }
+        C.mv[s] = bload((T *)nullptr, F.mv, S.off((T *)nullptr, s), so);
+        C.e0[s] = bload((T *)nullptr, F.e1, S.off((T *)nullptr, s), so);
+        C.em1[s] = bload((T *)nullptr, F.e1, S.offm1((T *)nullptr, s), so);
     }
-    C.mvj = mv64[G.ca - 1];
-}
-
-// Inclusive scan of affine maps over the 32 lanes of each half, forward
-// (lane hl composes lanes 0..hl): x -> A x + B.
-template <typename T>
-__device__ __forceinline__ void scan_fwd32(T &A, T &B, int hl) {
-#pragma unroll
-    for (int off = 1; off < 32; off <<= 1) {
-        T Ap = __shfl_up(A, off, 32);
-        T Bp = __shfl_up(B, off, 32);
-        if (hl >= off) {
-            B = A * Bp + B;
-            A = A * Ap;
-        }
-    }
-}
-
-// Same, backward (lane hl composes lanes hl..31).
-template <typename T>
-__device__ __forceinline__ void scan_bwd32(T &U, T &G, int hl) {
-#pragma unroll
-    for (int off = 1; off < 32; off <<= 1) {
-        T Un = __shfl_down(U, off, 32);
-        T Gn = __shfl_down(G, off, 32);
-        if (hl + off < 32) {
-            G = U * Gn + G;
-            U = U * Un;
-        }
-    }
+    C.mvj = F.mv64[(long long)m * G.n + G.ca - 1];
 }
 
 // x = T^{-1} y for one line held by the calling wavefront (all 64 lanes).
 // Lower sweep: g_c = a_c g_{c-1} + b_c along each chain toward the twist with
-// a_c = -cp/M, b_c = y/M; the twist row takes both neighbours, in FP64.
-// Upper sweep: x_c = u_c x_{c+1} + g_c from the twist outward, u_c = -cn/M,
-// the top of chain B being seeded with the twist value.
+// a_c = -cp/M, b_c = y/M (cp = coupling to the chain predecessor); the twist
+// row takes both neighbours, in FP64.  Upper sweep: x_c = u_c x_{c+1} + g_c
+// from the twist outward, u_c = -cn/M (cn = coupling toward the twist), the
+// top of chain B being seeded with the twist value.
 template <typename T, int EPL>
-__device__ __forceinline__ void line_solve(const LineGeom &G, const LineCoef<T, EPL> &C,
-                                           const T (&y)[EPL], T (&x)[EPL]) {
-    T a[EPL], g[EPL], gm1[EPL];
+__device__ __forceinline__ void line_solve(const LineGeom &G, const Slots<EPL> &S,
+                                           const LineIn<T, EPL> &C, const T (&y)[EPL],
+                                           T (&x)[EPL]) {
+    const int lane = threadIdx.x & 63;
+    T a[EPL], g[EPL], gm1[EPL], cp[EPL], cn[EPL];
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) {
+        cp[s] = G.half ? C.e0[s] : C.em1[s];
+        cn[s] = G.half ? C.em1[s] : C.e0[s];
+    }
     T A = T(1), B = T(0);
 #pragma unroll
     for (int s = 0; s < EPL; ++s) {
-        bool ok = G.ok(G.pos(s, EPL));
-        a[s] = ok ? -C.mv[s] * C.cp[s] : T(1);
-        g[s] = ok ? C.mv[s] * y[s] : T(0);
+        const bool ok = S.valid(s);
+        a[s] = ok ? -C.mv[s] * cp[s] : T(1);
+        g[s] = C.mv[s] * y[s];  // 1/M is 0 outside the chain
         B = a[s] * B + g[s];
         A = a[s] * A;
     }
-    scan_fwd32(A, B, G.hl);
-    T carry = __shfl_up(B, 1, 32);
+    scan_fwd32(A, B);
+    T carry = dpp<kWaveShr1>(T(0), B);
     if (G.hl == 0) carry = T(0);
 #pragma unroll
     for (int s = 0; s < EPL; ++s) {
@@ -177,39 +318,22 @@ __device__ __forceinline__ void line_solve(const LineGeom &G, const LineCoef<T, 
         g[s] = a[s] * carry + g[s];
         carry = g[s];
     }
-    // Twist element j: chain A position ca-1, neighbour j+1 = last of chain B.
-    const int cta = G.ca - 1, lt = cta / EPL, st = cta % EPL;
-    T gB = T(0);
-    if (G.cb > 0) {
-        const int ctb = G.cb - 1;
-        T v = pick(g, ctb % EPL);
-        gB = __shfl(v, 32 + ctb / EPL, 64);
-    }
-    double gj = 0.0;
-    if (G.half == 0 && G.hl == lt) {
-        double yj = (double)pick(y, st), gjm1 = (double)pick(gm1, st);
-        double cpj = (double)pick(C.cp, st), cnj = (double)pick(C.cn, st);
-        gj = C.mvj * (yj - cpj * gjm1 - cnj * (double)gB);
-        put(g, st, (T)gj);
-    }
-    gj = __shfl(gj, lt, 64);
+    // Twist element j: lane 31, slot EPL-1; its neighbour j+1 ends chain B in
+    // lane 63, slot EPL-1 (0 there when chain B is empty).  The twist row is
+    // evaluated in FP64 and broadcast.
+    constexpr int L = EPL - 1;
+    const T gB = rdlane(g[L], 63);
+    double gj = C.mvj * ((double)y[L] - (double)cp[L] * (double)gm1[L] - (double)cn[L] * (double)gB);
+    gj = rdlane(gj, 31);
     const T xj = (T)gj;
+    if (lane == 31) g[L] = xj;
     T u[EPL];
 #pragma unroll
-    for (int s = 0; s < EPL; ++s) {
-        bool ok = G.ok(G.pos(s, EPL));
-        u[s] = ok ? -C.mv[s] * C.cn[s] : T(0);
-        if (!ok) g[s] = T(0);
-    }
-    if (G.half == 0) {
-        if (G.hl == lt) put(u, st, T(0));
-    } else if (G.cb > 0) {
-        const int ctb = G.cb - 1;
-        if (G.hl == ctb / EPL) {
-            const int sb = ctb % EPL;
-            put(g, sb, pick(g, sb) + pick(u, sb) * xj);
-            put(u, sb, T(0));
-        }
+    for (int s = 0; s < EPL; ++s) u[s] = -C.mv[s] * cn[s];  // 0 outside the chain
+    if (lane == 31) u[L] = T(0);
+    if (lane == 63) {  // seed chain B with x_j = g_j
+        g[L] = g[L] + u[L] * xj;
+        u[L] = T(0);
     }
     T U = T(1), Gs = T(0);
 #pragma unroll
@@ -217,8 +341,8 @@ __device__ __forceinline__ void line_solve(const LineGeom &G, const LineCoef<T, 
         Gs = u[s] * Gs + g[s];
         U = u[s] * U;
     }
-    scan_bwd32(U, Gs, G.hl);
-    T xn = __shfl_down(Gs, 1, 32);
+    scan_bwd32(U, Gs, lane);
+    T xn = dpp<kWaveShl1>(T(0), Gs);
     if (G.hl == 31) xn = T(0);
 #pragma unroll
     for (int s = EPL - 1; s >= 0; --s) {
@@ -231,115 +355,139 @@ __device__ __forceinline__ void line_solve(const LineGeom &G, const LineCoef<T, 
 // Level 2: one plane per workgroup, two wavefronts (the two half chains).
 // ---------------------------------------------------------------------------
 
-// Solve Pt x = y for the plane whose factors start at e1p/mvp/mv64p/f2p:
+// Solve Pt x = y for the plane described by F:
 //   lower: w_m = T_m^{-1}(y_m - f*w_{m-1}) for m < j2 (wave 0), mirrored for
 //          m > j2 (wave 1), the twist line j2 taking both neighbours;
 //   upper: x_{j2} = w_{j2}; x_m = w_m - T_m^{-1}(f*x_{m+-1}) outward.
-// rhs(m, G, y) fills the right-hand side of line m; W (plane-sized) keeps the
-// lower results; out(m, G, x) receives the final value of line m exactly once.
-// All threads of the block must call it (it holds two block barriers).
-template <typename T, int EPL, class Rhs, class Out>
-__device__ void plane_solve(int nx, int ny, const T *__restrict__ e1p, const T *__restrict__ mvp,
-                            const double *__restrict__ mv64p, const T *__restrict__ f2p,
-                            T *__restrict__ W, Rhs rhs, Out out, T *lds /* [2][64*EPL] */) {
+// The policy `pol` supplies the right-hand side and takes the results:
+//   pol.load_rhs(m, S, in)  issue the loads of line m's right-hand side into in
+//   pol.rhs(in, s)          the right-hand side value of slot s
+//   pol.load_out(m, S, in)  issue the loads the output of line m needs
+//   pol.out(m, S, x, in)    receive the final x of line m (exactly once)
+// F.W (plane-sized) keeps the lower results.  Every input of line m+1 is
+// loaded while line m is solved.  All threads of the block must call it (it
+// holds two block barriers).
+template <typename T, int EPL, class Pol>
+__device__ void plane_solve(int nx, int ny, const PlaneFac<T> &F, Pol &pol,
+                            T *lds /* [2][64*EPL] */) {
     const int wv = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const LineGeom G(nx);
+    const LineGeom G(nx, EPL);
+    const Slots<EPL> S(G);
     const int j2 = (ny - 1) / 2;
-    T y[EPL], w[EPL], prev[EPL], f[EPL];
-    LineCoef<T, EPL> C;
+    const unsigned lineT = (unsigned)nx * (unsigned)sizeof(T);
+    T y[EPL], w[EPL], prev[EPL], fhi[EPL];
+    LineIn<T, EPL> A, B;
+    zero_line(prev);
+
+    // inputs of the lower step of line m, coupled to its chain predecessor
+    // through the f2 line lc (lc < 0: first line of the chain)
+    auto load_lower = [&](int m, int lc, LineIn<T, EPL> &in) {
+        pol.load_rhs(m, S, in);
+        if (lc >= 0) bload_line(S, F.f2, F.soT + (unsigned)lc * lineT, in.f);
+        else zero_line(in.f);
+        load_coef(S, G, F, m, in);
+    };
+    // inputs of the upper step of line m, coupled to its final neighbour toward
+    // the twist through the f2 line lc
+    auto load_upper = [&](int m, int lc, LineIn<T, EPL> &in) {
+        bload_line(S, F.W, F.soW + (unsigned)m * lineT, in.w);
+        bload_line(S, F.f2, F.soT + (unsigned)lc * lineT, in.f);
+        load_coef(S, G, F, m, in);
+        pol.load_out(m, S, in);
+    };
+    auto lower_step = [&](int m, const LineIn<T, EPL> &in) {
 #pragma unroll
-    for (int s = 0; s < EPL; ++s) prev[s] = T(0);
+        for (int s = 0; s < EPL; ++s) y[s] = pol.rhs(in, s) - in.f[s] * prev[s];
+        line_solve(G, S, in, y, w);
+        bstore_line(S, F.W, F.soW + (unsigned)m * lineT, w);
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) prev[s] = w[s];
+    };
+    auto upper_step = [&](int m, const LineIn<T, EPL> &in) {
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) y[s] = in.f[s] * prev[s];
+        line_solve(G, S, in, y, w);
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) w[s] = in.w[s] - w[s];
+        pol.out(m, S, w, in);
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) prev[s] = w[s];
+    };
+    // Steps i = 0..count-1 of a chain with two input buffers: the inputs of
+    // step i+1 are issued before step i runs.  With `tail`, the inputs of step
+    // `count` are issued too and left in A; with `pre`, those of step 0 are
+    // already in A.
+    auto chain = [&](int count, bool tail, bool pre, auto &&load, auto &&step) {
+        const int nl = count + (tail ? 1 : 0);
+        if (nl > 0 && !pre) load(0, A);
+        int i = 0;
+        for (; i + 1 < count; i += 2) {
+            load(i + 1, B);
+            step(i, A);
+            if (i + 2 < nl) load(i + 2, A);
+            step(i + 1, B);
+        }
+        if (i < count) {
+            if (i + 1 < nl) load(i + 1, B);
+            step(i, A);
+            if (tail) A = B;
+        }
+    };
 
     if (wv == 0) {
-        for (int m = 0; m < j2; ++m) {
-            const long long lo = (long long)m * nx;
-            rhs(m, G, y);
-            if (m > 0) {
-                load_line(G, f2p + lo - nx, f);
-#pragma unroll
-                for (int s = 0; s < EPL; ++s) y[s] -= f[s] * prev[s];
-            }
-            load_coef(G, e1p + lo, mvp + lo, mv64p + lo, C);
-            line_solve(G, C, y, w);
-            store_line(G, W + lo, w);
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) prev[s] = w[s];
-        }
+        // lines 0..j2-1 upward, then the inputs of the twist line j2 in A
+        chain(j2, true, false,
+              [&](int i, LineIn<T, EPL> &in) { load_lower(i, i - 1, in); },
+              [&](int i, const LineIn<T, EPL> &in) { lower_step(i, in); });
+        pol.load_out(j2, S, A);
+        if (j2 < ny - 1) bload_line(S, F.f2, F.soT + (unsigned)j2 * lineT, fhi);
+        else zero_line(fhi);
     } else if (wv == 1) {
-        for (int m = ny - 1; m > j2; --m) {
-            const long long lo = (long long)m * nx;
-            rhs(m, G, y);
-            if (m < ny - 1) {
-                load_line(G, f2p + lo, f);
-#pragma unroll
-                for (int s = 0; s < EPL; ++s) y[s] -= f[s] * prev[s];
-            }
-            load_coef(G, e1p + lo, mvp + lo, mv64p + lo, C);
-            line_solve(G, C, y, w);
-            store_line(G, W + lo, w);
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) prev[s] = w[s];
-        }
+        // lines ny-1..j2+1 downward (line m couples to m+1 through f2 line m)
+        chain(ny - 1 - j2, false, false,
+              [&](int i, LineIn<T, EPL> &in) {
+                  const int m = ny - 1 - i;
+                  load_lower(m, i == 0 ? -1 : m, in);
+              },
+              [&](int i, const LineIn<T, EPL> &in) { lower_step(ny - 1 - i, in); });
 #pragma unroll
         for (int s = 0; s < EPL; ++s) lds[64 * EPL + lane * EPL + s] = prev[s];
+        if (j2 + 1 < ny) load_upper(j2 + 1, j2, A);
     }
     __syncthreads();
     if (wv == 0) {  // twist line: both neighbours
-        const long long lo = (long long)j2 * nx;
-        rhs(j2, G, y);
-        if (j2 > 0) {
-            load_line(G, f2p + lo - nx, f);
 #pragma unroll
-            for (int s = 0; s < EPL; ++s) y[s] -= f[s] * prev[s];
-        }
-        if (j2 < ny - 1) {
-            load_line(G, f2p + lo, f);
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) y[s] -= f[s] * lds[64 * EPL + lane * EPL + s];
-        }
-        load_coef(G, e1p + lo, mvp + lo, mv64p + lo, C);
-        line_solve(G, C, y, w);
-        out(j2, G, w);
+        for (int s = 0; s < EPL; ++s)
+            y[s] = pol.rhs(A, s) - A.f[s] * prev[s] - fhi[s] * lds[64 * EPL + lane * EPL + s];
+        line_solve(G, S, A, y, w);
+        pol.out(j2, S, w, A);
 #pragma unroll
         for (int s = 0; s < EPL; ++s) {
             prev[s] = w[s];
             lds[lane * EPL + s] = w[s];
         }
+        if (j2 > 0) load_upper(j2 - 1, j2 - 1, A);
     }
     __syncthreads();
     if (wv == 1) {
 #pragma unroll
         for (int s = 0; s < EPL; ++s) prev[s] = lds[lane * EPL + s];
-        for (int m = j2 + 1; m < ny; ++m) {
-            const long long lo = (long long)m * nx;
-            load_line(G, f2p + lo - nx, f);
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) y[s] = f[s] * prev[s];
-            load_coef(G, e1p + lo, mvp + lo, mv64p + lo, C);
-            line_solve(G, C, y, w);
-            load_line(G, W + lo, f);
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) w[s] = f[s] - w[s];
-            out(m, G, w);
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) prev[s] = w[s];
-        }
+        // lines j2+1..ny-1 upward (line m couples to m-1 through f2 line m-1)
+        chain(ny - 1 - j2, false, true,
+              [&](int i, LineIn<T, EPL> &in) {
+                  const int m = j2 + 1 + i;
+                  load_upper(m, m - 1, in);
+              },
+              [&](int i, const LineIn<T, EPL> &in) { upper_step(j2 + 1 + i, in); });
     } else if (wv == 0) {
-        for (int m = j2 - 1; m >= 0; --m) {
-            const long long lo = (long long)m * nx;
-            load_line(G, f2p + lo, f);
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) y[s] = f[s] * prev[s];
-            load_coef(G, e1p + lo, mvp + lo, mv64p + lo, C);
-            line_solve(G, C, y, w);
-            load_line(G, W + lo, f);
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) w[s] = f[s] - w[s];
-            out(m, G, w);
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) prev[s] = w[s];
-        }
+        // lines j2-1..0 downward (line m couples to m+1 through f2 line m)
+        chain(j2, false, true,
+              [&](int i, LineIn<T, EPL> &in) {
+                  const int m = j2 - 1 - i;
+                  load_upper(m, m, in);
+              },
+              [&](int i, const LineIn<T, EPL> &in) { upper_step(j2 - 1 - i, in); });
     }
 }
 
@@ -354,6 +502,133 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Level 3: the apply z = B^{-1} r as three launches.
 // ---------------------------------------------------------------------------
 
+template <typename T>
+__device__ __forceinline__ PlaneFac<T> plane_fac(const ApplyArgs<T> &a, long long pk, rsrc_t W,
+                                                 unsigned soW) {
+    PlaneFac<T> F;
+    F.e1 = make_rsrc(a.e1);
+    F.mv = make_rsrc(a.mv);
+    F.f2 = make_rsrc(a.f2);
+    F.W = W;
+    F.mv64 = a.mv64 + pk;
+    F.soT = (unsigned)pk * (unsigned)sizeof(T);
+    F.soW = soW;
+    return F;
+}
+
+template <typename T, int EPL>
+__device__ __forceinline__ void load_r(const Slots<EPL> &S, rsrc_t r, unsigned so8,
+                                       double (&v)[EPL]) {
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) v[s] = bload((double *)nullptr, r, S.o8[s], so8);
+}
+
+// Lower level-3 step of plane k: rhs = r_k - g3 * z_kn (kn = the finished
+// neighbour toward the chain start, if any); the result z_k goes to Z.
+template <typename T, int EPL>
+struct PolLower {
+    rsrc_t r, g3, Z;
+    unsigned so8k;  // byte offset of plane k in r (FP64)
+    unsigned soTk;  // byte offset of plane k in Z
+    unsigned soTc;  // byte offset of the coupling plane min(k, kn) in g3
+    unsigned soTn;  // byte offset of plane kn in Z
+    unsigned lineT, line8;
+    bool has;
+    __device__ void load_rhs(int m, const Slots<EPL> &S, LineIn<T, EPL> &in) const {
+        load_r<T>(S, r, so8k + m * line8, in.d0);
+        if (has) {
+            bload_line(S, g3, soTc + m * lineT, in.a0);
+            bload_line(S, Z, soTn + m * lineT, in.a1);
+        }
+    }
+    __device__ T rhs(const LineIn<T, EPL> &in, int s) const {
+        T v = (T)in.d0[s];
+        if (has) v -= in.a0[s] * in.a1[s];
+        return v;
+    }
+    __device__ void load_out(int, const Slots<EPL> &, LineIn<T, EPL> &) const {}
+    __device__ void out(int m, const Slots<EPL> &S, const T (&x)[EPL], const LineIn<T, EPL> &) {
+        bstore_line(S, Z, soTk + m * lineT, x);
+    }
+};
+
+// The twist plane: rhs = r - g3_lo * z_lo - g3_hi * z_hi; the result is final.
+template <typename T, int EPL>
+struct PolTwist {
+    rsrc_t r, g3, Z, zout;
+    unsigned so8k, soTk, soTlo, soThi;  // plane k, plane k-1 and plane k+1 (Z, g3)
+    unsigned lineT, line8;
+    bool lo_nb, hi_nb, copy64;
+    double acc;
+    __device__ void load_rhs(int m, const Slots<EPL> &S, LineIn<T, EPL> &in) const {
+        load_r<T>(S, r, so8k + m * line8, in.d0);
+        if (lo_nb) {
+            bload_line(S, g3, soTlo + m * lineT, in.a0);
+            bload_line(S, Z, soTlo + m * lineT, in.a1);
+        }
+        if (hi_nb) {
+            bload_line(S, g3, soTk + m * lineT, in.a2);
+            bload_line(S, Z, soThi + m * lineT, in.a3);
+        }
+    }
+    __device__ T rhs(const LineIn<T, EPL> &in, int s) const {
+        T v = (T)in.d0[s];
+        if (lo_nb) v -= in.a0[s] * in.a1[s];
+        if (hi_nb) v -= in.a2[s] * in.a3[s];
+        return v;
+    }
+    __device__ void load_out(int m, const Slots<EPL> &S, LineIn<T, EPL> &in) const {
+        load_r<T>(S, r, so8k + m * line8, in.d0);
+    }
+    __device__ void out(int m, const Slots<EPL> &S, const T (&x)[EPL], const LineIn<T, EPL> &in) {
+        bstore_line(S, Z, soTk + m * lineT, x);
+        double xd[EPL];
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) {
+            xd[s] = (double)x[s];
+            acc += S.valid(s) ? in.d0[s] * xd[s] : 0.0;
+        }
+        if (copy64) bstore_line(S, zout, so8k + m * line8, xd);
+    }
+};
+
+// Upper level-3 step of plane k: the correction c = Pt_k^{-1}(g3 * x_kn) with
+// kn the final neighbour toward the twist plane; x_k = z_k - c over Z.
+template <typename T, int EPL>
+struct PolUpper {
+    rsrc_t r, g3, Z, zout;
+    unsigned so8k, soTk, soTc, soTn;
+    unsigned lineT, line8;
+    bool copy64;
+    double acc;
+    __device__ void load_rhs(int m, const Slots<EPL> &S, LineIn<T, EPL> &in) const {
+        bload_line(S, g3, soTc + m * lineT, in.a0);
+        bload_line(S, Z, soTn + m * lineT, in.a1);
+    }
+    __device__ T rhs(const LineIn<T, EPL> &in, int s) const { return in.a0[s] * in.a1[s]; }
+    __device__ void load_out(int m, const Slots<EPL> &S, LineIn<T, EPL> &in) const {
+        bload_line(S, Z, soTk + m * lineT, in.a2);
+        load_r<T>(S, r, so8k + m * line8, in.d0);
+    }
+    __device__ void out(int m, const Slots<EPL> &S, const T (&cv)[EPL], const LineIn<T, EPL> &in) {
+        T xv[EPL];
+        double xd[EPL];
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) {
+            xv[s] = in.a2[s] - cv[s];
+            xd[s] = (double)xv[s];
+            acc += S.valid(s) ? in.d0[s] * xd[s] : 0.0;
+        }
+        bstore_line(S, Z, soTk + m * lineT, xv);
+        if (copy64) bstore_line(S, zout, so8k + m * line8, xd);
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ bool has_fp64_copy(const ApplyArgs<T> &a) {
+    return (const void *)a.zout != (const void *)a.Z;
+}
+
 // Lower level-3 sweep of one half: block 0 takes planes 0..j3-1 upward, block 1
 // planes nz-1..j3+1 downward; z_k = Pt_k^{-1}(r_k - g3 * z_{k-+1}) into Z.
 template <typename T, int EPL>
@@ -363,34 +638,25 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply_lower(ApplyArgs<T> a) {
     const long long nxy = (long long)nx * ny;
     const int j3 = (nz - 1) / 2;
     const int h = blockIdx.x;
-    const int k0 = h == 0 ? 0 : nz - 1;
-    const int kend = h == 0 ? j3 : j3;  // exclusive bound, walked toward the twist
     const int dk = h == 0 ? 1 : -1;
-    for (int k = k0; h == 0 ? k < kend : k > kend; k += dk) {
+    PolLower<T, EPL> pol;
+    pol.r = make_rsrc(a.r);
+    pol.g3 = make_rsrc(a.g3);
+    pol.Z = make_rsrc(a.Z);
+    pol.lineT = (unsigned)nx * sizeof(T);
+    pol.line8 = (unsigned)nx * 8u;
+    for (int k = h == 0 ? 0 : nz - 1; h == 0 ? k < j3 : k > j3; k += dk) {
         const long long pk = k * nxy;
         const int kn = k - dk;  // neighbour already solved (toward the chain start)
-        const bool has = (kn >= 0 && kn < nz);
-        const long long pn = kn * nxy, pc = (has ? (k < kn ? k : kn) : 0) * nxy;
-        auto rhs = [&](int m, const LineGeom &G, T (&y)[EPL]) {
-            const long long lo = (long long)m * nx;
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) {
-                int c = G.pos(s, EPL);
-                if (G.ok(c)) {
-                    long long e = lo + G.elem(c);
-                    T v = (T)a.r[pk + e];
-                    if (has) v -= a.g3[pc + e] * a.Z[pn + e];
-                    y[s] = v;
-                } else {
-                    y[s] = T(0);
-                }
-            }
-        };
-        auto out = [&](int m, const LineGeom &G, const T (&x)[EPL]) {
-            store_line(G, a.Z + pk + (long long)m * nx, x);
-        };
-        plane_solve<T, EPL>(nx, ny, a.e1 + pk, a.mv + pk, a.mv64 + pk, a.f2 + pk, a.Z + pk, rhs,
-                            out, lds);
+        pol.has = (kn >= 0 && kn < nz);
+        const long long pc = pol.has ? (k < kn ? k : kn) * nxy : 0;
+        const long long pn = pol.has ? kn * nxy : 0;
+        pol.so8k = (unsigned)(pk * 8);
+        pol.soTk = (unsigned)(pk * (long long)sizeof(T));
+        pol.soTc = (unsigned)(pc * (long long)sizeof(T));
+        pol.soTn = (unsigned)(pn * (long long)sizeof(T));
+        const PlaneFac<T> F = plane_fac(a, pk, pol.Z, pol.soTk);
+        plane_solve<T, EPL>(nx, ny, F, pol, lds);
     }
 }
 
@@ -402,42 +668,25 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply_twist(ApplyArgs<T> a) {
     const long long nxy = (long long)nx * ny;
     const int k = (nz - 1) / 2;
     const long long pk = k * nxy;
-    const bool lo_nb = k > 0, hi_nb = k < nz - 1;
-    double acc = 0.0;
-    auto rhs = [&](int m, const LineGeom &G, T (&y)[EPL]) {
-        const long long lo = (long long)m * nx;
-#pragma unroll
-        for (int s = 0; s < EPL; ++s) {
-            int c = G.pos(s, EPL);
-            if (G.ok(c)) {
-                long long e = lo + G.elem(c);
-                T v = (T)a.r[pk + e];
-                if (lo_nb) v -= a.g3[pk - nxy + e] * a.Z[pk - nxy + e];
-                if (hi_nb) v -= a.g3[pk + e] * a.Z[pk + nxy + e];
-                y[s] = v;
-            } else {
-                y[s] = T(0);
-            }
-        }
-    };
-    auto out = [&](int m, const LineGeom &G, const T (&x)[EPL]) {
-        const long long lo = pk + (long long)m * nx;
-#pragma unroll
-        for (int s = 0; s < EPL; ++s) {
-            int c = G.pos(s, EPL);
-            if (G.ok(c)) {
-                long long e = lo + G.elem(c);
-                a.Z[e] = x[s];
-                double xd = (double)x[s];
-                if ((void *)a.zout != (void *)a.Z) a.zout[e] = xd;
-                acc += a.r[e] * xd;
-            }
-        }
-    };
-    plane_solve<T, EPL>(nx, ny, a.e1 + pk, a.mv + pk, a.mv64 + pk, a.f2 + pk, a.Z + pk, rhs, out,
-                        lds);
+    PolTwist<T, EPL> pol;
+    pol.r = make_rsrc(a.r);
+    pol.g3 = make_rsrc(a.g3);
+    pol.Z = make_rsrc(a.Z);
+    pol.zout = make_rsrc(a.zout);
+    pol.copy64 = has_fp64_copy(a);
+    pol.lo_nb = k > 0;
+    pol.hi_nb = k < nz - 1;
+    pol.lineT = (unsigned)nx * sizeof(T);
+    pol.line8 = (unsigned)nx * 8u;
+    pol.so8k = (unsigned)(pk * 8);
+    pol.soTk = (unsigned)(pk * (long long)sizeof(T));
+    pol.soTlo = pol.lo_nb ? (unsigned)((pk - nxy) * (long long)sizeof(T)) : 0u;
+    pol.soThi = pol.hi_nb ? (unsigned)((pk + nxy) * (long long)sizeof(T)) : 0u;
+    pol.acc = 0.0;
+    const PlaneFac<T> F = plane_fac(a, pk, pol.Z, pol.soTk);
+    plane_solve<T, EPL>(nx, ny, F, pol, lds);
     if (a.partials) {
-        double sum = wave_sum(acc);
+        const double sum = wave_sum(pol.acc);
         if ((threadIdx.x & 63) == 0) a.partials[threadIdx.x >> 6] = sum;
     }
 }
@@ -452,45 +701,29 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply_upper(ApplyArgs<T> a) {
     const int j3 = (nz - 1) / 2;
     const int h = blockIdx.x;
     const int dk = h == 0 ? -1 : 1;
-    T *W = a.scratch + h * nxy;
-    double acc = 0.0;
+    const rsrc_t W = make_rsrc(a.scratch);
+    const unsigned soW = (unsigned)(h * nxy * (long long)sizeof(T));
+    PolUpper<T, EPL> pol;
+    pol.r = make_rsrc(a.r);
+    pol.g3 = make_rsrc(a.g3);
+    pol.Z = make_rsrc(a.Z);
+    pol.zout = make_rsrc(a.zout);
+    pol.copy64 = has_fp64_copy(a);
+    pol.lineT = (unsigned)nx * sizeof(T);
+    pol.line8 = (unsigned)nx * 8u;
+    pol.acc = 0.0;
     for (int k = j3 + dk; k >= 0 && k < nz; k += dk) {
         const long long pk = k * nxy;
         const int kn = k - dk;  // final neighbour, toward the twist plane
-        const long long pn = kn * nxy, pc = (k < kn ? k : kn) * nxy;
-        auto rhs = [&](int m, const LineGeom &G, T (&y)[EPL]) {
-            const long long lo = (long long)m * nx;
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) {
-                int c = G.pos(s, EPL);
-                if (G.ok(c)) {
-                    long long e = lo + G.elem(c);
-                    y[s] = a.g3[pc + e] * a.Z[pn + e];
-                } else {
-                    y[s] = T(0);
-                }
-            }
-        };
-        auto out = [&](int m, const LineGeom &G, const T (&cv)[EPL]) {
-            const long long lo = pk + (long long)m * nx;
-#pragma unroll
-            for (int s = 0; s < EPL; ++s) {
-                int c = G.pos(s, EPL);
-                if (G.ok(c)) {
-                    long long e = lo + G.elem(c);
-                    T xv = a.Z[e] - cv[s];
-                    a.Z[e] = xv;
-                    double xd = (double)xv;
-                    if ((void *)a.zout != (void *)a.Z) a.zout[e] = xd;
-                    acc += a.r[e] * xd;
-                }
-            }
-        };
-        plane_solve<T, EPL>(nx, ny, a.e1 + pk, a.mv + pk, a.mv64 + pk, a.f2 + pk, W, rhs, out,
-                            lds);
+        pol.so8k = (unsigned)(pk * 8);
+        pol.soTk = (unsigned)(pk * (long long)sizeof(T));
+        pol.soTc = (unsigned)((k < kn ? k : kn) * nxy * (long long)sizeof(T));
+        pol.soTn = (unsigned)(kn * nxy * (long long)sizeof(T));
+        const PlaneFac<T> F = plane_fac(a, pk, W, soW);
+        plane_solve<T, EPL>(nx, ny, F, pol, lds);
     }
     if (a.partials) {
-        double sum = wave_sum(acc);
+        const double sum = wave_sum(pol.acc);
         if ((threadIdx.x & 63) == 0) a.partials[2 + 2 * h + (threadIdx.x >> 6)] = sum;
     }
 }
@@ -507,6 +740,22 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ double tval(const double *t, long long p) { return t ? t[p] : 1.0; }
 
+// Plain plane solve x = Pt^{-1} y with y and x plane-sized buffers.
+template <int EPL>
+struct PolPlain {
+    rsrc_t y, x;
+    unsigned line8;
+    __device__ void load_rhs(int m, const Slots<EPL> &S, LineIn<double, EPL> &in) const {
+        bload_line(S, y, m * line8, in.a0);
+    }
+    __device__ double rhs(const LineIn<double, EPL> &in, int s) const { return in.a0[s]; }
+    __device__ void load_out(int, const Slots<EPL> &, LineIn<double, EPL> &) const {}
+    __device__ void out(int m, const Slots<EPL> &S, const double (&v)[EPL],
+                        const LineIn<double, EPL> &) {
+        bstore_line(S, x, m * line8, v);
+    }
+};
+
 // Line m of plane k (one wavefront): T_m starts as the line block of P_k and
 // loses, for each neighbour line nb, phi Y phi with g = (T_nb^{-1} v)./v,
 // v = phi .* t_m, phi = the y-coupling of the two lines and Y = 2g - g T_nb g
@@ -515,7 +764,8 @@ template <int EPL>
 __device__ void line_setup(const SetupArgs &a, long long pk, int m, int nnb, int nb0, int nb1,
                            double *sh /* per-wave LDS: 5 * nx doubles */) {
     const int nx = a.nx;
-    const LineGeom G(nx);
+    const LineGeom G(nx, EPL);
+    const Slots<EPL> S(G);
     const int lane = threadIdx.x & 63;
     double *sd = sh, *se = sh + nx, *sM = sh + 2 * nx, *sg = sh + 3 * nx, *sp = sh + 4 * nx;
     const long long lm = pk + (long long)m * nx;
@@ -533,9 +783,14 @@ __device__ void line_setup(const SetupArgs &a, long long pk, int m, int nnb, int
             int c = G.pos(s, EPL);
             v[s] = G.ok(c) ? phi[s] * tval(a.t, lm + G.elem(c)) : 0.0;
         }
-        LineCoef<double, EPL> C;
-        load_coef(G, a.e1 + ln, a.mv + ln, a.mv + ln, C);
-        line_solve(G, C, v, zl);
+        LineIn<double, EPL> C;
+        PlaneFac<double> F;
+        F.e1 = make_rsrc(a.e1 + ln);
+        F.mv = make_rsrc(a.mv + ln);
+        F.mv64 = a.mv + ln;
+        F.soT = 0;
+        load_coef(S, G, F, 0, C);
+        line_solve(G, S, C, v, zl);
         load_line(G, a.dT + ln, dTn);
         load_line(G, a.e1 + ln, en);
 #pragma unroll
@@ -663,14 +918,19 @@ __device__ void plane_setup(const SetupArgs &a, int k, int nnb, int nb0, int nb1
         for (long long u = threadIdx.x; u < nxy; u += blockDim.x)
             wbuf[u] = psi[u] * tval(a.t, pk + u);
         __syncthreads();
-        auto rhs = [&](int m, const LineGeom &G, double (&y)[EPL]) {
-            load_line(G, wbuf + (long long)m * nx, y);
-        };
-        auto out = [&](int m, const LineGeom &G, const double (&x)[EPL]) {
-            store_line(G, zbuf + (long long)m * nx, x);
-        };
-        plane_solve<double, EPL>(nx, ny, a.e1 + pn, a.mv + pn, a.mv + pn, a.f2 + pn, zbuf, rhs,
-                                 out, lds_x);
+        PolPlain<EPL> pol;
+        pol.y = make_rsrc(wbuf);
+        pol.x = make_rsrc(zbuf);
+        pol.line8 = (unsigned)nx * 8u;
+        PlaneFac<double> F;
+        F.e1 = make_rsrc(a.e1 + pn);
+        F.mv = make_rsrc(a.mv + pn);
+        F.f2 = make_rsrc(a.f2 + pn);
+        F.W = pol.x;
+        F.mv64 = a.mv + pn;
+        F.soT = 0;
+        F.soW = 0;
+        plane_solve<double, EPL>(nx, ny, F, pol, lds_x);
         __syncthreads();
         const double *dPn = a.dP + pn, *xPn = a.xP + pn, *yPn = a.f2 + pn;
         for (long long u = threadIdx.x; u < nxy; u += blockDim.x) {
@@ -710,8 +970,8 @@ __device__ void plane_setup(const SetupArgs &a, int k, int nnb, int nb0, int nb1
 template <int EPL>
 __global__ void __launch_bounds__(kSetupThreads) k_setup_halves(SetupArgs a) {
     extern __shared__ double smem[];
-    double *lds_lines = smem;                  // 2 waves x 5 lines
-    double *lds_x = smem + 10 * a.nx;          // 2 x 64*EPL exchange lines
+    double *lds_lines = smem;          // 2 waves x 5 lines
+    double *lds_x = smem + 10 * a.nx;  // 2 x 64*EPL exchange lines
     const long long nxy = (long long)a.nx * a.ny;
     const int j3 = (a.nz - 1) / 2;
     const int h = blockIdx.x;
@@ -739,11 +999,17 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup_twist(SetupArgs a) {
                      lds_x);
 }
 
+// The apply as three stream-ordered launches; ev (optional, 4 events) brackets
+// them for per-launch timing.
 template <typename T, int EPL>
-hipError_t apply_impl(const ApplyArgs<T> &a, hipStream_t s) {
+hipError_t apply_impl(const ApplyArgs<T> &a, hipStream_t s, hipEvent_t *ev) {
+    if (ev) (void)hipEventRecord(ev[0], s);
     hipLaunchKernelGGL((k_apply_lower<T, EPL>), dim3(2), dim3(kApplyThreads), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[1], s);
     hipLaunchKernelGGL((k_apply_twist<T, EPL>), dim3(1), dim3(kApplyThreads), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[2], s);
     hipLaunchKernelGGL((k_apply_upper<T, EPL>), dim3(2), dim3(kApplyThreads), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[3], s);
     return hipGetLastError();
 }
 
@@ -751,10 +1017,10 @@ template <int EPL>
 hipError_t setup_impl(const SetupArgs &a, hipStream_t s) {
     size_t sh = sizeof(double) * (10 * (size_t)a.nx + 2 * 64 * EPL);
     if (sh > 65536) {
-        hipFuncSetAttribute((const void *)k_setup_halves<EPL>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        hipFuncSetAttribute((const void *)k_setup_twist<EPL>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        (void)hipFuncSetAttribute((const void *)k_setup_halves<EPL>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        (void)hipFuncSetAttribute((const void *)k_setup_twist<EPL>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     }
     hipLaunchKernelGGL((k_setup_halves<EPL>), dim3(2), dim3(kSetupThreads), sh, s, a);
     hipLaunchKernelGGL((k_setup_twist<EPL>), dim3(1), dim3(kSetupThreads), sh, s, a);
