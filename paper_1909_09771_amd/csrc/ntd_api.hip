@@ -13,13 +13,14 @@ using ntd::Scalars;
 
 struct ntd_handle {
     int nx, ny, nz, prec, schur, epl;
-    long long N, nxy;
+    long long N, nxy, npack;                  // npack = ny*nz*64*epl packed slots
     size_t used;
     double *d, *ax, *ay, *az;                 // bands of A
-    double *e1, *mv, *f2, *dT, *dP, *xP;      // factors (FP64) and setup state
+    double *e1, *mv, *f2, *dT, *dP, *xP;      // factors (FP64, natural layout) and setup state
     double *r, *z, *p, *q;                    // PCG vectors
-    float *e1f, *mvf, *f2f, *g3f, *Zf;        // MIXED: float copies and the sweep intermediate
-    void *scratch;                            // plane-sized scratch
+    void *pmv, *pa, *pu, *pf2, *pg3, *pZ;     // packed apply arrays (float in MIXED, else double)
+    double *tw;                               // FP64 twist records, 4 per line
+    void *scratch;                            // setup planes / packed apply planes
     double *partials;
     Scalars *sc;
     int *flag;
@@ -47,23 +48,27 @@ struct Carver {
 bool grid_ok(int nx, int ny, int nz) {
     if (nx < 1 || ny < 1 || nz < 1) return false;
     if (nx > NTD_MAX_NX || ntd::epl_for(nx) == 0) return false;
-    // the sweeps address FP64 arrays with 32-bit byte offsets
+    // the sweeps address FP64 arrays (natural and packed) with 32-bit byte offsets
     long long N = (long long)nx * ny * nz;
-    return N * 8 < 0x7fffffffLL;
+    long long npack = (long long)ny * nz * 64 * ntd::epl_for(nx);
+    return N * 8 < 0x7fffffffLL && npack * 8 < 0x7fffffffLL;
 }
 
 size_t layout(ntd_handle *h, void *ws, int nx, int ny, int nz, int prec) {
     const long long N = (long long)nx * ny * nz, nxy = (long long)nx * ny;
+    const long long lane_slots = 64LL * ntd::epl_for(nx);
+    const long long npack = (long long)ny * nz * lane_slots;
+    const size_t tsz = prec == NTD_PREC_MIXED ? sizeof(float) : sizeof(double);
     Carver c(ws);
     double **f64[] = {&h->d, &h->ax, &h->ay, &h->az, &h->e1, &h->mv, &h->f2,
                       &h->dT, &h->dP, &h->xP, &h->r, &h->z, &h->p, &h->q};
     for (double **a : f64) *a = c.take<double>(N);
-    h->e1f = h->mvf = h->f2f = h->g3f = h->Zf = nullptr;
-    if (prec == NTD_PREC_MIXED) {
-        float **f32[] = {&h->e1f, &h->mvf, &h->f2f, &h->g3f, &h->Zf};
-        for (float **a : f32) *a = c.take<float>(N);
-    }
-    h->scratch = c.take<double>(6 * nxy);
+    void **pk[] = {&h->pmv, &h->pa, &h->pu, &h->pf2, &h->pg3, &h->pZ};
+    for (void **a : pk) *a = (void *)c.take<char>(npack * tsz);
+    h->tw = c.take<double>(4 * (size_t)ny * nz);
+    const size_t setup_scr = 6 * (size_t)nxy * sizeof(double);
+    const size_t apply_scr = 2 * (size_t)ny * lane_slots * tsz;
+    h->scratch = (void *)c.take<char>(setup_scr > apply_scr ? setup_scr : apply_scr);
     h->partials = c.take<double>(ntd::kMaxBlocks + ntd::kApplySlots);
     h->sc = c.take<Scalars>(1);
     h->flag = c.take<int>(4);
@@ -83,32 +88,45 @@ ntd::Grid grid_of(const ntd_handle *h) {
     return g;
 }
 
+template <typename T>
+ntd::ApplyArgs<T> apply_args(const ntd_handle *h, const double *r, double *z, double *partials) {
+    ntd::ApplyArgs<T> a;
+    a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
+    a.pmv = (const T *)h->pmv; a.pa = (const T *)h->pa; a.pu = (const T *)h->pu;
+    a.pf2 = (const T *)h->pf2; a.pg3 = (const T *)h->pg3; a.tw = h->tw;
+    a.r = r; a.Z = (T *)h->pZ; a.zout = z; a.scratch = (T *)h->scratch; a.partials = partials;
+    return a;
+}
+
+template <typename T>
+ntd::PackArgs<T> pack_args(const ntd_handle *h) {
+    ntd::PackArgs<T> p;
+    p.nx = h->nx; p.nlines = (long long)h->ny * h->nz;
+    p.e1 = h->e1; p.mv = h->mv; p.f2 = h->f2; p.g3 = h->az;
+    p.pmv = (T *)h->pmv; p.pa = (T *)h->pa; p.pu = (T *)h->pu; p.pf2 = (T *)h->pf2;
+    p.pg3 = (T *)h->pg3; p.tw = h->tw;
+    return p;
+}
+
 // z = B^{-1} r; partials (if not null) receive the 6 per-wave partials of r.z;
 // ev (if not null, 4 events) brackets the three launches.
 int apply_internal(ntd_handle *h, const double *r, double *z, double *partials, hipStream_t s,
                    hipEvent_t *ev = nullptr) {
     if (h->prec == NTD_PREC_FP64) {
-        ntd::ApplyArgs<double> a;
-        a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
-        a.e1 = h->e1; a.mv = h->mv; a.f2 = h->f2; a.g3 = h->az; a.mv64 = h->mv;
-        a.r = r; a.Z = z; a.zout = z; a.scratch = (double *)h->scratch; a.partials = partials;
-        CK(ntd::launch_apply_f64(a, h->epl, s, ev));
+        CK(ntd::launch_apply_f64(apply_args<double>(h, r, z, partials), h->epl, s, ev));
     } else {
-        ntd::ApplyArgs<float> a;
-        a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
-        a.e1 = h->e1f; a.mv = h->mvf; a.f2 = h->f2f; a.g3 = h->g3f; a.mv64 = h->mv;
-        a.r = r; a.Z = h->Zf; a.zout = z; a.scratch = (float *)h->scratch; a.partials = partials;
-        CK(ntd::launch_apply_f32(a, h->epl, s, ev));
+        CK(ntd::launch_apply_f32(apply_args<float>(h, r, z, partials), h->epl, s, ev));
     }
     return NTD_OK;
 }
 
-int cast_factors(ntd_handle *h, hipStream_t s) {
-    if (h->prec != NTD_PREC_MIXED) return NTD_OK;
-    CK(ntd::launch_cast_f32(h->e1f, h->e1, h->N, s));
-    CK(ntd::launch_cast_f32(h->mvf, h->mv, h->N, s));
-    CK(ntd::launch_cast_f32(h->f2f, h->f2, h->N, s));
-    CK(ntd::launch_cast_f32(h->g3f, h->az, h->N, s));
+// Pack the FP64 natural-layout factors into the apply layout and precision.
+int pack_factors(ntd_handle *h, hipStream_t s) {
+    if (h->prec == NTD_PREC_FP64) {
+        CK(ntd::launch_pack_f64(pack_args<double>(h), h->epl, s));
+    } else {
+        CK(ntd::launch_pack_f32(pack_args<float>(h), h->epl, s));
+    }
     return NTD_OK;
 }
 
@@ -176,6 +194,7 @@ int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const 
     h->epl = ntd::epl_for(nx);
     h->N = (long long)nx * ny * nz;
     h->nxy = (long long)nx * ny;
+    h->npack = (long long)ny * nz * 64 * h->epl;
     h->used = layout(h, workspace, nx, ny, nz, prec);
     hipStream_t s = S(stream);
     int st = NTD_OK;
@@ -199,7 +218,7 @@ int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const 
     HK(hipMemcpyAsync(&hflag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HK(hipStreamSynchronize(s));
     if (hflag & ntd::kFlagNotSPD) FAIL(NTD_ENOTSPD);
-    if ((st = cast_factors(h, s)) != NTD_OK) goto fail;
+    if ((st = pack_factors(h, s)) != NTD_OK) goto fail;
     HK(hipStreamSynchronize(s));
     *out = h;
     return NTD_OK;
@@ -314,7 +333,7 @@ int ntd_load_factors(ntd_handle *h, const double *e1, const double *pivots, cons
     CK(ntd::launch_copy(h->e1, e1, h->N, s));
     CK(ntd::launch_recip(h->mv, pivots, h->N, s));
     CK(ntd::launch_copy(h->f2, f2, h->N, s));
-    return cast_factors(h, s);
+    return pack_factors(h, s);
 }
 
 size_t ntd_footprint_bytes(const ntd_handle *h) { return h ? h->used : 0; }

@@ -12,4 +12,13 @@ hipError_t launch_apply_f32(const ApplyArgs<float> &a, int epl, hipStream_t s, h
     }
 }
 
+hipError_t launch_pack_f32(const PackArgs<float> &p, int epl, hipStream_t s) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return pack_impl<float, E>(p, s);
+        NTD_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace ntd

@@ -12,4 +12,13 @@ hipError_t launch_apply_f64(const ApplyArgs<double> &a, int epl, hipStream_t s, 
     }
 }
 
+hipError_t launch_pack_f64(const PackArgs<double> &p, int epl, hipStream_t s) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return pack_impl<double, E>(p, s);
+        NTD_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace ntd

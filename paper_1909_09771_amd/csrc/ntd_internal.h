@@ -43,18 +43,34 @@ struct Grid {
     long long nxy, N;
 };
 
-// Arguments of the nested sweeps (apply): factor arrays in the sweep precision T,
-// the FP64 pivots of the twist rows, and the buffers of one apply.
+// Packed ("lane order") layout of the apply: every grid line (nx elements) is
+// stored as 64*EPL slots, slot lane*EPL + s holding the element that lane's
+// position s solves (lanes 0-31: elements 0..j, lanes 32-63: elements nx-1 down
+// to j+1, j = floor((nx-1)/2), both right-aligned in their half); unused slots
+// hold identity values.  Line L = k*ny + m starts at slot L*64*EPL.
+
+// Arguments of the nested sweeps (apply) in the sweep precision T.
 template <typename T>
 struct ApplyArgs {
     int nx, ny, nz;
-    const T *e1, *mv, *f2, *g3;   // x-band of T, 1/pivot, y-band of P, z-band of A
-    const double *mv64;           // FP64 1/pivot (read at the twist row of each line)
-    const double *r;              // right-hand side (FP64)
-    T *Z;                         // intermediate / final result in precision T
-    double *zout;                 // final FP64 result (== Z when T is double)
-    T *scratch;                   // two plane-sized buffers (one per half chain)
+    const T *pmv, *pa, *pu;       // packed 1/M, a = -cp/M, u = -cn/M
+    const T *pf2, *pg3;           // packed y-band of P and z-band of A
+    const double *tw;             // per line: 1/M_j, e1[j-1], e1[j], 0 (FP64 twist row)
+    const double *r;              // right-hand side (FP64, natural layout)
+    T *Z;                         // packed intermediate / final result
+    double *zout;                 // final result (FP64, natural layout)
+    T *scratch;                   // two packed plane buffers (one per half chain)
     double *partials;             // kApplySlots partial sums of r.z (may be null)
+};
+
+// Arguments of the packing of FP64 natural-layout factors into the apply layout.
+template <typename T>
+struct PackArgs {
+    int nx;
+    long long nlines;             // ny*nz
+    const double *e1, *mv, *f2, *g3;
+    T *pmv, *pa, *pu, *pf2, *pg3;
+    double *tw;
 };
 
 // Arguments of the factorization.
@@ -72,6 +88,8 @@ int epl_for(int nx);  // elements per lane of a half-wave chain, 0 if unsupporte
 hipError_t launch_apply_f64(const ApplyArgs<double> &a, int epl, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_apply_f32(const ApplyArgs<float> &a, int epl, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_setup(const SetupArgs &a, int epl, hipStream_t s);
+hipError_t launch_pack_f64(const PackArgs<double> &p, int epl, hipStream_t s);
+hipError_t launch_pack_f32(const PackArgs<float> &p, int epl, hipStream_t s);
 
 hipError_t launch_check_positive(const double *kappa, const double *t, long long N, int *flag,
                                  hipStream_t s);

@@ -246,72 +246,114 @@ __device__ __forceinline__ void scan_bwd32(T &U, T &G, int lane) {
     if (((lane >> 4) & 1) == 0) G = U * gn + G;
 }
 
-// Everything one line step reads from memory, loaded one step ahead: 1/M and
-// the x-band e1 at the slot's element (e0) and its left neighbour (em1), the
-// FP64 1/M of the twist row, the y-coupling f to the neighbour line, the
-// lower-sweep result w (upper sweeps), and raw inputs a*, d0 of the caller's
-// right-hand side and output (combined only when used, so that the loads stay
-// in flight).
+// Vector access to one lane's EPL consecutive values of a packed line, in the
+// widest chunks (16, 8 or 4 bytes) that divide EPL*sizeof(T); lane bases are
+// multiples of EPL*sizeof(T) and line bases of 64*EPL*sizeof(T), so every chunk
+// is aligned to its size.
+// (Elements of the returned vectors are first copied into plain unsigned
+// scalars: a bit cast applied directly to a vector element is mis-compiled by
+// this toolchain, which then loads only the first dword.)
 template <typename T, int EPL>
-struct LineIn {
-    T mv[EPL], e0[EPL], em1[EPL];
-    T f[EPL], w[EPL];
-    T a0[EPL], a1[EPL], a2[EPL], a3[EPL];
-    double d0[EPL];
-    double mvj;
-};
-
-// Factor buffers of the plane being solved: so* are byte offsets of the plane.
-template <typename T>
-struct PlaneFac {
-    rsrc_t e1, mv, f2, W;
-    const double *mv64;  // FP64 1/M, pointer to the plane's first element
-    unsigned soT;        // byte offset of the plane in e1/mv/f2
-    unsigned soW;        // byte offset of the plane in W
-};
-
-template <typename T, int EPL>
-__device__ __forceinline__ void load_coef(const Slots<EPL> &S, const LineGeom &G,
-                                          const PlaneFac<T> &F, int m, LineIn<T, EPL> &C) {
-    const unsigned so = F.soT + (unsigned)(m * G.n) * (unsigned)sizeof(T);
+__device__ __forceinline__ void vload(rsrc_t r, unsigned vo, unsigned so, T (&v)[EPL]) {
+    typedef unsigned int u32x4 __attribute__((__vector_size__(4 * sizeof(unsigned int))));
+    constexpr int PB = EPL * (int)sizeof(T);
+    constexpr int CH = (PB % 16 == 0) ? 16 : (PB % 8 == 0) ? 8 : 4;
+    static_assert(CH >= (int)sizeof(T), "chunk");
 #pragma unroll
-    for (int s = 0; s < EPL; ++s) {
-        C.mv[s] = bload((T *)nullptr, F.mv, S.off((T *)nullptr, s), so);
-        C.e0[s] = bload((T *)nullptr, F.e1, S.off((T *)nullptr, s), so);
-        C.em1[s] = bload((T *)nullptr, F.e1, S.offm1((T *)nullptr, s), so);
+    for (int c = 0; c < PB / CH; ++c) {
+        const int vo_c = (int)(vo + c * CH);
+        if constexpr (CH == 16) {
+            const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, vo_c, (int)so, 0);
+            const unsigned w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3];
+            if constexpr (sizeof(T) == 4) {
+                v[c * 4 + 0] = __builtin_bit_cast(T, w0);
+                v[c * 4 + 1] = __builtin_bit_cast(T, w1);
+                v[c * 4 + 2] = __builtin_bit_cast(T, w2);
+                v[c * 4 + 3] = __builtin_bit_cast(T, w3);
+            } else {
+                v[c * 2 + 0] = __builtin_bit_cast(T, ((unsigned long long)w1 << 32) | w0);
+                v[c * 2 + 1] = __builtin_bit_cast(T, ((unsigned long long)w3 << 32) | w2);
+            }
+        } else if constexpr (CH == 8) {
+            const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, vo_c, (int)so, 0);
+            const unsigned w0 = w[0], w1 = w[1];
+            if constexpr (sizeof(T) == 4) {
+                v[c * 2 + 0] = __builtin_bit_cast(T, w0);
+                v[c * 2 + 1] = __builtin_bit_cast(T, w1);
+            } else {
+                v[c] = __builtin_bit_cast(T, ((unsigned long long)w1 << 32) | w0);
+            }
+        } else {
+            const unsigned w0 = __builtin_amdgcn_raw_buffer_load_b32(r, vo_c, (int)so, 0);
+            v[c] = __builtin_bit_cast(T, w0);
+        }
     }
-    C.mvj = F.mv64[(long long)m * G.n + G.ca - 1];
 }
 
-// x = T^{-1} y for one line held by the calling wavefront (all 64 lanes).
-// Lower sweep: g_c = a_c g_{c-1} + b_c along each chain toward the twist with
-// a_c = -cp/M, b_c = y/M (cp = coupling to the chain predecessor); the twist
-// row takes both neighbours, in FP64.  Upper sweep: x_c = u_c x_{c+1} + g_c
-// from the twist outward, u_c = -cn/M (cn = coupling toward the twist), the
-// top of chain B being seeded with the twist value.
 template <typename T, int EPL>
-__device__ __forceinline__ void line_solve(const LineGeom &G, const Slots<EPL> &S,
-                                           const LineIn<T, EPL> &C, const T (&y)[EPL],
-                                           T (&x)[EPL]) {
-    const int lane = threadIdx.x & 63;
-    T a[EPL], g[EPL], gm1[EPL], cp[EPL], cn[EPL];
+__device__ __forceinline__ void vstore(rsrc_t r, unsigned vo, unsigned so, const T (&v)[EPL]) {
+    typedef unsigned int u32x4 __attribute__((__vector_size__(4 * sizeof(unsigned int))));
+    constexpr int PB = EPL * (int)sizeof(T);
+    constexpr int CH = (PB % 16 == 0) ? 16 : (PB % 8 == 0) ? 8 : 4;
 #pragma unroll
-    for (int s = 0; s < EPL; ++s) {
-        cp[s] = G.half ? C.e0[s] : C.em1[s];
-        cn[s] = G.half ? C.em1[s] : C.e0[s];
+    for (int c = 0; c < PB / CH; ++c) {
+        const int vo_c = (int)(vo + c * CH);
+        if constexpr (CH == 16) {
+            u32x4 w;
+            if constexpr (sizeof(T) == 4) {
+                w[0] = __builtin_bit_cast(unsigned, v[c * 4 + 0]);
+                w[1] = __builtin_bit_cast(unsigned, v[c * 4 + 1]);
+                w[2] = __builtin_bit_cast(unsigned, v[c * 4 + 2]);
+                w[3] = __builtin_bit_cast(unsigned, v[c * 4 + 3]);
+            } else {
+                const unsigned long long x0 = __builtin_bit_cast(unsigned long long, v[c * 2 + 0]);
+                const unsigned long long x1 = __builtin_bit_cast(unsigned long long, v[c * 2 + 1]);
+                w[0] = (unsigned)x0; w[1] = (unsigned)(x0 >> 32);
+                w[2] = (unsigned)x1; w[3] = (unsigned)(x1 >> 32);
+            }
+            __builtin_amdgcn_raw_buffer_store_b128(w, r, vo_c, (int)so, 0);
+        } else if constexpr (CH == 8) {
+            u32x2 w;
+            if constexpr (sizeof(T) == 4) {
+                w[0] = __builtin_bit_cast(unsigned, v[c * 2 + 0]);
+                w[1] = __builtin_bit_cast(unsigned, v[c * 2 + 1]);
+            } else {
+                const unsigned long long x0 = __builtin_bit_cast(unsigned long long, v[c]);
+                w[0] = (unsigned)x0; w[1] = (unsigned)(x0 >> 32);
+            }
+            __builtin_amdgcn_raw_buffer_store_b64(w, r, vo_c, (int)so, 0);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v[c]), r, vo_c,
+                                                  (int)so, 0);
+        }
     }
+}
+
+// The twisted solve of one line held by the calling wavefront, given per slot
+// the lower-sweep coefficient a (-cp/M; 1 on unused slots), 1/M (0 on unused
+// slots) and the upper-sweep coefficient u (-cn/M; 0 on unused slots and on
+// the twist slot), and, for the twist row, 1/M, cp and cn in FP64.
+// Lower sweep: g_c = a_c g_{c-1} + y_c/M_c along each chain toward the twist;
+// the twist row takes both neighbours, in FP64.  Upper sweep: x_c = u_c x_{c+1}
+// + g_c from the twist outward, the top of chain B (lane 63, last slot) being
+// seeded with the twist value.
+template <typename T, int EPL>
+__device__ __forceinline__ void solve_core(const T (&a)[EPL], const T (&mv)[EPL],
+                                           const T (&uin)[EPL], double mvj, double cpj,
+                                           double cnj, const T (&y)[EPL], T (&x)[EPL]) {
+    const int lane = threadIdx.x & 63;
+    const int hl = lane & 31;
+    T g[EPL], gm1[EPL], u[EPL];
     T A = T(1), B = T(0);
 #pragma unroll
     for (int s = 0; s < EPL; ++s) {
-        const bool ok = S.valid(s);
-        a[s] = ok ? -C.mv[s] * cp[s] : T(1);
-        g[s] = C.mv[s] * y[s];  // 1/M is 0 outside the chain
+        g[s] = mv[s] * y[s];
         B = a[s] * B + g[s];
         A = a[s] * A;
     }
     scan_fwd32(A, B);
     T carry = dpp<kWaveShr1>(T(0), B);
-    if (G.hl == 0) carry = T(0);
+    if (hl == 0) carry = T(0);
 #pragma unroll
     for (int s = 0; s < EPL; ++s) {
         gm1[s] = carry;
@@ -319,19 +361,19 @@ __device__ __forceinline__ void line_solve(const LineGeom &G, const Slots<EPL> &
         carry = g[s];
     }
     // Twist element j: lane 31, slot EPL-1; its neighbour j+1 ends chain B in
-    // lane 63, slot EPL-1 (0 there when chain B is empty).  The twist row is
-    // evaluated in FP64 and broadcast.
+    // lane 63, slot EPL-1 (0 there when chain B is empty).
     constexpr int L = EPL - 1;
     const T gB = rdlane(g[L], 63);
-    double gj = C.mvj * ((double)y[L] - (double)cp[L] * (double)gm1[L] - (double)cn[L] * (double)gB);
+    double gj = mvj * ((double)y[L] - cpj * (double)gm1[L] - cnj * (double)gB);
     gj = rdlane(gj, 31);
     const T xj = (T)gj;
-    if (lane == 31) g[L] = xj;
-    T u[EPL];
 #pragma unroll
-    for (int s = 0; s < EPL; ++s) u[s] = -C.mv[s] * cn[s];  // 0 outside the chain
-    if (lane == 31) u[L] = T(0);
-    if (lane == 63) {  // seed chain B with x_j = g_j
+    for (int s = 0; s < EPL; ++s) u[s] = uin[s];
+    if (lane == 31) {
+        g[L] = xj;
+        u[L] = T(0);
+    }
+    if (lane == 63) {  // seed chain B with x_j
         g[L] = g[L] + u[L] * xj;
         u[L] = T(0);
     }
@@ -343,7 +385,7 @@ __device__ __forceinline__ void line_solve(const LineGeom &G, const Slots<EPL> &
     }
     scan_bwd32(U, Gs, lane);
     T xn = dpp<kWaveShl1>(T(0), Gs);
-    if (G.hl == 31) xn = T(0);
+    if (hl == 31) xn = T(0);
 #pragma unroll
     for (int s = EPL - 1; s >= 0; --s) {
         x[s] = u[s] * xn + g[s];
@@ -351,87 +393,211 @@ __device__ __forceinline__ void line_solve(const LineGeom &G, const Slots<EPL> &
     }
 }
 
+// Everything one line step reads from memory, loaded ahead of use: the line's
+// solve coefficients (format dependent), the y-coupling f to the neighbour
+// line, the lower-sweep result w (upper sweeps), and raw inputs a*, d0 of the
+// caller's right-hand side and output (combined only when used, so that the
+// loads stay in flight).
+template <typename T, int EPL>
+struct LineIn {
+    T c0[EPL], c1[EPL], c2[EPL];  // natural: 1/M, e1[e], e1[e-1]; packed: 1/M, a, u
+    T f[EPL], w[EPL];
+    T a0[EPL], a1[EPL], a2[EPL], a3[EPL];
+    double d0[EPL];
+    double mvj, cpj, cnj;
+};
+
+// Natural layout (the factorization's own arrays, FP64): lines of nx elements,
+// couplings taken from the x-band e1 around each slot's element.
+template <typename T, int EPL>
+struct NatFmt {
+    using Ty = T;
+    static constexpr int kEPL = EPL;
+    LineGeom G;
+    Slots<EPL> S;
+    rsrc_t e1, mv, f2, W;
+    const double *mv64;  // FP64 1/M of the plane
+    unsigned soT, soW, lineB;
+    __device__ NatFmt(int nx) : G(nx, EPL), S(G) {}
+    __device__ void load_coef(int m, LineIn<T, EPL> &in) const {
+        const unsigned so = soT + (unsigned)m * lineB;
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) {
+            in.c0[s] = bload((T *)nullptr, mv, S.off((T *)nullptr, s), so);
+            in.c1[s] = bload((T *)nullptr, e1, S.off((T *)nullptr, s), so);
+            in.c2[s] = bload((T *)nullptr, e1, S.offm1((T *)nullptr, s), so);
+        }
+        in.mvj = mv64[(long long)m * G.n + G.ca - 1];
+    }
+    __device__ void load_f(int lc, T (&f)[EPL]) const {
+        bload_line(S, f2, soT + (unsigned)lc * lineB, f);
+    }
+    __device__ void load_w(int m, T (&w)[EPL]) const {
+        bload_line(S, W, soW + (unsigned)m * lineB, w);
+    }
+    __device__ void store_w(int m, const T (&w)[EPL]) const {
+        bstore_line(S, W, soW + (unsigned)m * lineB, w);
+    }
+    __device__ void solve(const LineIn<T, EPL> &in, const T (&y)[EPL], T (&x)[EPL]) const {
+        T a[EPL], u[EPL];
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) {
+            const T cp = G.half ? in.c1[s] : in.c2[s];
+            const T cn = G.half ? in.c2[s] : in.c1[s];
+            a[s] = S.valid(s) ? -in.c0[s] * cp : T(1);
+            u[s] = -in.c0[s] * cn;
+        }
+        constexpr int L = EPL - 1;
+        const double cpj = (double)(G.half ? in.c1[L] : in.c2[L]);
+        const double cnj = (double)(G.half ? in.c2[L] : in.c1[L]);
+        solve_core(a, in.c0, u, in.mvj, cpj, cnj, y, x);
+    }
+};
+
+// Packed layout (the apply): every line is 64*EPL slots in lane order, the
+// slot of lane l and position s holding the element LineGeom assigns to it;
+// unused slots hold 1/M = 0, a = 1, u = 0, f = g3 = 0.  The FP64 twist record
+// of line m is (1/M_j, e1[j-1], e1[j], 0).
+template <typename T, int EPL>
+struct PackFmt {
+    using Ty = T;
+    static constexpr int kEPL = EPL;
+    LineGeom G;
+    Slots<EPL> S;        // natural-layout offsets, for r and the FP64 output
+    rsrc_t mv, a, u, f2, W;
+    const double *tw;    // twist records of the plane, 4 doubles per line
+    unsigned soT, soW;   // byte offset of the plane in the packed arrays / in W
+    unsigned lineB;      // bytes of one packed line
+    unsigned laneB;      // byte offset of this lane inside a packed line
+    __device__ explicit PackFmt(int nx) : G(nx, EPL), S(G) {
+        lineB = 64u * EPL * (unsigned)sizeof(T);
+        laneB = (unsigned)(threadIdx.x & 63) * EPL * (unsigned)sizeof(T);
+    }
+    __device__ void load_coef(int m, LineIn<T, EPL> &in) const {
+        const unsigned so = soT + (unsigned)m * lineB;
+        vload(mv, laneB, so, in.c0);
+        vload(a, laneB, so, in.c1);
+        vload(u, laneB, so, in.c2);
+        in.mvj = tw[4 * m + 0];
+        in.cpj = tw[4 * m + 1];
+        in.cnj = tw[4 * m + 2];
+    }
+    __device__ void load_f(int lc, T (&f)[EPL]) const {
+        vload(f2, laneB, soT + (unsigned)lc * lineB, f);
+    }
+    __device__ void load_w(int m, T (&w)[EPL]) const { vload(W, laneB, soW + (unsigned)m * lineB, w); }
+    __device__ void store_w(int m, const T (&w)[EPL]) const {
+        vstore(W, laneB, soW + (unsigned)m * lineB, w);
+    }
+    __device__ void solve(const LineIn<T, EPL> &in, const T (&y)[EPL], T (&x)[EPL]) const {
+        solve_core(in.c1, in.c0, in.c2, in.mvj, in.cpj, in.cnj, y, x);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Level 2: one plane per workgroup, two wavefronts (the two half chains).
 // ---------------------------------------------------------------------------
 
-// Solve Pt x = y for the plane described by F:
+// Solve Pt x = y for one plane:
 //   lower: w_m = T_m^{-1}(y_m - f*w_{m-1}) for m < j2 (wave 0), mirrored for
 //          m > j2 (wave 1), the twist line j2 taking both neighbours;
 //   upper: x_{j2} = w_{j2}; x_m = w_m - T_m^{-1}(f*x_{m+-1}) outward.
-// The policy `pol` supplies the right-hand side and takes the results:
-//   pol.load_rhs(m, S, in)  issue the loads of line m's right-hand side into in
-//   pol.rhs(in, s)          the right-hand side value of slot s
-//   pol.load_out(m, S, in)  issue the loads the output of line m needs
-//   pol.out(m, S, x, in)    receive the final x of line m (exactly once)
-// F.W (plane-sized) keeps the lower results.  Every input of line m+1 is
-// loaded while line m is solved.  All threads of the block must call it (it
-// holds two block barriers).
-template <typename T, int EPL, class Pol>
-__device__ void plane_solve(int nx, int ny, const PlaneFac<T> &F, Pol &pol,
-                            T *lds /* [2][64*EPL] */) {
+// `fmt` addresses the plane's factors and the lower-result buffer W; the
+// policy `pol` supplies the right-hand side and takes the results:
+//   pol.load_rhs(m, fmt, in)  issue the loads of line m's right-hand side
+//   pol.rhs(in, s)            the right-hand side value of slot s
+//   pol.load_out(m, fmt, in)  issue the loads the output of line m needs
+//   pol.out(m, fmt, x, in)    receive the final x of line m (exactly once)
+// The inputs of the next DEPTH lines are in flight while a line is solved.
+// All threads of the block must call it (it holds two block barriers).
+template <int DEPTH, class Fmt, class Pol>
+__device__ void plane_solve(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty *lds) {
+    using T = typename Fmt::Ty;
+    constexpr int EPL = Fmt::kEPL;
+    static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth");
     const int wv = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const LineGeom G(nx, EPL);
-    const Slots<EPL> S(G);
     const int j2 = (ny - 1) / 2;
-    const unsigned lineT = (unsigned)nx * (unsigned)sizeof(T);
     T y[EPL], w[EPL], prev[EPL], fhi[EPL];
     LineIn<T, EPL> A, B;
+    [[maybe_unused]] LineIn<T, EPL> C;
     zero_line(prev);
 
     // inputs of the lower step of line m, coupled to its chain predecessor
     // through the f2 line lc (lc < 0: first line of the chain)
     auto load_lower = [&](int m, int lc, LineIn<T, EPL> &in) {
-        pol.load_rhs(m, S, in);
-        if (lc >= 0) bload_line(S, F.f2, F.soT + (unsigned)lc * lineT, in.f);
+        pol.load_rhs(m, fmt, in);
+        if (lc >= 0) fmt.load_f(lc, in.f);
         else zero_line(in.f);
-        load_coef(S, G, F, m, in);
+        fmt.load_coef(m, in);
     };
     // inputs of the upper step of line m, coupled to its final neighbour toward
     // the twist through the f2 line lc
     auto load_upper = [&](int m, int lc, LineIn<T, EPL> &in) {
-        bload_line(S, F.W, F.soW + (unsigned)m * lineT, in.w);
-        bload_line(S, F.f2, F.soT + (unsigned)lc * lineT, in.f);
-        load_coef(S, G, F, m, in);
-        pol.load_out(m, S, in);
+        fmt.load_w(m, in.w);
+        fmt.load_f(lc, in.f);
+        fmt.load_coef(m, in);
+        pol.load_out(m, fmt, in);
     };
     auto lower_step = [&](int m, const LineIn<T, EPL> &in) {
 #pragma unroll
         for (int s = 0; s < EPL; ++s) y[s] = pol.rhs(in, s) - in.f[s] * prev[s];
-        line_solve(G, S, in, y, w);
-        bstore_line(S, F.W, F.soW + (unsigned)m * lineT, w);
+        fmt.solve(in, y, w);
+        fmt.store_w(m, w);
 #pragma unroll
         for (int s = 0; s < EPL; ++s) prev[s] = w[s];
     };
     auto upper_step = [&](int m, const LineIn<T, EPL> &in) {
 #pragma unroll
         for (int s = 0; s < EPL; ++s) y[s] = in.f[s] * prev[s];
-        line_solve(G, S, in, y, w);
+        fmt.solve(in, y, w);
 #pragma unroll
         for (int s = 0; s < EPL; ++s) w[s] = in.w[s] - w[s];
-        pol.out(m, S, w, in);
+        pol.out(m, fmt, w, in);
 #pragma unroll
         for (int s = 0; s < EPL; ++s) prev[s] = w[s];
     };
-    // Steps i = 0..count-1 of a chain with two input buffers: the inputs of
-    // step i+1 are issued before step i runs.  With `tail`, the inputs of step
-    // `count` are issued too and left in A; with `pre`, those of step 0 are
-    // already in A.
+    // Steps i = 0..count-1 of a chain.  DEPTH 2: three rotating input buffers,
+    // the inputs of steps i+1 and i+2 are in flight while step i runs; DEPTH 1:
+    // two buffers, one step ahead.  With `tail`, the inputs of step `count` are
+    // issued too and left in A; with `pre`, those of step 0 are already in A.
     auto chain = [&](int count, bool tail, bool pre, auto &&load, auto &&step) {
         const int nl = count + (tail ? 1 : 0);
         if (nl > 0 && !pre) load(0, A);
-        int i = 0;
-        for (; i + 1 < count; i += 2) {
-            load(i + 1, B);
-            step(i, A);
-            if (i + 2 < nl) load(i + 2, A);
-            step(i + 1, B);
-        }
-        if (i < count) {
-            if (i + 1 < nl) load(i + 1, B);
-            step(i, A);
-            if (tail) A = B;
+        if constexpr (DEPTH == 2) {
+            if (nl > 1) load(1, B);
+            int i = 0;
+            for (; i + 2 < count; i += 3) {
+                load(i + 2, C);
+                step(i, A);
+                if (i + 3 < nl) load(i + 3, A);
+                step(i + 1, B);
+                if (i + 4 < nl) load(i + 4, B);
+                step(i + 2, C);
+            }
+            const int rest = count - i;  // 0, 1 or 2 steps left, in A then B
+            if (rest >= 1) {
+                if (i + 2 < nl) load(i + 2, C);
+                step(i, A);
+            }
+            if (rest == 2) step(i + 1, B);
+            if (tail) {  // the inputs of step `count` are in A, B or C
+                if (rest == 1) A = B;
+                else if (rest == 2) A = C;
+            }
+        } else {
+            int i = 0;
+            for (; i + 1 < count; i += 2) {
+                load(i + 1, B);
+                step(i, A);
+                if (i + 2 < nl) load(i + 2, A);
+                step(i + 1, B);
+            }
+            if (i < count) {
+                if (i + 1 < nl) load(i + 1, B);
+                step(i, A);
+                if (tail) A = B;
+            }
         }
     };
 
@@ -440,8 +606,8 @@ __device__ void plane_solve(int nx, int ny, const PlaneFac<T> &F, Pol &pol,
         chain(j2, true, false,
               [&](int i, LineIn<T, EPL> &in) { load_lower(i, i - 1, in); },
               [&](int i, const LineIn<T, EPL> &in) { lower_step(i, in); });
-        pol.load_out(j2, S, A);
-        if (j2 < ny - 1) bload_line(S, F.f2, F.soT + (unsigned)j2 * lineT, fhi);
+        pol.load_out(j2, fmt, A);
+        if (j2 < ny - 1) fmt.load_f(j2, fhi);
         else zero_line(fhi);
     } else if (wv == 1) {
         // lines ny-1..j2+1 downward (line m couples to m+1 through f2 line m)
@@ -460,8 +626,8 @@ __device__ void plane_solve(int nx, int ny, const PlaneFac<T> &F, Pol &pol,
 #pragma unroll
         for (int s = 0; s < EPL; ++s)
             y[s] = pol.rhs(A, s) - A.f[s] * prev[s] - fhi[s] * lds[64 * EPL + lane * EPL + s];
-        line_solve(G, S, A, y, w);
-        pol.out(j2, S, w, A);
+        fmt.solve(A, y, w);
+        pol.out(j2, fmt, w, A);
 #pragma unroll
         for (int s = 0; s < EPL; ++s) {
             prev[s] = w[s];
@@ -491,6 +657,12 @@ __device__ void plane_solve(int nx, int ny, const PlaneFac<T> &F, Pol &pol,
     }
 }
 
+// Prefetch depth of the apply sweeps: two lines ahead while the three input
+// buffers fit the register file (float up to 8 and double up to 4 elements per
+// lane), else one.
+template <typename T, int EPL>
+constexpr int kApplyDepth = (sizeof(T) * EPL <= 32) ? 2 : 1;
+
 // Wave-level sum (fixed butterfly order) of a double.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -499,28 +671,30 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// Level 3: the apply z = B^{-1} r as three launches.
+// Level 3: the apply z = B^{-1} r as three launches, on the packed layout.
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__device__ __forceinline__ PlaneFac<T> plane_fac(const ApplyArgs<T> &a, long long pk, rsrc_t W,
-                                                 unsigned soW) {
-    PlaneFac<T> F;
-    F.e1 = make_rsrc(a.e1);
-    F.mv = make_rsrc(a.mv);
-    F.f2 = make_rsrc(a.f2);
+template <typename T, int EPL>
+__device__ __forceinline__ PackFmt<T, EPL> pack_fmt(const ApplyArgs<T> &a, int k, rsrc_t W,
+                                                    unsigned soW) {
+    PackFmt<T, EPL> F(a.nx);
+    F.mv = make_rsrc(a.pmv);
+    F.a = make_rsrc(a.pa);
+    F.u = make_rsrc(a.pu);
+    F.f2 = make_rsrc(a.pf2);
     F.W = W;
-    F.mv64 = a.mv64 + pk;
-    F.soT = (unsigned)pk * (unsigned)sizeof(T);
+    F.tw = a.tw + 4LL * k * a.ny;
+    F.soT = (unsigned)k * (unsigned)a.ny * F.lineB;
     F.soW = soW;
     return F;
 }
 
+// r of line m (natural layout, FP64) into d0.
 template <typename T, int EPL>
-__device__ __forceinline__ void load_r(const Slots<EPL> &S, rsrc_t r, unsigned so8,
+__device__ __forceinline__ void load_r(const PackFmt<T, EPL> &F, rsrc_t r, unsigned so8,
                                        double (&v)[EPL]) {
 #pragma unroll
-    for (int s = 0; s < EPL; ++s) v[s] = bload((double *)nullptr, r, S.o8[s], so8);
+    for (int s = 0; s < EPL; ++s) v[s] = bload((double *)nullptr, r, F.S.o8[s], so8);
 }
 
 // Lower level-3 step of plane k: rhs = r_k - g3 * z_kn (kn = the finished
@@ -528,17 +702,17 @@ __device__ __forceinline__ void load_r(const Slots<EPL> &S, rsrc_t r, unsigned s
 template <typename T, int EPL>
 struct PolLower {
     rsrc_t r, g3, Z;
-    unsigned so8k;  // byte offset of plane k in r (FP64)
-    unsigned soTk;  // byte offset of plane k in Z
-    unsigned soTc;  // byte offset of the coupling plane min(k, kn) in g3
-    unsigned soTn;  // byte offset of plane kn in Z
-    unsigned lineT, line8;
+    unsigned so8k;  // byte offset of plane k in r (natural FP64)
+    unsigned soPk;  // byte offset of plane k in the packed arrays
+    unsigned soPc;  // byte offset of the coupling plane min(k, kn) in packed g3
+    unsigned soPn;  // byte offset of plane kn in packed Z
+    unsigned line8;
     bool has;
-    __device__ void load_rhs(int m, const Slots<EPL> &S, LineIn<T, EPL> &in) const {
-        load_r<T>(S, r, so8k + m * line8, in.d0);
+    __device__ void load_rhs(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
+        load_r(F, r, so8k + m * line8, in.d0);
         if (has) {
-            bload_line(S, g3, soTc + m * lineT, in.a0);
-            bload_line(S, Z, soTn + m * lineT, in.a1);
+            vload(g3, F.laneB, soPc + m * F.lineB, in.a0);
+            vload(Z, F.laneB, soPn + m * F.lineB, in.a1);
         }
     }
     __device__ T rhs(const LineIn<T, EPL> &in, int s) const {
@@ -546,9 +720,10 @@ struct PolLower {
         if (has) v -= in.a0[s] * in.a1[s];
         return v;
     }
-    __device__ void load_out(int, const Slots<EPL> &, LineIn<T, EPL> &) const {}
-    __device__ void out(int m, const Slots<EPL> &S, const T (&x)[EPL], const LineIn<T, EPL> &) {
-        bstore_line(S, Z, soTk + m * lineT, x);
+    __device__ void load_out(int, const PackFmt<T, EPL> &, LineIn<T, EPL> &) const {}
+    __device__ void out(int m, const PackFmt<T, EPL> &F, const T (&x)[EPL],
+                        const LineIn<T, EPL> &) {
+        vstore(Z, F.laneB, soPk + m * F.lineB, x);
     }
 };
 
@@ -556,19 +731,19 @@ struct PolLower {
 template <typename T, int EPL>
 struct PolTwist {
     rsrc_t r, g3, Z, zout;
-    unsigned so8k, soTk, soTlo, soThi;  // plane k, plane k-1 and plane k+1 (Z, g3)
-    unsigned lineT, line8;
-    bool lo_nb, hi_nb, copy64;
+    unsigned so8k, soPk, soPlo, soPhi;  // plane k, plane k-1 and plane k+1 (packed Z, g3)
+    unsigned line8;
+    bool lo_nb, hi_nb;
     double acc;
-    __device__ void load_rhs(int m, const Slots<EPL> &S, LineIn<T, EPL> &in) const {
-        load_r<T>(S, r, so8k + m * line8, in.d0);
+    __device__ void load_rhs(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
+        load_r(F, r, so8k + m * line8, in.d0);
         if (lo_nb) {
-            bload_line(S, g3, soTlo + m * lineT, in.a0);
-            bload_line(S, Z, soTlo + m * lineT, in.a1);
+            vload(g3, F.laneB, soPlo + m * F.lineB, in.a0);
+            vload(Z, F.laneB, soPlo + m * F.lineB, in.a1);
         }
         if (hi_nb) {
-            bload_line(S, g3, soTk + m * lineT, in.a2);
-            bload_line(S, Z, soThi + m * lineT, in.a3);
+            vload(g3, F.laneB, soPk + m * F.lineB, in.a2);
+            vload(Z, F.laneB, soPhi + m * F.lineB, in.a3);
         }
     }
     __device__ T rhs(const LineIn<T, EPL> &in, int s) const {
@@ -577,18 +752,19 @@ struct PolTwist {
         if (hi_nb) v -= in.a2[s] * in.a3[s];
         return v;
     }
-    __device__ void load_out(int m, const Slots<EPL> &S, LineIn<T, EPL> &in) const {
-        load_r<T>(S, r, so8k + m * line8, in.d0);
+    __device__ void load_out(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
+        load_r(F, r, so8k + m * line8, in.d0);
     }
-    __device__ void out(int m, const Slots<EPL> &S, const T (&x)[EPL], const LineIn<T, EPL> &in) {
-        bstore_line(S, Z, soTk + m * lineT, x);
+    __device__ void out(int m, const PackFmt<T, EPL> &F, const T (&x)[EPL],
+                        const LineIn<T, EPL> &in) {
+        vstore(Z, F.laneB, soPk + m * F.lineB, x);
         double xd[EPL];
 #pragma unroll
         for (int s = 0; s < EPL; ++s) {
             xd[s] = (double)x[s];
-            acc += S.valid(s) ? in.d0[s] * xd[s] : 0.0;
+            acc += in.d0[s] * xd[s];  // both 0 on unused slots
         }
-        if (copy64) bstore_line(S, zout, so8k + m * line8, xd);
+        bstore_line(F.S, zout, so8k + m * line8, xd);
     }
 };
 
@@ -597,66 +773,57 @@ struct PolTwist {
 template <typename T, int EPL>
 struct PolUpper {
     rsrc_t r, g3, Z, zout;
-    unsigned so8k, soTk, soTc, soTn;
-    unsigned lineT, line8;
-    bool copy64;
+    unsigned so8k, soPk, soPc, soPn;
+    unsigned line8;
     double acc;
-    __device__ void load_rhs(int m, const Slots<EPL> &S, LineIn<T, EPL> &in) const {
-        bload_line(S, g3, soTc + m * lineT, in.a0);
-        bload_line(S, Z, soTn + m * lineT, in.a1);
+    __device__ void load_rhs(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
+        vload(g3, F.laneB, soPc + m * F.lineB, in.a0);
+        vload(Z, F.laneB, soPn + m * F.lineB, in.a1);
     }
     __device__ T rhs(const LineIn<T, EPL> &in, int s) const { return in.a0[s] * in.a1[s]; }
-    __device__ void load_out(int m, const Slots<EPL> &S, LineIn<T, EPL> &in) const {
-        bload_line(S, Z, soTk + m * lineT, in.a2);
-        load_r<T>(S, r, so8k + m * line8, in.d0);
+    __device__ void load_out(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
+        vload(Z, F.laneB, soPk + m * F.lineB, in.a2);
+        load_r(F, r, so8k + m * line8, in.d0);
     }
-    __device__ void out(int m, const Slots<EPL> &S, const T (&cv)[EPL], const LineIn<T, EPL> &in) {
+    __device__ void out(int m, const PackFmt<T, EPL> &F, const T (&cv)[EPL],
+                        const LineIn<T, EPL> &in) {
         T xv[EPL];
         double xd[EPL];
 #pragma unroll
         for (int s = 0; s < EPL; ++s) {
             xv[s] = in.a2[s] - cv[s];
             xd[s] = (double)xv[s];
-            acc += S.valid(s) ? in.d0[s] * xd[s] : 0.0;
+            acc += in.d0[s] * xd[s];
         }
-        bstore_line(S, Z, soTk + m * lineT, xv);
-        if (copy64) bstore_line(S, zout, so8k + m * line8, xd);
+        vstore(Z, F.laneB, soPk + m * F.lineB, xv);
+        bstore_line(F.S, zout, so8k + m * line8, xd);
     }
 };
-
-template <typename T>
-__device__ __forceinline__ bool has_fp64_copy(const ApplyArgs<T> &a) {
-    return (const void *)a.zout != (const void *)a.Z;
-}
 
 // Lower level-3 sweep of one half: block 0 takes planes 0..j3-1 upward, block 1
 // planes nz-1..j3+1 downward; z_k = Pt_k^{-1}(r_k - g3 * z_{k-+1}) into Z.
 template <typename T, int EPL>
 __global__ void __launch_bounds__(kApplyThreads) k_apply_lower(ApplyArgs<T> a) {
     __shared__ T lds[2 * 64 * EPL];
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const long long nxy = (long long)nx * ny;
+    const int ny = a.ny, nz = a.nz;
     const int j3 = (nz - 1) / 2;
     const int h = blockIdx.x;
     const int dk = h == 0 ? 1 : -1;
+    const unsigned planeP = (unsigned)ny * 64u * EPL * (unsigned)sizeof(T);
     PolLower<T, EPL> pol;
     pol.r = make_rsrc(a.r);
-    pol.g3 = make_rsrc(a.g3);
+    pol.g3 = make_rsrc(a.pg3);
     pol.Z = make_rsrc(a.Z);
-    pol.lineT = (unsigned)nx * sizeof(T);
-    pol.line8 = (unsigned)nx * 8u;
+    pol.line8 = (unsigned)a.nx * 8u;
     for (int k = h == 0 ? 0 : nz - 1; h == 0 ? k < j3 : k > j3; k += dk) {
-        const long long pk = k * nxy;
         const int kn = k - dk;  // neighbour already solved (toward the chain start)
         pol.has = (kn >= 0 && kn < nz);
-        const long long pc = pol.has ? (k < kn ? k : kn) * nxy : 0;
-        const long long pn = pol.has ? kn * nxy : 0;
-        pol.so8k = (unsigned)(pk * 8);
-        pol.soTk = (unsigned)(pk * (long long)sizeof(T));
-        pol.soTc = (unsigned)(pc * (long long)sizeof(T));
-        pol.soTn = (unsigned)(pn * (long long)sizeof(T));
-        const PlaneFac<T> F = plane_fac(a, pk, pol.Z, pol.soTk);
-        plane_solve<T, EPL>(nx, ny, F, pol, lds);
+        pol.so8k = (unsigned)k * (unsigned)ny * pol.line8;
+        pol.soPk = (unsigned)k * planeP;
+        pol.soPc = pol.has ? (unsigned)(k < kn ? k : kn) * planeP : 0u;
+        pol.soPn = pol.has ? (unsigned)kn * planeP : 0u;
+        const PackFmt<T, EPL> F = pack_fmt<T, EPL>(a, k, pol.Z, pol.soPk);
+        plane_solve<kApplyDepth<T, EPL>>(ny, F, pol, lds);
     }
 }
 
@@ -664,27 +831,24 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply_lower(ApplyArgs<T> a) {
 template <typename T, int EPL>
 __global__ void __launch_bounds__(kApplyThreads) k_apply_twist(ApplyArgs<T> a) {
     __shared__ T lds[2 * 64 * EPL];
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const long long nxy = (long long)nx * ny;
+    const int ny = a.ny, nz = a.nz;
     const int k = (nz - 1) / 2;
-    const long long pk = k * nxy;
+    const unsigned planeP = (unsigned)ny * 64u * EPL * (unsigned)sizeof(T);
     PolTwist<T, EPL> pol;
     pol.r = make_rsrc(a.r);
-    pol.g3 = make_rsrc(a.g3);
+    pol.g3 = make_rsrc(a.pg3);
     pol.Z = make_rsrc(a.Z);
     pol.zout = make_rsrc(a.zout);
-    pol.copy64 = has_fp64_copy(a);
     pol.lo_nb = k > 0;
     pol.hi_nb = k < nz - 1;
-    pol.lineT = (unsigned)nx * sizeof(T);
-    pol.line8 = (unsigned)nx * 8u;
-    pol.so8k = (unsigned)(pk * 8);
-    pol.soTk = (unsigned)(pk * (long long)sizeof(T));
-    pol.soTlo = pol.lo_nb ? (unsigned)((pk - nxy) * (long long)sizeof(T)) : 0u;
-    pol.soThi = pol.hi_nb ? (unsigned)((pk + nxy) * (long long)sizeof(T)) : 0u;
+    pol.line8 = (unsigned)a.nx * 8u;
+    pol.so8k = (unsigned)k * (unsigned)ny * pol.line8;
+    pol.soPk = (unsigned)k * planeP;
+    pol.soPlo = pol.lo_nb ? (unsigned)(k - 1) * planeP : 0u;
+    pol.soPhi = pol.hi_nb ? (unsigned)(k + 1) * planeP : 0u;
     pol.acc = 0.0;
-    const PlaneFac<T> F = plane_fac(a, pk, pol.Z, pol.soTk);
-    plane_solve<T, EPL>(nx, ny, F, pol, lds);
+    const PackFmt<T, EPL> F = pack_fmt<T, EPL>(a, k, pol.Z, pol.soPk);
+    plane_solve<kApplyDepth<T, EPL>>(ny, F, pol, lds);
     if (a.partials) {
         const double sum = wave_sum(pol.acc);
         if ((threadIdx.x & 63) == 0) a.partials[threadIdx.x >> 6] = sum;
@@ -692,39 +856,84 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply_twist(ApplyArgs<T> a) {
 }
 
 // Upper level-3 sweep: block 0 takes planes j3-1..0, block 1 planes j3+1..nz-1;
-// x_k = z_k - Pt_k^{-1}(g3 * x_{k+-1}), written over Z (and zout).
+// x_k = z_k - Pt_k^{-1}(g3 * x_{k+-1}), written over Z and to the FP64 output.
 template <typename T, int EPL>
 __global__ void __launch_bounds__(kApplyThreads) k_apply_upper(ApplyArgs<T> a) {
     __shared__ T lds[2 * 64 * EPL];
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const long long nxy = (long long)nx * ny;
+    const int ny = a.ny, nz = a.nz;
     const int j3 = (nz - 1) / 2;
     const int h = blockIdx.x;
     const int dk = h == 0 ? -1 : 1;
+    const unsigned planeP = (unsigned)ny * 64u * EPL * (unsigned)sizeof(T);
     const rsrc_t W = make_rsrc(a.scratch);
-    const unsigned soW = (unsigned)(h * nxy * (long long)sizeof(T));
     PolUpper<T, EPL> pol;
     pol.r = make_rsrc(a.r);
-    pol.g3 = make_rsrc(a.g3);
+    pol.g3 = make_rsrc(a.pg3);
     pol.Z = make_rsrc(a.Z);
     pol.zout = make_rsrc(a.zout);
-    pol.copy64 = has_fp64_copy(a);
-    pol.lineT = (unsigned)nx * sizeof(T);
-    pol.line8 = (unsigned)nx * 8u;
+    pol.line8 = (unsigned)a.nx * 8u;
     pol.acc = 0.0;
     for (int k = j3 + dk; k >= 0 && k < nz; k += dk) {
-        const long long pk = k * nxy;
         const int kn = k - dk;  // final neighbour, toward the twist plane
-        pol.so8k = (unsigned)(pk * 8);
-        pol.soTk = (unsigned)(pk * (long long)sizeof(T));
-        pol.soTc = (unsigned)((k < kn ? k : kn) * nxy * (long long)sizeof(T));
-        pol.soTn = (unsigned)(kn * nxy * (long long)sizeof(T));
-        const PlaneFac<T> F = plane_fac(a, pk, W, soW);
-        plane_solve<T, EPL>(nx, ny, F, pol, lds);
+        pol.so8k = (unsigned)k * (unsigned)ny * pol.line8;
+        pol.soPk = (unsigned)k * planeP;
+        pol.soPc = (unsigned)(k < kn ? k : kn) * planeP;
+        pol.soPn = (unsigned)kn * planeP;
+        const PackFmt<T, EPL> F = pack_fmt<T, EPL>(a, k, W, (unsigned)h * planeP);
+        plane_solve<kApplyDepth<T, EPL>>(ny, F, pol, lds);
     }
     if (a.partials) {
         const double sum = wave_sum(pol.acc);
         if ((threadIdx.x & 63) == 0) a.partials[2 + 2 * h + (threadIdx.x >> 6)] = sum;
+    }
+}
+
+// Packing of the factors into the apply's layout (one thread per packed slot):
+// 1/M, a = -cp/M, u = -cn/M (0 at the twist row), f2 and g3 at the slot's
+// element, identity values on unused slots, and the FP64 twist record.
+template <typename T, int EPL>
+__global__ void __launch_bounds__(256) k_pack(PackArgs<T> p) {
+    const long long nslot = 64LL * EPL;
+    const long long total = (long long)p.nlines * nslot;
+    const int n = p.nx;
+    const int ca = (n + 1) / 2, cb = n - ca, j = ca - 1;
+    for (long long q = blockIdx.x * 256LL + threadIdx.x; q < total; q += (long long)gridDim.x * 256) {
+        const long long line = q / nslot;
+        const int slot = (int)(q - line * nslot);
+        const int lane = slot / EPL, s = slot - lane * EPL;
+        const int half = lane >> 5, hl = lane & 31;
+        const int cnt = half ? cb : ca;
+        const int c = hl * EPL + s - (32 * EPL - cnt);
+        const long long base = line * n;
+        T mv = T(0), av = T(1), uv = T(0), fv = T(0), gv = T(0);
+        if (c >= 0) {
+            const int e = half ? n - 1 - c : c;
+            const double m = p.mv[base + e];
+            double cp, cn;
+            if (half == 0) {
+                cp = e > 0 ? p.e1[base + e - 1] : 0.0;
+                cn = e == j ? 0.0 : p.e1[base + e];
+            } else {
+                cp = p.e1[base + e];
+                cn = p.e1[base + e - 1];
+            }
+            mv = (T)m;
+            av = (T)(-m * cp);
+            uv = (T)(-m * cn);
+            fv = (T)p.f2[base + e];
+            gv = (T)p.g3[base + e];
+        }
+        p.pmv[q] = mv;
+        p.pa[q] = av;
+        p.pu[q] = uv;
+        p.pf2[q] = fv;
+        p.pg3[q] = gv;
+        if (slot == 0) {
+            p.tw[4 * line + 0] = p.mv[base + j];
+            p.tw[4 * line + 1] = j > 0 ? p.e1[base + j - 1] : 0.0;
+            p.tw[4 * line + 2] = j < n - 1 ? p.e1[base + j] : 0.0;
+            p.tw[4 * line + 3] = 0.0;
+        }
     }
 }
 
@@ -740,19 +949,20 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ double tval(const double *t, long long p) { return t ? t[p] : 1.0; }
 
-// Plain plane solve x = Pt^{-1} y with y and x plane-sized buffers.
+// Plain plane solve x = Pt^{-1} y with y and x plane-sized buffers (natural layout).
 template <int EPL>
 struct PolPlain {
     rsrc_t y, x;
     unsigned line8;
-    __device__ void load_rhs(int m, const Slots<EPL> &S, LineIn<double, EPL> &in) const {
-        bload_line(S, y, m * line8, in.a0);
+    __device__ void load_rhs(int m, const NatFmt<double, EPL> &F,
+                             LineIn<double, EPL> &in) const {
+        bload_line(F.S, y, m * line8, in.a0);
     }
     __device__ double rhs(const LineIn<double, EPL> &in, int s) const { return in.a0[s]; }
-    __device__ void load_out(int, const Slots<EPL> &, LineIn<double, EPL> &) const {}
-    __device__ void out(int m, const Slots<EPL> &S, const double (&v)[EPL],
+    __device__ void load_out(int, const NatFmt<double, EPL> &, LineIn<double, EPL> &) const {}
+    __device__ void out(int m, const NatFmt<double, EPL> &F, const double (&v)[EPL],
                         const LineIn<double, EPL> &) {
-        bstore_line(S, x, m * line8, v);
+        bstore_line(F.S, x, m * line8, v);
     }
 };
 
@@ -765,7 +975,6 @@ __device__ void line_setup(const SetupArgs &a, long long pk, int m, int nnb, int
                            double *sh /* per-wave LDS: 5 * nx doubles */) {
     const int nx = a.nx;
     const LineGeom G(nx, EPL);
-    const Slots<EPL> S(G);
     const int lane = threadIdx.x & 63;
     double *sd = sh, *se = sh + nx, *sM = sh + 2 * nx, *sg = sh + 3 * nx, *sp = sh + 4 * nx;
     const long long lm = pk + (long long)m * nx;
@@ -784,13 +993,14 @@ __device__ void line_setup(const SetupArgs &a, long long pk, int m, int nnb, int
             v[s] = G.ok(c) ? phi[s] * tval(a.t, lm + G.elem(c)) : 0.0;
         }
         LineIn<double, EPL> C;
-        PlaneFac<double> F;
+        NatFmt<double, EPL> F(nx);
         F.e1 = make_rsrc(a.e1 + ln);
         F.mv = make_rsrc(a.mv + ln);
         F.mv64 = a.mv + ln;
         F.soT = 0;
-        load_coef(S, G, F, 0, C);
-        line_solve(G, S, C, v, zl);
+        F.lineB = (unsigned)nx * 8u;
+        F.load_coef(0, C);
+        F.solve(C, v, zl);
         load_line(G, a.dT + ln, dTn);
         load_line(G, a.e1 + ln, en);
 #pragma unroll
@@ -922,7 +1132,7 @@ __device__ void plane_setup(const SetupArgs &a, int k, int nnb, int nb0, int nb1
         pol.y = make_rsrc(wbuf);
         pol.x = make_rsrc(zbuf);
         pol.line8 = (unsigned)nx * 8u;
-        PlaneFac<double> F;
+        NatFmt<double, EPL> F(nx);
         F.e1 = make_rsrc(a.e1 + pn);
         F.mv = make_rsrc(a.mv + pn);
         F.f2 = make_rsrc(a.f2 + pn);
@@ -930,7 +1140,8 @@ __device__ void plane_setup(const SetupArgs &a, int k, int nnb, int nb0, int nb1
         F.mv64 = a.mv + pn;
         F.soT = 0;
         F.soW = 0;
-        plane_solve<double, EPL>(nx, ny, F, pol, lds_x);
+        F.lineB = (unsigned)nx * 8u;
+        plane_solve<1>(ny, F, pol, lds_x);
         __syncthreads();
         const double *dPn = a.dP + pn, *xPn = a.xP + pn, *yPn = a.f2 + pn;
         for (long long u = threadIdx.x; u < nxy; u += blockDim.x) {
@@ -1010,6 +1221,15 @@ hipError_t apply_impl(const ApplyArgs<T> &a, hipStream_t s, hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[2], s);
     hipLaunchKernelGGL((k_apply_upper<T, EPL>), dim3(2), dim3(kApplyThreads), 0, s, a);
     if (ev) (void)hipEventRecord(ev[3], s);
+    return hipGetLastError();
+}
+
+template <typename T, int EPL>
+hipError_t pack_impl(const PackArgs<T> &p, hipStream_t s) {
+    const long long total = (long long)p.nlines * 64 * EPL;
+    long long nb = (total + 255) / 256;
+    if (nb > 65535) nb = 65535;
+    hipLaunchKernelGGL((k_pack<T, EPL>), dim3((unsigned)nb), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 

@@ -53,7 +53,8 @@ def test_workspace_bytes(L):
     assert L.ntd_workspace_bytes(2048, 1, 1, 0) == 0          # beyond the longest line
     a = L.ntd_workspace_bytes(32, 32, 32, 0)
     b = L.ntd_workspace_bytes(32, 32, 32, 1)
-    assert a > 14 * 8 * 32 ** 3 and b > a                      # 14 FP64 vectors, + float copies
+    assert a > 14 * 8 * 32 ** 3 and b > 14 * 8 * 32 ** 3       # 14 FP64 vectors + packed factors
+    assert b < a                                               # packed factors in float
     assert L.ntd_workspace_bytes(1024, 2, 2, 1) > 0
 
 

@@ -143,6 +143,26 @@ def test_apply_mixed_within_1e5(shape, kind, schur):
     assert np.linalg.norm(z - want) <= 1e-5 * np.linalg.norm(want)
 
 
+# one shape per supported elements-per-lane count (line length nx -> EPL):
+# 32 -> 1, 65 -> 2, 150 -> 3, 256 -> 4, 300 -> 5, 350 -> 6, 420 -> 7, 512 -> 8,
+# 600 -> 10, 700 -> 12, 900 -> 14, 1024 -> 16
+EPL_SHAPES = [(3, 5, 32), (3, 4, 65), (2, 5, 150), (3, 4, 256), (2, 3, 300), (2, 3, 350),
+              (2, 3, 420), (2, 2, 512), (2, 2, 600), (2, 2, 700), (2, 2, 900), (2, 2, 1024)]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+@pytest.mark.parametrize("shape", EPL_SHAPES)
+def test_apply_every_lane_width(shape, prec, tol):
+    kappa, bc = case(shape, "rand", seed=17)
+    F = O.setup(O.assemble(kappa, bc), mode="diag")
+    S = ntd().Solver(G(kappa), bc, prec=prec, schur="diag")
+    S.load_factors(G(F["e1"]), G(F["M"]), G(F["f2"]))
+    r = np.random.default_rng(19).uniform(-1, 1, shape)
+    z = C(S.apply(G(r)))
+    want = O.apply(F, r)
+    assert np.linalg.norm(z - want) <= tol * np.linalg.norm(want)
+
+
 @pytest.mark.parametrize("schur", ["newton", "diag"])
 def test_filter_property_on_gpu(schur):
     shape = (40, 36, 48)
