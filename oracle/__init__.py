@@ -59,8 +59,14 @@ def _L():
         lib.orc_line_solve.restype = None
         lib.orc_line_pivots.argtypes = [i, P, P, P]
         lib.orc_line_pivots.restype = i
-        lib.orc_pcg.argtypes = [i, i, i, P, P, P, P, P, P, P, P, P, d, i,
+        lib.orc_pcg.argtypes = [i, i, i, P, P, P, P, P, P, P, P, i, P, P, d, i,
                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), P]
+        lib.orc_ilu0.argtypes = [i, i, i, P, P, P, P, i, P]
+        lib.orc_ilu0.restype = i
+        lib.orc_ilu0_apply.argtypes = [i, i, i, P, P, P, P, i, P, P]
+        lib.orc_ilu0_apply.restype = None
+        lib.orc_combo_apply.argtypes = [i, i, i, P, P, P, P, P, P, P, P, i, P, P]
+        lib.orc_combo_apply.restype = i
         lib.orc_pcg.restype = i
         _lib = lib
     return _lib
@@ -162,8 +168,44 @@ def line_solve(e, M, y):
     return x
 
 
-def pcg(bands, F, b, tol=1e-8, maxit=200):
-    """PCG with B; returns (x, iters, true relres, status, residual history)."""
+def ilu0(bands, nblocks=2, raise_on_error=True):
+    """Diagonal dt of ILU(0) of blkD(A) (nblocks = 2, split at M = floor(N/2)) or of A."""
+    d, ax, ay, az = [_f64(a) for a in bands]
+    nz, ny, nx = d.shape
+    dt = np.empty_like(d)
+    st = _L().orc_ilu0(nx, ny, nz, _ptr(d), _ptr(ax), _ptr(ay), _ptr(az), int(nblocks), _ptr(dt))
+    if st != OK and raise_on_error:
+        raise OracleError(st, "orc_ilu0")
+    return dt, st
+
+
+def ilu0_apply(bands, dt, r, nblocks=2):
+    d, ax, ay, az = [_f64(a) for a in bands]
+    nz, ny, nx = d.shape
+    r = _f64(r).reshape(d.shape)
+    z = np.empty_like(d)
+    _L().orc_ilu0_apply(nx, ny, nz, _ptr(ax), _ptr(ay), _ptr(az), _ptr(_f64(dt)), int(nblocks),
+                        _ptr(r), _ptr(z))
+    return z
+
+
+def combo_apply(bands, F, dt, r, nblocks=2):
+    """z = B^{-1} r + B_ILU^{-1} r - B^{-1} A B_ILU^{-1} r (eq. com)."""
+    d, ax, ay, az = [_f64(a) for a in bands]
+    nz, ny, nx = d.shape
+    r = _f64(r).reshape(d.shape)
+    z = np.empty_like(d)
+    st = _L().orc_combo_apply(nx, ny, nz, _ptr(d), _ptr(ax), _ptr(ay), _ptr(az), _ptr(F["e1"]),
+                              _ptr(F["M"]), _ptr(F["f2"]), _ptr(_f64(dt)), int(nblocks), _ptr(r),
+                              _ptr(z))
+    if st != OK:
+        raise OracleError(st, "orc_combo_apply")
+    return z
+
+
+def pcg(bands, F, b, tol=1e-8, maxit=200, dt=None, nblocks=2):
+    """PCG with B (dt None) or with the combination of B and ILU(0) (dt given);
+    returns (x, iters, true relres, status, residual history)."""
     d, ax, ay, az = [_f64(a) for a in bands]
     nz, ny, nx = d.shape
     b = _f64(b).reshape(d.shape)
@@ -171,7 +213,8 @@ def pcg(bands, F, b, tol=1e-8, maxit=200):
     it = ctypes.c_int(0)
     rr = ctypes.c_double(0.0)
     hist = np.zeros(maxit + 1)
+    dtp = None if dt is None else _f64(dt)
     st = _L().orc_pcg(nx, ny, nz, _ptr(d), _ptr(ax), _ptr(ay), _ptr(az), _ptr(F["e1"]),
-                      _ptr(F["M"]), _ptr(F["f2"]), _ptr(b), _ptr(x), float(tol), int(maxit),
-                      ctypes.byref(it), ctypes.byref(rr), _ptr(hist))
+                      _ptr(F["M"]), _ptr(F["f2"]), _ptr(dtp), int(nblocks), _ptr(b), _ptr(x),
+                      float(tol), int(maxit), ctypes.byref(it), ctypes.byref(rr), _ptr(hist))
     return x, it.value, rr.value, st, hist[: it.value]

@@ -495,15 +495,108 @@ int orc_setup(int nx, int ny, int nz, const double *d, const double *ax, const d
 }
 
 /* ------------------------------------------------------------------------- */
+/* ILU(0) smoother and the combination preconditioner (Sec. 3, "Smoothing     */
+/* high frequency components of error", eq. com, and "Parallel Solve with     */
+/* Preconditioner"): ILU(0) of the block-diagonal approximation               */
+/* blkD(A(1:M,1:M), A(M+1:N,M+1:N)), M = floor(N/2) (nblocks = 2), or of A    */
+/* itself (nblocks = 1).  For the 7-point pattern ILU(0) creates no fill      */
+/* inside the pattern, so only the diagonal changes:                          */
+/*   dt_p = a_pp - sum over kept lower neighbours q of a_pq^2 / dt_q,         */
+/* and B_ILU = (Dt + L) Dt^{-1} (Dt + U) with L, U the kept strict parts.     */
+/* ------------------------------------------------------------------------- */
+
+/* Is the coupling between rows p < q kept by the block-diagonal split? */
+static int ilu_kept(long p, long q, long M, int nblocks)
+{
+    return nblocks == 1 || !(p < M && q >= M);
+}
+
+int orc_ilu0(int nx, int ny, int nz, const double *d, const double *ax, const double *ay,
+             const double *az, int nblocks, double *dt)
+{
+    if (nblocks != 1 && nblocks != 2) return ORC_EINVAL;
+    const long sy = nx, sz = (long)nx * ny, N = sz * nz, M = N / 2;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                long p = i + sy * j + sz * k;
+                double v = d[p];
+                if (i > 0 && ilu_kept(p - 1, p, M, nblocks)) v -= ax[p - 1] * ax[p - 1] / dt[p - 1];
+                if (j > 0 && ilu_kept(p - sy, p, M, nblocks)) v -= ay[p - sy] * ay[p - sy] / dt[p - sy];
+                if (k > 0 && ilu_kept(p - sz, p, M, nblocks)) v -= az[p - sz] * az[p - sz] / dt[p - sz];
+                if (!(v > 0.0) || !isfinite(v)) return ORC_ENOTSPD;
+                dt[p] = v;
+            }
+    return ORC_OK;
+}
+
+/* z = B_ILU^{-1} r: forward sweep (Dt + L) y = r, then (I + Dt^{-1} U) z = y. */
+void orc_ilu0_apply(int nx, int ny, int nz, const double *ax, const double *ay, const double *az,
+                    const double *dt, int nblocks, const double *r, double *z)
+{
+    const long sy = nx, sz = (long)nx * ny, N = sz * nz, M = N / 2;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                long p = i + sy * j + sz * k;
+                double v = r[p];
+                if (i > 0 && ilu_kept(p - 1, p, M, nblocks)) v -= ax[p - 1] * z[p - 1];
+                if (j > 0 && ilu_kept(p - sy, p, M, nblocks)) v -= ay[p - sy] * z[p - sy];
+                if (k > 0 && ilu_kept(p - sz, p, M, nblocks)) v -= az[p - sz] * z[p - sz];
+                z[p] = v / dt[p];
+            }
+    for (int k = nz - 1; k >= 0; --k)
+        for (int j = ny - 1; j >= 0; --j)
+            for (int i = nx - 1; i >= 0; --i) {
+                long p = i + sy * j + sz * k;
+                double v = 0.0;
+                if (i < nx - 1 && ilu_kept(p, p + 1, M, nblocks)) v += ax[p] * z[p + 1];
+                if (j < ny - 1 && ilu_kept(p, p + sy, M, nblocks)) v += ay[p] * z[p + sy];
+                if (k < nz - 1 && ilu_kept(p, p + sz, M, nblocks)) v += az[p] * z[p + sz];
+                z[p] -= v / dt[p];
+            }
+}
+
+/* The combination of eq. com, evaluated as written:
+ * z = B^{-1} r + B_ILU^{-1} r - B^{-1} A B_ILU^{-1} r. */
+int orc_combo_apply(int nx, int ny, int nz, const double *d, const double *ax, const double *ay,
+                    const double *az, const double *e1, const double *M_, const double *f2,
+                    const double *dt, int nblocks, const double *r, double *z)
+{
+    const long N = (long)nx * ny * nz;
+    double *zi = malloc(sizeof(double) * N), *t = malloc(sizeof(double) * N);
+    double *zb = malloc(sizeof(double) * N);
+    if (!zi || !t || !zb) { free(zi); free(t); free(zb); return ORC_ENOMEM; }
+    orc_apply(nx, ny, nz, e1, M_, f2, az, r, z);                  /* B^{-1} r */
+    orc_ilu0_apply(nx, ny, nz, ax, ay, az, dt, nblocks, r, zi);    /* B_ILU^{-1} r */
+    orc_spmv(nx, ny, nz, d, ax, ay, az, zi, t);                   /* A B_ILU^{-1} r */
+    orc_apply(nx, ny, nz, e1, M_, f2, az, t, zb);                 /* B^{-1} A B_ILU^{-1} r */
+    for (long p = 0; p < N; ++p) z[p] = z[p] + zi[p] - zb[p];
+    free(zi); free(t); free(zb);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Preconditioned conjugate gradient (Sec. 1; stopping rule of Sec. 3):       */
 /* x0 = 0, stop when ||r||/||b|| <= tol on the recursively updated residual,  */
 /* then confirm with the true residual ||b - A x||/||b|| (iterate on if it is */
-/* still above tol).  iters counts products with A inside the loop.           */
+/* still above tol).  iters counts products with A inside the loop.  With dt  */
+/* (ILU(0) diagonal, nblocks blocks) the preconditioner is the combination.   */
 /* ------------------------------------------------------------------------- */
+/* Preconditioner of the PCG: B^{-1} (dt == NULL) or the combination (eq. com). */
+static void pcg_precond(int nx, int ny, int nz, const double *d, const double *ax,
+                        const double *ay, const double *az, const double *e1, const double *M,
+                        const double *f2, const double *dt, int nblocks, const double *r,
+                        double *z)
+{
+    if (dt) orc_combo_apply(nx, ny, nz, d, ax, ay, az, e1, M, f2, dt, nblocks, r, z);
+    else orc_apply(nx, ny, nz, e1, M, f2, az, r, z);
+}
+
 int orc_pcg(int nx, int ny, int nz, const double *d, const double *ax, const double *ay,
             const double *az, const double *e1, const double *M, const double *f2,
-            const double *b, double *x, double tol, int maxit, int *iters, double *relres,
-            double *hist)
+            const double *dt, int nblocks, const double *b, double *x, double tol, int maxit,
+            int *iters, double *relres, double *hist)
 {
     const long N = (long)nx * ny * nz;
     double *r = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N);
@@ -514,7 +607,7 @@ int orc_pcg(int nx, int ny, int nz, const double *d, const double *ax, const dou
     for (long i = 0; i < N; ++i) { x[i] = 0.0; r[i] = b[i]; }
     *iters = 0;
     if (bn == 0.0) { *relres = 0.0; goto done; }
-    orc_apply(nx, ny, nz, e1, M, f2, az, r, z);
+    pcg_precond(nx, ny, nz, d, ax, ay, az, e1, M, f2, dt, nblocks, r, z);
     for (long i = 0; i < N; ++i) p[i] = z[i];
     double rho = orc_dot(N, r, z);
     int it = 0;
@@ -534,7 +627,7 @@ int orc_pcg(int nx, int ny, int nz, const double *d, const double *ax, const dou
             double tr = sqrt(orc_dot(N, q, q)) / bn;
             if (tr <= tol) break;
         }
-        orc_apply(nx, ny, nz, e1, M, f2, az, r, z);
+        pcg_precond(nx, ny, nz, d, ax, ay, az, e1, M, f2, dt, nblocks, r, z);
         double rho_new = orc_dot(N, r, z);
         double beta = rho_new / rho;
         rho = rho_new;

@@ -450,3 +450,89 @@ def test_pcg_reports_no_convergence():
     F = O.setup(bands, mode="diag")
     x, it, rr, st, _ = O.pcg(bands, F, W.rhs_uniform(6, 6, 6, 1), 1e-14, 2)
     assert st == O.ENOCONV and it == 2
+
+
+# --------------------------------------------------------------------------
+# ILU(0) smoother and the combination preconditioner (Sec. 3, eq. com)
+# --------------------------------------------------------------------------
+
+def _dense_ilu(bands, dt, nblocks):
+    """B_ILU = (Dt + L) Dt^{-1} (Dt + U) formed densely from the oracle's dt and
+    the kept strict parts of A (couplings across row M = floor(N/2) dropped)."""
+    A = R.dense_from_bands(bands)
+    N = A.shape[0]
+    M = N // 2
+    At = A.copy()
+    if nblocks == 2:
+        At[:M, M:] = 0.0
+        At[M:, :M] = 0.0
+    L = np.tril(At, -1)
+    D = np.diag(dt.ravel())
+    return (D + L) @ np.linalg.inv(D) @ (D + L.T), At
+
+
+@pytest.mark.parametrize("nblocks", [1, 2])
+@pytest.mark.parametrize("shape", [(3, 4, 5), (5, 3, 2), (1, 5, 7), (2, 3, 3)])
+def test_ilu0_matches_matrix_on_its_pattern(shape, nblocks):
+    """The defining property of ILU(0): L D^{-1} U reproduces the (block-diagonal)
+    matrix on every position of its sparsity pattern; fill appears only outside."""
+    bands = O.assemble(rand_kappa(shape, 131), W.BC_Z0_DIRICHLET)
+    dt, st = O.ilu0(bands, nblocks)
+    assert st == 0 and np.all(dt > 0)
+    B, At = _dense_ilu(bands, dt, nblocks)
+    pattern = At != 0
+    np.testing.assert_allclose(B[pattern], At[pattern], rtol=1e-12, atol=1e-12 * np.abs(At).max())
+    if nblocks == 2:
+        M = At.shape[0] // 2
+        assert np.abs(B[:M, M:]).max() == 0.0 and np.abs(B[M:, :M]).max() == 0.0
+    z = O.ilu0_apply(bands, dt, np.ones(shape), nblocks)
+    np.testing.assert_allclose(B @ z.ravel(), np.ones(At.shape[0]), rtol=1e-10, atol=1e-10)
+
+
+def test_ilu0_is_exact_on_a_line():
+    """A tridiagonal matrix has no ILU(0) fill: one block gives B_ILU = A."""
+    bc = np.array([0, 0, 1, 1, 1, 1], dtype=np.int32)
+    kappa = rand_kappa((1, 1, 11), 141)
+    bands = O.assemble(kappa, bc)
+    dt, _ = O.ilu0(bands, 1)
+    r = np.random.default_rng(5).standard_normal((1, 1, 11))
+    A = R.assemble_dense(kappa, bc)
+    np.testing.assert_allclose(O.ilu0_apply(bands, dt, r, 1).ravel(), np.linalg.solve(A, r.ravel()),
+                               rtol=1e-11)
+
+
+@pytest.mark.parametrize("mode", ["newton", "diag"])
+def test_combination_error_propagation(mode):
+    """eq. com is equivalent to I - Bc^{-1} A = (I - B^{-1} A)(I - B_ILU^{-1} A)."""
+    shape = (3, 4, 4)
+    kappa = rand_kappa(shape, 151, contrast=2.0)
+    bands = O.assemble(kappa, W.BC_ALL_DIRICHLET)
+    F = O.setup(bands, mode=mode)
+    dt, _ = O.ilu0(bands, 2)
+    A = R.assemble_dense(kappa, W.BC_ALL_DIRICHLET)
+    N = A.shape[0]
+    Bc = np.zeros((N, N))
+    for c in range(N):
+        e = np.zeros(N)
+        e[c] = 1.0
+        Bc[:, c] = O.combo_apply(bands, F, dt, e.reshape(shape)).ravel()
+    Bi = dense_Binv(F, shape)
+    Bilu, _ = _dense_ilu(bands, dt, 2)
+    I = np.eye(N)
+    lhs = I - Bc @ A
+    rhs = (I - Bi @ A) @ (I - np.linalg.solve(Bilu, A))
+    np.testing.assert_allclose(lhs, rhs, atol=1e-10)
+
+
+def test_pcg_with_combination_matches_dense_solve():
+    shape = (8, 7, 6)
+    kappa = W.kappa_subcubes(6, 7, 8, 161, cubes=2)
+    bands = O.assemble(kappa, W.BC_Z0_DIRICHLET)
+    F = O.setup(bands, mode="newton")
+    dt, _ = O.ilu0(bands, 2)
+    b = W.rhs_uniform(6, 7, 8, 162)
+    x, it, rr, st, _ = O.pcg(bands, F, b, 1e-11, 300, dt=dt)
+    assert st == 0 and rr <= 1e-11
+    A = R.assemble_dense(kappa, W.BC_Z0_DIRICHLET)
+    xr = np.linalg.solve(A, b.ravel())
+    assert np.linalg.norm(x.ravel() - xr) <= 10 * np.linalg.cond(A) * 1e-11 * np.linalg.norm(xr)
