@@ -60,38 +60,54 @@ typedef struct ntd_handle ntd_handle;
 #define NTD_SCHUR_NEWTON 0
 #define NTD_SCHUR_DIAG 1
 
+/* Smoother combined with B (Sec. 3, eq. com): none, or ILU(0) of the
+ * block-diagonal approximation blkD(A(1:M,1:M), A(M+1:N,M+1:N)), M = floor(N/2),
+ * giving the combination Bc^{-1} = B^{-1} + B_ILU^{-1} - B^{-1} A B_ILU^{-1}
+ * (the preconditioner of the paper's experiments, Table 1). */
+#define NTD_SMOOTHER_NONE 0
+#define NTD_SMOOTHER_ILU0 1
+
 /* Largest supported line length nx (one wavefront solves one line).  The
  * grid must also satisfy 8*nx*ny*nz < 2^31 (32-bit byte offsets). */
 #define NTD_MAX_NX 1024
 
-/* Bytes of device workspace that ntd_setup needs for this grid and precision.
- * Returns 0 for invalid sizes. */
-size_t ntd_workspace_bytes(int nx, int ny, int nz, int prec);
+/* Bytes of device workspace that ntd_setup needs for this grid, precision and
+ * smoother.  Returns 0 for invalid arguments. */
+size_t ntd_workspace_bytes(int nx, int ny, int nz, int prec, int smoother);
 
 /* Assemble A from kappa and the face types, then factor B (Sec. 2.1: the
  * level-3 plane recurrence, the level-2 line recurrence of every plane, the
- * level-1 twisted pivots of every line).
+ * level-1 twisted pivots of every line) and, with the ILU(0) smoother, the
+ * block-diagonal ILU(0) (Sec. 3).
  *   kappa     [N] device, finite and > 0
  *   bc        [6] HOST, NTD_BC_* per face; at least one Dirichlet face
  *   t         [N] device filter vector, finite and > 0, or NULL for t = 1
  *             (the rowsum filter, eq. rowsum); B depends only on its direction
- *   prec      NTD_PREC_*; schur NTD_SCHUR_*
+ *   prec      NTD_PREC_*; schur NTD_SCHUR_*; smoother NTD_SMOOTHER_*
  *   workspace device buffer of >= ntd_workspace_bytes() bytes, 256-byte
  *             aligned, owned by the caller and used by the handle until
  *             ntd_destroy; its contents need no initialisation
  * Synchronises `stream`.  On success *out receives a new handle; on failure
  * *out = NULL (NTD_ENOTSPD if a pivot is not positive). */
 int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const double *t,
-              int prec, int schur, void *workspace, size_t workspace_bytes, void *stream,
-              ntd_handle **out);
+              int prec, int schur, int smoother, void *workspace, size_t workspace_bytes,
+              void *stream, ntd_handle **out);
 
-/* z = B^{-1} r (Sec. 2.2, Algorithms 1-7: level-3 twisted block sweeps over
- * planes, each plane block solved by level-2 sweeps over lines, each line by
- * the exact twisted tridiagonal solve).  r and z are [N] device FP64 and must
+/* z = (the handle's preconditioner)^{-1} r: B^{-1} r, or with the ILU(0)
+ * smoother the combination of eq. com.  r and z are [N] device FP64 and must
  * not overlap.  Stream-ordered, asynchronous. */
 int ntd_apply_precond(ntd_handle *h, const double *r, double *z, void *stream);
 
-/* Same as ntd_apply_precond, synchronous, and ms[0..2] (HOST) receive the
+/* z = B^{-1} r alone (Sec. 2.2, Algorithms 1-7: level-3 twisted block sweeps
+ * over planes, each plane block solved by level-2 sweeps over lines, each line
+ * by the exact twisted tridiagonal solve).  Same conventions. */
+int ntd_apply_ntd(ntd_handle *h, const double *r, double *z, void *stream);
+
+/* z = B_ILU^{-1} r alone (forward and backward sweeps of the block-diagonal
+ * ILU(0)); NTD_EINVAL if the handle has no smoother.  Same conventions. */
+int ntd_apply_ilu0(ntd_handle *h, const double *r, double *z, void *stream);
+
+/* Same as ntd_apply_ntd, synchronous, and ms[0..2] (HOST) receive the
  * durations in milliseconds of its three launches (lower level-3 sweep of the
  * two half chains, twist plane, upper level-3 sweep), measured with HIP events
  * on `stream`.  For benchmarking. */
@@ -117,7 +133,8 @@ int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int max
 /* Copy an internal array of the handle into dst ([N] device FP64), for tests
  * and diagnostics.  which: 0..3 = bands d, ax, ay, az of A; 4 = e1 (x-band of
  * the line blocks T); 5 = 1/pivot of T; 6 = f2 (y-band of the plane blocks P);
- * 7 = diagonal of T; 8 = diagonal of P; 9 = x-band of P. Stream-ordered. */
+ * 7 = diagonal of T; 8 = diagonal of P; 9 = x-band of P; 10 = diagonal of the
+ * ILU(0) factor (smoother only). Stream-ordered. */
 int ntd_export(const ntd_handle *h, int which, double *dst, void *stream);
 
 /* Replace the factors of the handle by given FP64 ones (e1, pivots M -- not

@@ -22,8 +22,9 @@ LIB_PATH = os.path.join(_HERE, "libntd.so")
 OK, EINVAL, ENOMEM, ENOTSPD, EBREAKDOWN, ENOCONV, EHIP = range(7)
 PREC = {"fp64": 0, "mixed": 1}
 SCHUR = {"newton": 0, "diag": 1}
+SMOOTHER = {"none": 0, "ilu0": 1}
 EXPORTS = {"d": 0, "ax": 1, "ay": 2, "az": 3, "e1": 4, "minv": 5, "f2": 6, "dT": 7, "dP": 8,
-           "xP": 9}
+           "xP": 9, "dt": 10}
 MAX_NX = 1024
 
 _lib = None
@@ -44,12 +45,13 @@ def lib() -> ctypes.CDLL:
                                "(or __graft_entry__.build()) first")
         L = ctypes.CDLL(LIB_PATH)
         P, I, D, Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
-        L.ntd_workspace_bytes.argtypes = [I, I, I, I]
+        L.ntd_workspace_bytes.argtypes = [I, I, I, I, I]
         L.ntd_workspace_bytes.restype = Z
-        L.ntd_setup.argtypes = [I, I, I, P, P, P, I, I, P, Z, P, ctypes.POINTER(P)]
+        L.ntd_setup.argtypes = [I, I, I, P, P, P, I, I, I, P, Z, P, ctypes.POINTER(P)]
         L.ntd_setup.restype = I
-        L.ntd_apply_precond.argtypes = [P, P, P, P]
-        L.ntd_apply_precond.restype = I
+        for name in ("ntd_apply_precond", "ntd_apply_ntd", "ntd_apply_ilu0"):
+            getattr(L, name).argtypes = [P, P, P, P]
+            getattr(L, name).restype = I
         L.ntd_apply_profile.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_float), P]
         L.ntd_apply_profile.restype = I
         L.ntd_spmv.argtypes = [P, P, P, P]
@@ -76,8 +78,8 @@ def strerror(status: int) -> str:
     return lib().ntd_strerror(int(status)).decode()
 
 
-def workspace_bytes(nx: int, ny: int, nz: int, prec: str = "mixed") -> int:
-    return int(lib().ntd_workspace_bytes(nx, ny, nz, PREC[prec]))
+def workspace_bytes(nx: int, ny: int, nz: int, prec: str = "mixed", smoother: str = "none") -> int:
+    return int(lib().ntd_workspace_bytes(nx, ny, nz, PREC[prec], SMOOTHER[smoother]))
 
 
 def _stream_ptr(device) -> ctypes.c_void_p:
@@ -102,11 +104,12 @@ class Solver:
 
     kappa: float64 CUDA tensor (nz, ny, nx), > 0.  bc: six ints (x-, x+, y-, y+,
     z-, z+), 0 = Dirichlet, 1 = Neumann.  t: optional filter vector (> 0), default
-    ones.  prec: "fp64" or "mixed".  schur: "newton" or "diag".
+    ones.  prec: "fp64" or "mixed".  schur: "newton" or "diag".  smoother: "none"
+    or "ilu0" (the combination preconditioner of the paper's experiments).
     """
 
     def __init__(self, kappa: torch.Tensor, bc, t: torch.Tensor | None = None,
-                 prec: str = "mixed", schur: str = "diag"):
+                 prec: str = "mixed", schur: str = "diag", smoother: str = "none"):
         if kappa.dim() != 3:
             raise ValueError("kappa must have shape (nz, ny, nx)")
         self.shape = tuple(kappa.shape)
@@ -115,31 +118,43 @@ class Solver:
         _check_vec(kappa, self.shape, self.device, "kappa")
         if t is not None:
             _check_vec(t, self.shape, self.device, "t")
-        self.prec, self.schur = prec, schur
+        self.prec, self.schur, self.smoother = prec, schur, smoother
         L = lib()
-        nbytes = int(L.ntd_workspace_bytes(nx, ny, nz, PREC[prec]))
+        nbytes = int(L.ntd_workspace_bytes(nx, ny, nz, PREC[prec], SMOOTHER[smoother]))
         if nbytes == 0:
             raise NTDError(EINVAL, "ntd_workspace_bytes(%d, %d, %d)" % (nx, ny, nz))
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         bc_arr = (ctypes.c_int * 6)(*[int(v) for v in bc])
         h = ctypes.c_void_p()
         st = L.ntd_setup(nx, ny, nz, _dptr(kappa), bc_arr, _dptr(t) if t is not None else None,
-                         PREC[prec], SCHUR[schur], _dptr(self.workspace), nbytes,
+                         PREC[prec], SCHUR[schur], SMOOTHER[smoother], _dptr(self.workspace),
+                         nbytes,
                          _stream_ptr(self.device), ctypes.byref(h))
         if st != OK:
             raise NTDError(st, "ntd_setup")
         self._h = h
 
     # -- the hot path -------------------------------------------------------
-    def apply(self, r: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        """z = B^{-1} r (stream-ordered)."""
+    def _apply_with(self, name: str, r: torch.Tensor, out: torch.Tensor | None):
         _check_vec(r, self.shape, self.device, "r")
         z = torch.empty_like(r) if out is None else out
         _check_vec(z, self.shape, self.device, "out")
-        st = lib().ntd_apply_precond(self._h, _dptr(r), _dptr(z), _stream_ptr(self.device))
+        st = getattr(lib(), name)(self._h, _dptr(r), _dptr(z), _stream_ptr(self.device))
         if st != OK:
-            raise NTDError(st, "ntd_apply_precond")
+            raise NTDError(st, name)
         return z
+
+    def apply(self, r: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """z = (preconditioner)^{-1} r: B^{-1} r, or the combination with ILU(0)."""
+        return self._apply_with("ntd_apply_precond", r, out)
+
+    def apply_ntd(self, r: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """z = B^{-1} r (the nested twisted sweeps alone)."""
+        return self._apply_with("ntd_apply_ntd", r, out)
+
+    def apply_ilu0(self, r: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """z = B_ILU^{-1} r (block-diagonal ILU(0) alone; needs smoother="ilu0")."""
+        return self._apply_with("ntd_apply_ilu0", r, out)
 
     def apply_profile(self, r: torch.Tensor, out: torch.Tensor):
         """z = B^{-1} r (synchronous); returns the durations in ms of the three

@@ -12,7 +12,9 @@
 using ntd::Scalars;
 
 struct ntd_handle {
-    int nx, ny, nz, prec, schur, epl;
+    int nx, ny, nz, prec, schur, smoother, epl;
+    ntd::IluGrid ilu;                         // ILU(0) level schedule (smoother only)
+    double *dt, *dtinv, *zi, *tv;             // ILU(0) diagonal, its inverse, two work vectors
     long long N, nxy, npack;                  // npack = ny*nz*64*epl packed slots
     size_t used;
     double *d, *ax, *ay, *az;                 // bands of A
@@ -54,7 +56,7 @@ bool grid_ok(int nx, int ny, int nz) {
     return N * 8 < 0x7fffffffLL && npack * 8 < 0x7fffffffLL;
 }
 
-size_t layout(ntd_handle *h, void *ws, int nx, int ny, int nz, int prec) {
+size_t layout(ntd_handle *h, void *ws, int nx, int ny, int nz, int prec, int smoother) {
     const long long N = (long long)nx * ny * nz, nxy = (long long)nx * ny;
     const long long lane_slots = 64LL * ntd::epl_for(nx);
     const long long npack = (long long)ny * nz * lane_slots;
@@ -66,6 +68,11 @@ size_t layout(ntd_handle *h, void *ws, int nx, int ny, int nz, int prec) {
     void **pk[] = {&h->pmv, &h->pa, &h->pu, &h->pf2, &h->pg3, &h->pZ};
     for (void **a : pk) *a = (void *)c.take<char>(npack * tsz);
     h->tw = c.take<double>(4 * (size_t)ny * nz);
+    h->dt = h->dtinv = h->zi = h->tv = nullptr;
+    if (smoother == NTD_SMOOTHER_ILU0) {
+        double **ilu[] = {&h->dt, &h->dtinv, &h->zi, &h->tv};
+        for (double **a : ilu) *a = c.take<double>(N);
+    }
     const size_t setup_scr = 6 * (size_t)nxy * sizeof(double);
     const size_t apply_scr = 2 * (size_t)ny * lane_slots * tsz;
     h->scratch = (void *)c.take<char>(setup_scr > apply_scr ? setup_scr : apply_scr);
@@ -111,13 +118,39 @@ ntd::PackArgs<T> pack_args(const ntd_handle *h) {
 // z = B^{-1} r; partials (if not null) receive the 6 per-wave partials of r.z;
 // ev (if not null, 4 events) brackets the three launches.
 int apply_internal(ntd_handle *h, const double *r, double *z, double *partials, hipStream_t s,
-                   hipEvent_t *ev = nullptr) {
+                   hipEvent_t *ev = nullptr, const double *zbase = nullptr,
+                   const double *rdot = nullptr) {
     if (h->prec == NTD_PREC_FP64) {
-        CK(ntd::launch_apply_f64(apply_args<double>(h, r, z, partials), h->epl, s, ev));
+        auto a = apply_args<double>(h, r, z, partials);
+        a.zbase = zbase;
+        a.rdot = rdot;
+        CK(ntd::launch_apply_f64(a, h->epl, s, ev));
     } else {
-        CK(ntd::launch_apply_f32(apply_args<float>(h, r, z, partials), h->epl, s, ev));
+        auto a = apply_args<float>(h, r, z, partials);
+        a.zbase = zbase;
+        a.rdot = rdot;
+        CK(ntd::launch_apply_f32(a, h->epl, s, ev));
     }
     return NTD_OK;
+}
+
+// z = B_ILU^{-1} r (block-diagonal ILU(0)).
+int ilu_internal(ntd_handle *h, const double *r, double *z, hipStream_t s) {
+    CK(ntd::launch_ilu_apply(h->ilu, h->ax, h->ay, h->az, h->dtinv, r, z, s));
+    return NTD_OK;
+}
+
+// The handle's preconditioner: B^{-1} r, or with the smoother the combination
+// of eq. com evaluated as z = B_ILU^{-1} r + B^{-1}(r - A B_ILU^{-1} r), the sum
+// and the partials of r.z fused into the last sweep.
+int precond_internal(ntd_handle *h, const double *r, double *z, double *partials, hipStream_t s,
+                     hipEvent_t *ev = nullptr) {
+    if (h->smoother != NTD_SMOOTHER_ILU0) return apply_internal(h, r, z, partials, s, ev);
+    int st = ilu_internal(h, r, h->zi, s);
+    if (st != NTD_OK) return st;
+    ntd::Grid g = grid_of(h);
+    CK(ntd::launch_spmv_residual(g, h->d, h->ax, h->ay, h->az, h->zi, r, h->tv, s));
+    return apply_internal(h, h->tv, z, partials, s, ev, h->zi, r);
 }
 
 // Pack the FP64 natural-layout factors into the apply layout and precision.
@@ -165,20 +198,22 @@ int true_relres(ntd_handle *h, const double *b, const double *x, double bn, doub
 
 extern "C" {
 
-size_t ntd_workspace_bytes(int nx, int ny, int nz, int prec) {
+size_t ntd_workspace_bytes(int nx, int ny, int nz, int prec, int smoother) {
     if (!grid_ok(nx, ny, nz) || (prec != NTD_PREC_FP64 && prec != NTD_PREC_MIXED)) return 0;
+    if (smoother != NTD_SMOOTHER_NONE && smoother != NTD_SMOOTHER_ILU0) return 0;
     ntd_handle tmp;
-    return layout(&tmp, nullptr, nx, ny, nz, prec);
+    return layout(&tmp, nullptr, nx, ny, nz, prec, smoother);
 }
 
 int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const double *t,
-              int prec, int schur, void *workspace, size_t workspace_bytes, void *stream,
-              ntd_handle **out) {
+              int prec, int schur, int smoother, void *workspace, size_t workspace_bytes,
+              void *stream, ntd_handle **out) {
     if (out) *out = nullptr;
     if (!out || !kappa || !bc || !workspace) return NTD_EINVAL;
     if (!grid_ok(nx, ny, nz)) return NTD_EINVAL;
     if (prec != NTD_PREC_FP64 && prec != NTD_PREC_MIXED) return NTD_EINVAL;
     if (schur != NTD_SCHUR_NEWTON && schur != NTD_SCHUR_DIAG) return NTD_EINVAL;
+    if (smoother != NTD_SMOOTHER_NONE && smoother != NTD_SMOOTHER_ILU0) return NTD_EINVAL;
     int ndir = 0;
     for (int f = 0; f < 6; ++f) {
         if (bc[f] != NTD_BC_DIRICHLET && bc[f] != NTD_BC_NEUMANN) return NTD_EINVAL;
@@ -186,16 +221,18 @@ int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const 
     }
     if (ndir == 0) return NTD_EINVAL;  // pure Neumann: A is singular
     if (((uintptr_t)workspace) % kAlign) return NTD_EINVAL;
-    if (workspace_bytes < ntd_workspace_bytes(nx, ny, nz, prec)) return NTD_EINVAL;
+    if (workspace_bytes < ntd_workspace_bytes(nx, ny, nz, prec, smoother)) return NTD_EINVAL;
 
     ntd_handle *h = (ntd_handle *)calloc(1, sizeof(ntd_handle));
     if (!h) return NTD_ENOMEM;
     h->nx = nx; h->ny = ny; h->nz = nz; h->prec = prec; h->schur = schur;
+    h->smoother = smoother;
     h->epl = ntd::epl_for(nx);
     h->N = (long long)nx * ny * nz;
     h->nxy = (long long)nx * ny;
     h->npack = (long long)ny * nz * 64 * h->epl;
-    h->used = layout(h, workspace, nx, ny, nz, prec);
+    h->used = layout(h, workspace, nx, ny, nz, prec, smoother);
+    h->ilu = ntd::ilu_grid(nx, ny, nz, 2);
     hipStream_t s = S(stream);
     int st = NTD_OK;
     int hflag = 0;
@@ -215,6 +252,8 @@ int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const 
     a.dP = h->dP; a.xP = h->xP; a.f2 = h->f2; a.dT = h->dT; a.e1 = h->e1; a.mv = h->mv;
     a.scratch = (double *)h->scratch; a.flag = h->flag;
     HK(ntd::launch_setup(a, h->epl, s));
+    if (smoother == NTD_SMOOTHER_ILU0)
+        HK(ntd::launch_ilu_factor(h->ilu, h->d, h->ax, h->ay, h->az, h->dt, h->dtinv, h->flag, s));
     HK(hipMemcpyAsync(&hflag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HK(hipStreamSynchronize(s));
     if (hflag & ntd::kFlagNotSPD) FAIL(NTD_ENOTSPD);
@@ -231,7 +270,17 @@ fail:
 
 int ntd_apply_precond(ntd_handle *h, const double *r, double *z, void *stream) {
     if (!h || !r || !z || r == z) return NTD_EINVAL;
+    return precond_internal(h, r, z, nullptr, S(stream));
+}
+
+int ntd_apply_ntd(ntd_handle *h, const double *r, double *z, void *stream) {
+    if (!h || !r || !z || r == z) return NTD_EINVAL;
     return apply_internal(h, r, z, nullptr, S(stream));
+}
+
+int ntd_apply_ilu0(ntd_handle *h, const double *r, double *z, void *stream) {
+    if (!h || !r || !z || r == z || h->smoother != NTD_SMOOTHER_ILU0) return NTD_EINVAL;
+    return ilu_internal(h, r, z, S(stream));
 }
 
 int ntd_apply_profile(ntd_handle *h, const double *r, double *z, float *ms, void *stream) {
@@ -241,7 +290,7 @@ int ntd_apply_profile(ntd_handle *h, const double *r, double *z, float *ms, void
     int made = 0, st = NTD_OK;
     for (; made < 4; ++made)
         if (hipEventCreate(&ev[made]) != hipSuccess) { st = NTD_EHIP; break; }
-    if (st == NTD_OK) st = apply_internal(h, r, z, nullptr, s, ev);
+    if (st == NTD_OK) st = apply_internal(h, r, z, nullptr, s, ev);  // the NTD sweeps alone
     if (st == NTD_OK && hipEventSynchronize(ev[3]) != hipSuccess) st = NTD_EHIP;
     for (int i = 0; st == NTD_OK && i < 3; ++i)
         if (hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]) != hipSuccess) st = NTD_EHIP;
@@ -289,7 +338,7 @@ int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int max
         CK(hipStreamSynchronize(s));
         return NTD_OK;
     }
-    if ((st = apply_internal(h, h->r, h->z, h->partials, s)) != NTD_OK) return st;
+    if ((st = precond_internal(h, h->r, h->z, h->partials, s)) != NTD_OK) return st;
     CK(ntd::launch_finalize(h->partials, 6, h->sc, ntd::kOpRhoInit, s));
     CK(ntd::launch_copy(h->p, h->z, N, s));
     int it = 0, status = NTD_OK, np = 0;
@@ -308,7 +357,7 @@ int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int max
             if ((st = true_relres(h, b, x, bn, &tr, s)) != NTD_OK) return st;
             if (tr <= tol) break;
         }
-        if ((st = apply_internal(h, h->r, h->z, h->partials, s)) != NTD_OK) return st;
+        if ((st = precond_internal(h, h->r, h->z, h->partials, s)) != NTD_OK) return st;
         CK(ntd::launch_finalize(h->partials, 6, h->sc, ntd::kOpBeta, s));
         CK(ntd::launch_xpay(h->p, h->z, h->sc, N, s));
     }
@@ -319,8 +368,8 @@ int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int max
 
 int ntd_export(const ntd_handle *h, int which, double *dst, void *stream) {
     if (!h || !dst) return NTD_EINVAL;
-    const double *src[] = {h->d, h->ax, h->ay, h->az, h->e1, h->mv, h->f2, h->dT, h->dP, h->xP};
-    if (which < 0 || which >= (int)(sizeof(src) / sizeof(src[0]))) return NTD_EINVAL;
+    const double *src[] = {h->d, h->ax, h->ay, h->az, h->e1, h->mv, h->f2, h->dT, h->dP, h->xP, h->dt};
+    if (which < 0 || which >= (int)(sizeof(src) / sizeof(src[0])) || !src[which]) return NTD_EINVAL;
     CK(hipMemcpyAsync(dst, src[which], sizeof(double) * h->N, hipMemcpyDeviceToDevice,
                       S(stream)));
     return NTD_OK;

@@ -60,7 +60,17 @@ struct ApplyArgs {
     T *Z;                         // packed intermediate / final result
     double *zout;                 // final result (FP64, natural layout)
     T *scratch;                   // two packed plane buffers (one per half chain)
-    double *partials;             // kApplySlots partial sums of r.z (may be null)
+    double *partials;             // kApplySlots partial sums of rdot.z (may be null)
+    const double *zbase;          // if not null, the output is zbase + B^{-1} r
+    const double *rdot;           // vector dotted with the output (null: r)
+};
+
+// Geometry of the ILU(0) level schedule: rows split at M (nblocks = 2) or not.
+struct IluGrid {
+    int nx, ny, nz, nblocks;
+    long long nxy, N, M;
+    int kz;       // plane of row M (start plane of the second block's level frame)
+    int levels;   // number of hyperplane levels
 };
 
 // Arguments of the packing of FP64 natural-layout factors into the apply layout.
@@ -90,6 +100,16 @@ hipError_t launch_apply_f32(const ApplyArgs<float> &a, int epl, hipStream_t s, h
 hipError_t launch_setup(const SetupArgs &a, int epl, hipStream_t s);
 hipError_t launch_pack_f64(const PackArgs<double> &p, int epl, hipStream_t s);
 hipError_t launch_pack_f32(const PackArgs<float> &p, int epl, hipStream_t s);
+
+IluGrid ilu_grid(int nx, int ny, int nz, int nblocks);
+hipError_t launch_ilu_factor(const IluGrid &g, const double *d, const double *ax, const double *ay,
+                             const double *az, double *dt, double *dtinv, int *flag,
+                             hipStream_t s);
+hipError_t launch_ilu_apply(const IluGrid &g, const double *ax, const double *ay, const double *az,
+                            const double *dtinv, const double *r, double *z, hipStream_t s);
+hipError_t launch_spmv_residual(const Grid &g, const double *d, const double *ax, const double *ay,
+                                const double *az, const double *x, const double *b, double *out,
+                                hipStream_t s);
 
 hipError_t launch_check_positive(const double *kappa, const double *t, long long N, int *flag,
                                  hipStream_t s);

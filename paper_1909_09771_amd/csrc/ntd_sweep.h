@@ -403,7 +403,7 @@ struct LineIn {
     T c0[EPL], c1[EPL], c2[EPL];  // natural: 1/M, e1[e], e1[e-1]; packed: 1/M, a, u
     T f[EPL], w[EPL];
     T a0[EPL], a1[EPL], a2[EPL], a3[EPL];
-    double d0[EPL];
+    double d0[EPL], d1[EPL], d2[EPL];
     double mvj, cpj, cnj;
 };
 
@@ -689,7 +689,7 @@ __device__ __forceinline__ PackFmt<T, EPL> pack_fmt(const ApplyArgs<T> &a, int k
     return F;
 }
 
-// r of line m (natural layout, FP64) into d0.
+// A natural-layout FP64 line (r, the dot operand or the base) into v.
 template <typename T, int EPL>
 __device__ __forceinline__ void load_r(const PackFmt<T, EPL> &F, rsrc_t r, unsigned so8,
                                        double (&v)[EPL]) {
@@ -730,10 +730,10 @@ struct PolLower {
 // The twist plane: rhs = r - g3_lo * z_lo - g3_hi * z_hi; the result is final.
 template <typename T, int EPL>
 struct PolTwist {
-    rsrc_t r, g3, Z, zout;
+    rsrc_t r, g3, Z, zout, rdot, zbase;
     unsigned so8k, soPk, soPlo, soPhi;  // plane k, plane k-1 and plane k+1 (packed Z, g3)
     unsigned line8;
-    bool lo_nb, hi_nb;
+    bool lo_nb, hi_nb, has_base;
     double acc;
     __device__ void load_rhs(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
         load_r(F, r, so8k + m * line8, in.d0);
@@ -752,8 +752,11 @@ struct PolTwist {
         if (hi_nb) v -= in.a2[s] * in.a3[s];
         return v;
     }
+    // d0 still holds the right-hand side when this runs (the twist line is
+    // loaded ahead of its solve), so the dot operand and base go to d1, d2.
     __device__ void load_out(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
-        load_r(F, r, so8k + m * line8, in.d0);
+        load_r(F, rdot, so8k + m * line8, in.d1);
+        if (has_base) load_r(F, zbase, so8k + m * line8, in.d2);
     }
     __device__ void out(int m, const PackFmt<T, EPL> &F, const T (&x)[EPL],
                         const LineIn<T, EPL> &in) {
@@ -762,7 +765,8 @@ struct PolTwist {
 #pragma unroll
         for (int s = 0; s < EPL; ++s) {
             xd[s] = (double)x[s];
-            acc += in.d0[s] * xd[s];  // both 0 on unused slots
+            if (has_base) xd[s] += in.d2[s];
+            acc += in.d1[s] * xd[s];  // both 0 on unused slots
         }
         bstore_line(F.S, zout, so8k + m * line8, xd);
     }
@@ -772,9 +776,10 @@ struct PolTwist {
 // kn the final neighbour toward the twist plane; x_k = z_k - c over Z.
 template <typename T, int EPL>
 struct PolUpper {
-    rsrc_t r, g3, Z, zout;
+    rsrc_t r, g3, Z, zout, rdot, zbase;
     unsigned so8k, soPk, soPc, soPn;
     unsigned line8;
+    bool has_base;
     double acc;
     __device__ void load_rhs(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
         vload(g3, F.laneB, soPc + m * F.lineB, in.a0);
@@ -783,7 +788,8 @@ struct PolUpper {
     __device__ T rhs(const LineIn<T, EPL> &in, int s) const { return in.a0[s] * in.a1[s]; }
     __device__ void load_out(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
         vload(Z, F.laneB, soPk + m * F.lineB, in.a2);
-        load_r(F, r, so8k + m * line8, in.d0);
+        load_r(F, rdot, so8k + m * line8, in.d0);
+        if (has_base) load_r(F, zbase, so8k + m * line8, in.d1);
     }
     __device__ void out(int m, const PackFmt<T, EPL> &F, const T (&cv)[EPL],
                         const LineIn<T, EPL> &in) {
@@ -793,6 +799,7 @@ struct PolUpper {
         for (int s = 0; s < EPL; ++s) {
             xv[s] = in.a2[s] - cv[s];
             xd[s] = (double)xv[s];
+            if (has_base) xd[s] += in.d1[s];
             acc += in.d0[s] * xd[s];
         }
         vstore(Z, F.laneB, soPk + m * F.lineB, xv);
@@ -839,6 +846,9 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply_twist(ApplyArgs<T> a) {
     pol.g3 = make_rsrc(a.pg3);
     pol.Z = make_rsrc(a.Z);
     pol.zout = make_rsrc(a.zout);
+    pol.rdot = make_rsrc(a.rdot ? a.rdot : a.r);
+    pol.zbase = make_rsrc(a.zbase ? a.zbase : a.r);
+    pol.has_base = a.zbase != nullptr;
     pol.lo_nb = k > 0;
     pol.hi_nb = k < nz - 1;
     pol.line8 = (unsigned)a.nx * 8u;
@@ -871,6 +881,9 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply_upper(ApplyArgs<T> a) {
     pol.g3 = make_rsrc(a.pg3);
     pol.Z = make_rsrc(a.Z);
     pol.zout = make_rsrc(a.zout);
+    pol.rdot = make_rsrc(a.rdot ? a.rdot : a.r);
+    pol.zbase = make_rsrc(a.zbase ? a.zbase : a.r);
+    pol.has_base = a.zbase != nullptr;
     pol.line8 = (unsigned)a.nx * 8u;
     pol.acc = 0.0;
     for (int k = j3 + dk; k >= 0 && k < nz; k += dk) {

@@ -268,3 +268,57 @@ def test_deterministic_repeat():
         d1 = S.dot(r, S.spmv(r))
         d2 = S.dot(r, S.spmv(r))
         assert d1 == d2
+
+
+# ---------------------------------------------------------------------------
+# ILU(0) smoother and the combination preconditioner (Sec. 3, eq. com)
+# ---------------------------------------------------------------------------
+
+ILU_SHAPES = [((16, 12, 20), "jump"), ((7, 11, 37), "rand"), ((5, 4, 3), "rand"), ((1, 6, 9), "jump"),
+              ((9, 1, 1), "rand"), ((2, 2, 2), "poisson")]
+
+
+@pytest.mark.parametrize("shape,kind", ILU_SHAPES)
+def test_ilu0_factor_and_apply_parity(shape, kind):
+    kappa, bc = case(shape, kind)
+    S = ntd().Solver(G(kappa), bc, prec="fp64", schur="newton", smoother="ilu0")
+    bands = O.assemble(kappa, bc)
+    dt, st = O.ilu0(bands, 2)
+    assert st == 0
+    np.testing.assert_allclose(C(S.export("dt")), dt, rtol=1e-13)
+    r = np.random.default_rng(23).uniform(-1, 1, shape)
+    z = C(S.apply_ilu0(G(r)))
+    assert relmax(z, O.ilu0_apply(bands, dt, r, 2)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("mixed", 1e-5)])
+@pytest.mark.parametrize("shape,kind", ILU_SHAPES[:4])
+def test_combination_apply_parity(shape, kind, prec, tol):
+    kappa, bc = case(shape, kind)
+    S = ntd().Solver(G(kappa), bc, prec=prec, schur="newton", smoother="ilu0")
+    bands = O.assemble(kappa, bc)
+    F = O.setup(bands, mode="newton")
+    dt, _ = O.ilu0(bands, 2)
+    r = np.random.default_rng(29).uniform(-1, 1, shape)
+    want = O.combo_apply(bands, F, dt, r, 2)
+    z = C(S.apply(G(r)))
+    assert np.linalg.norm(z - want) <= tol * np.linalg.norm(want)
+    zn = C(S.apply_ntd(G(r)))
+    assert np.linalg.norm(zn - O.apply(F, r)) <= tol * np.linalg.norm(O.apply(F, r))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_pcg_combination_parity(prec):
+    shape = (24, 20, 36)
+    kappa, bc = case(shape, "jump")
+    b = W.rhs_uniform(shape[2], shape[1], shape[0], 31)
+    S = ntd().Solver(G(kappa), bc, prec=prec, schur="newton", smoother="ilu0")
+    x, it, rr, st = S.pcg(G(b), tol=1e-8, maxit=500)
+    bands = O.assemble(kappa, bc)
+    dt, _ = O.ilu0(bands, 2)
+    xo, ito, rro, sto = O.pcg(bands, O.setup(bands, mode="newton"), b, 1e-8, 500, dt=dt)[:4]
+    print("combination PCG: %s iterations %d, FP64 oracle %d" % (prec, it, ito))
+    assert st == 0 and sto == 0 and rr <= 1e-8
+    assert abs(it - ito) <= (1 if prec == "fp64" else ito // 4 + 3)
+    d = O.spmv(bands, C(x) - xo)
+    assert np.linalg.norm(d) <= 2.01e-8 * np.linalg.norm(b)
