@@ -2,13 +2,19 @@
 and the preconditioner-apply bandwidth, on one MI355X.
 
 One step = the whole hot path on one synthetic system: assemble A from kappa,
-factor B (setup), and PCG to a true relative residual <= 1e-8.  Inputs are
-resident in HBM before the timed region.  Prints one JSON line.
+factor B (setup, plus the ILU(0) smoother of the combination preconditioner of
+eq. com), and PCG to a true relative residual <= 1e-8.  Inputs are resident in
+HBM before the timed region.  Prints one JSON line.
 
 Default workload: 256^3 grid, kappa piecewise constant on 8^3 subcubes with
 kappa = 10^U(-3,3) (seed 601), Dirichlet on the z = 0 face, Neumann elsewhere,
-b ~ U[-1,1] (seed 602), filter t = 1, mixed precision (float factors and
-sweeps, FP64 CG).
+b ~ U[-1,1] (seed 602), filter t = 1; Newton Schur blocks with the ILU(0)
+combination; mixed precision (float factors and sweeps, FP64 CG), next to the
+same solve in FP64.
+
+--kernels-only runs the preconditioner and the SpMV a few times plus a plain
+device copy of known size (the calibration of the HBM byte counters) and exits;
+it is the program the hardware-counter runs profile.
 """
 from __future__ import annotations
 
@@ -26,15 +32,30 @@ if ROOT not in sys.path:
 METRIC = "PCG time-to-1e-8 & precond-apply GB/s, 256³ jump κ: mixed/learned vs FP64"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_traffic_jump256.json")
-SWEEP_SRC = os.path.join(ROOT, "paper_1909_09771_amd", "csrc", "ntd_sweep.h")
+# Sources of the sweep kernels; the recorded byte counts hold only for them.
+SWEEP_SRCS = [os.path.join(ROOT, "paper_1909_09771_amd", "csrc", f)
+              for f in ("ntd_sweep.h", "ntd_internal.h", "ntd_apply_f32.hip", "ntd_apply_f64.hip")]
 
-# Algorithmic HBM bytes per unknown of each apply launch (reads of r and of the
-# four factor arrays e1, 1/M, f2, g3; the intermediate write/read; the final
-# FP64 write; r again for the fused r.z partial).  See the design notes.
-APPLY_BYTES = {
-    "mixed": {"lower": 8 + 16 + 4, "upper": 4 + 16 + 8 + 8},
-    "fp64": {"lower": 8 + 32 + 8, "upper": 8 + 32 + 8 + 8},
-}
+# Algorithmic HBM bytes per unknown of each sweep launch.  Lower: the FP64
+# right-hand side, the four factor arrays (e1, 1/M, f2, g3) and the
+# intermediate z written in the factor precision.  Upper: z read back, the four
+# factor arrays, the final FP64 output, r read again for the fused r.z partial,
+# and with the ILU(0) combination the base zi added to the output.
+FACTOR_BYTES = {"mixed": 4, "fp64": 8}
+
+
+def apply_bytes(prec: str, smoother: str):
+    e = FACTOR_BYTES[prec]
+    lower = 8 + 4 * e + e
+    upper = e + 4 * e + 8 + 8 + (8 if smoother == "ilu0" else 0)
+    return {"lower": lower, "upper": upper}
+
+
+# The smoother part of the combination: the ILU(0) forward and backward level
+# sweeps (each reads the three couplings, the inverted diagonal and its input,
+# and writes its output) and the residual r - A zi (four bands, zi and r read,
+# one vector written), all FP64.
+SMOOTHER_BYTES = 2 * (5 * 8 + 8) + 7 * 8
 
 
 def parse():
@@ -44,21 +65,32 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="cubic grid side")
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--schur", default="diag", choices=["diag", "newton"])
+    ap.add_argument("--schur", default="newton", choices=["diag", "newton"])
+    ap.add_argument("--smoother", default="ilu0", choices=["none", "ilu0"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=2, help="oracle PCG iterations sampled")
+    ap.add_argument("--cpu-iters", type=int, default=3, help="oracle PCG iterations sampled")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="run the preconditioner, the SpMV and a calibration copy, then exit")
+    ap.add_argument("--reps", type=int, default=3, help="launches per kernel in --kernels-only")
     return ap.parse_args()
 
 
+def log(msg: str):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def sweep_hash() -> str:
-    with open(SWEEP_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in SWEEP_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str, prec: str, n: int):
+def traffic_for(kernel: str, prec: str, smoother: str, n: int):
     """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by
     the copy-kernel calibration) if recorded for the current kernel source."""
     try:
@@ -66,42 +98,67 @@ def traffic_for(kernel: str, prec: str, n: int):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    key = "%s/%s/%d" % (kernel, prec, n)
+    key = "%s/%s/%s/%d" % (kernel, prec, smoother, n)
     ent = rec.get("kernels", {}).get(key)
     if not ent or rec.get("sweep_sha") != sweep_hash():
         return None
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(w, gpu_iters: int, n_iters: int):
-    """The FP64 oracle (single thread) on a bounded sample: assembly + setup on the
-    full grid and `n_iters` PCG iterations; extrapolated to the GPU's iteration
-    count as setup + iters x (time per iteration)."""
-    import numpy as np
+def cpu_baseline(w, args, gpu_iters: int):
+    """The FP64 oracle (single thread) on a bounded sample: assembly, setup (and
+    the ILU(0) factorization) on the full grid, then a few PCG iterations;
+    extrapolated to the GPU's iteration count as setup + iters x (time per
+    iteration, the initial preconditioner application included)."""
     import oracle as O
+    n_iters = args.cpu_iters
     t0 = time.perf_counter()
     bands = O.assemble(w["kappa"], w["bc"])
-    F = O.setup(bands, mode="diag")
+    F = O.setup(bands, mode=args.schur)
+    dt = O.ilu0(bands, 2)[0] if args.smoother == "ilu0" else None
     t1 = time.perf_counter()
-    O.pcg(bands, F, w["b"], 1e-30, n_iters)
+    O.pcg(bands, F, w["b"], 1e-30, n_iters, dt=dt)
     t2 = time.perf_counter()
     per_iter = (t2 - t1) / n_iters
     est = (t1 - t0) + gpu_iters * per_iter
-    del bands, F
-    return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": "assembly+setup on the full %d^3 grid (%.2f s) and %d PCG iterations "
-                      "(%.3f s/iter), extrapolated to %d iterations; 1 thread of %d host cores"
-                      % (w["n"][0], t1 - t0, n_iters, per_iter, gpu_iters, os.cpu_count() or 0)}
+    del bands, F, dt
+    n = w["n"][0]
+    combo = " + ILU(0) combination" if args.smoother == "ilu0" else ""
+    return {"value": round(est, 3), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": "FP64 oracle, %s Schur blocks%s: assembly+setup on the full %d^3 grid "
+                      "(%.2f s) and %d PCG iterations (%.3f s/iter), extrapolated to the GPU's "
+                      "%d iterations; 1 thread of %d host cores"
+                      % (args.schur, combo, n, t1 - t0, n_iters, per_iter, gpu_iters,
+                         os.cpu_count() or 0)}
+
+
+def kernels_only(args, S, b, n):
+    """A short program for hardware-counter runs: the preconditioner and the
+    SpMV `reps` times each, then a device copy of 2 GiB (the byte-counter
+    calibration: 2 GiB read, 2 GiB written)."""
+    import torch
+    z = torch.empty_like(b)
+    for _ in range(args.reps):
+        S.apply_profile(b, z)
+    q = torch.empty_like(b)
+    for _ in range(args.reps):
+        S.spmv(b, out=q)
+    src = torch.ones(1 << 28, dtype=torch.float64, device=b.device)
+    dst = torch.empty_like(src)
+    for _ in range(args.reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernels_only": True, "n": n, "prec": args.prec, "schur": args.schur,
+                      "smoother": args.smoother, "reps": args.reps,
+                      "copy_bytes_each_way": src.numel() * 8}), flush=True)
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); "
-              "the level-3 twist split across two GPUs is described in the design notes "
-              "but not built", file=sys.stderr)
+        print("bench.py: runs on one GPU only (--gpus 1); the level-3 twist split "
+              "across two GPUs is a design, not built", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     import paper_1909_09771_amd as P
     import workloads as W
@@ -114,57 +171,64 @@ def main():
     bc = w["bc"]
     torch.cuda.synchronize()
 
+    def make(prec):
+        return P.Solver(kappa, bc, prec=prec, schur=args.schur, smoother=args.smoother)
+
+    if args.kernels_only:
+        kernels_only(args, make(args.prec), b, n)
+        return
+
     def step(prec):
-        S = P.Solver(kappa, bc, prec=prec, schur=args.schur)
+        S = make(prec)
         x, it, rr, st = S.pcg(b, tol=args.tol, maxit=args.maxit)
         return S, x, it, rr, st
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         S, x, it, rr, st = step(args.prec)
+        log("warmup %d: %d iterations, relres %.3e, status %d" % (i, it, rr, st))
         del S, x
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
-    for _ in range(args.steps):
+    for i in range(args.steps):
         S, x, it, rr, st = step(args.prec)
         results.append((it, rr, st))
-        if _ != args.steps - 1:
+        log("step %d: %d iterations, relres %.3e, status %d" % (i, it, rr, st))
+        if i != args.steps - 1:
             del S, x
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     iters, relres, status = results[-1]
 
-    # Apply: per-launch durations with HIP events on the solver's stream.
-    r = b.clone()
+    # Preconditioner launches as PCG issues them, timed with HIP events on the
+    # solver's stream (median of 5).
     z = torch.empty_like(b)
-    S.apply(r, out=z)
-    prof = [S.apply_profile(r, z) for _ in range(5)]
-    lower_ms = sorted(p[0] for p in prof)[2]
-    twist_ms = sorted(p[1] for p in prof)[2]
-    upper_ms = sorted(p[2] for p in prof)[2]
-    apply_ms = lower_ms + twist_ms + upper_ms
+    S.apply_profile(b, z)
+    prof = [S.apply_profile(b, z) for _ in range(5)]
+    med = [sorted(p[i] for p in prof)[2] for i in range(4)]
+    lower_ms, twist_ms, upper_ms, smooth_ms = med
+    sweeps_ms = lower_ms + twist_ms + upper_ms
     N = n ** 3
-    nxy = n * n
-    by = APPLY_BYTES[args.prec]
-    units_lower = (n - 1) * nxy
-    units_upper = (n - 1) * nxy
-    cand = {"k_apply_lower": (lower_ms, by["lower"] * units_lower),
-            "k_apply_upper": (upper_ms, by["upper"] * units_upper)}
+    by = apply_bytes(args.prec, args.smoother)
+    units = (n - 1) * n * n  # unknowns outside the twist plane: one half chain each side
+    cand = {"k_apply_lower": (lower_ms, by["lower"] * units),
+            "k_apply_upper": (upper_ms, by["upper"] * units)}
     kname = max(cand, key=lambda k: cand[k][0])
     k_ms, k_bytes = cand[kname]
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
-    apply_gbs = (by["lower"] + by["upper"]) * N / (apply_ms * 1e-3) / 1e9
-    t_spmv0 = torch.cuda.Event(enable_timing=True)
-    t_spmv1 = torch.cuda.Event(enable_timing=True)
+    sweeps_gbs = (by["lower"] + by["upper"]) * N / (sweeps_ms * 1e-3) / 1e9
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     q = S.spmv(b)
-    t_spmv0.record()
+    e0.record()
     for _ in range(10):
         S.spmv(b, out=q)
-    t_spmv1.record()
+    e1.record()
     torch.cuda.synchronize()
-    spmv_ms = t_spmv0.elapsed_time(t_spmv1) / 10
+    spmv_ms = e0.elapsed_time(e1) / 10
     footprint = S.footprint_bytes
+    x_main = x.clone()
     del S, x
 
     extra = {}
@@ -175,10 +239,14 @@ def main():
         S2, x2, it2, rr2, st2 = step(other)
         torch.cuda.synchronize()
         c1 = time.perf_counter()
+        diff = (torch.linalg.vector_norm(x_main - x2) / torch.linalg.vector_norm(x2)).item()
         extra["compare"] = {"prec": other, "s_to_solution": round(c1 - c0, 4), "iters": it2,
-                            "relres": rr2, "status": st2}
+                            "relres": rr2, "status": st2,
+                            "rel_diff_of_solutions": diff}
+        log("comparison solve (%s): %.2f s, %d iterations" % (other, c1 - c0, it2))
         del S2, x2
 
+    precond_ms = sweeps_ms + smooth_ms
     line = {
         "metric": METRIC,
         "value": round(ms_per_step / 1e3, 4),
@@ -193,28 +261,31 @@ def main():
         "dtype": "f32-precond/f64-cg" if args.prec == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": "jump%d" % n, "grid": [n, n, n],
-                   "kappa": "8^3 subcubes, 10^U(-3,3), seed 601" if n == 256 else
-                            "8^3 subcubes, 10^U(-3,3), seed 201",
+                   "kappa": "8^3 subcubes, 10^U(-3,3), seed %d" % (601 if n == 256 else 201),
                    "bc": "Dirichlet z=0, Neumann else", "tol": args.tol, "prec": args.prec,
-                   "schur": args.schur, "filter": "t=1"},
+                   "schur": args.schur, "smoother": args.smoother, "filter": "t=1"},
         "iters": iters,
         "relres": relres,
         "status": status,
-        "apply_ms": round(apply_ms, 4),
-        "apply_GBps": round(apply_gbs, 2),
-        "apply_launch_ms": {"lower": round(lower_ms, 4), "twist": round(twist_ms, 4),
-                            "upper": round(upper_ms, 4)},
+        "precond_ms": round(precond_ms, 4),
+        "sweeps_ms": round(sweeps_ms, 4),
+        "sweeps_GBps": round(sweeps_gbs, 2),
+        "launch_ms": {"lower": round(lower_ms, 4), "twist": round(twist_ms, 4),
+                      "upper": round(upper_ms, 4), "smoother": round(smooth_ms, 4)},
         "spmv_ms": round(spmv_ms, 4),
         "spmv_GBps": round(48 * N / (spmv_ms * 1e-3) / 1e9, 1),
         "footprint_bytes": footprint,
         "roofline": {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": traffic_for(kname, args.prec, n)},
+                     "traffic": traffic_for(kname, args.prec, args.smoother, n)},
     }
+    if args.smoother == "ilu0":
+        line["smoother_GBps"] = round(SMOOTHER_BYTES * N / (smooth_ms * 1e-3) / 1e9, 1)
     line.update(extra)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w, iters, args.cpu_iters)
+        log("timing the CPU oracle on a sample")
+        line["cpu_baseline"] = cpu_baseline(w, args, iters)
     print(json.dumps(line), flush=True)
 
 

@@ -107,10 +107,13 @@ int ntd_apply_ntd(ntd_handle *h, const double *r, double *z, void *stream);
  * ILU(0)); NTD_EINVAL if the handle has no smoother.  Same conventions. */
 int ntd_apply_ilu0(ntd_handle *h, const double *r, double *z, void *stream);
 
-/* Same as ntd_apply_ntd, synchronous, and ms[0..2] (HOST) receive the
- * durations in milliseconds of its three launches (lower level-3 sweep of the
- * two half chains, twist plane, upper level-3 sweep), measured with HIP events
- * on `stream`.  For benchmarking. */
+/* Same as ntd_apply_precond (launched exactly as inside ntd_pcg_solve, with
+ * the fused r.z partials), but synchronous; ms[0..3] (HOST) receive durations
+ * in milliseconds measured with HIP events on `stream`: ms[0..2] the three
+ * sweep launches (lower level-3 sweep of the two half chains, twist plane,
+ * upper level-3 sweep), ms[3] the smoother part before them (ILU(0) sweeps and
+ * the residual r - A zi; without a smoother only the gap between two
+ * back-to-back events).  For benchmarking. */
 int ntd_apply_profile(ntd_handle *h, const double *r, double *z, float *ms, void *stream);
 
 /* y = A x with the assembled 7-point bands.  [N] device FP64, no overlap.

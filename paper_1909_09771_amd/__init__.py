@@ -157,15 +157,17 @@ class Solver:
         return self._apply_with("ntd_apply_ilu0", r, out)
 
     def apply_profile(self, r: torch.Tensor, out: torch.Tensor):
-        """z = B^{-1} r (synchronous); returns the durations in ms of the three
-        launches (lower level-3 sweep, twist plane, upper level-3 sweep)."""
+        """The preconditioner as PCG launches it (synchronous); returns the
+        durations in ms of the lower level-3 sweep, the twist plane, the upper
+        level-3 sweep and the smoother part before them (without a smoother,
+        the gap between two back-to-back events)."""
         _check_vec(r, self.shape, self.device, "r")
         _check_vec(out, self.shape, self.device, "out")
-        ms = (ctypes.c_float * 3)()
+        ms = (ctypes.c_float * 4)()
         st = lib().ntd_apply_profile(self._h, _dptr(r), _dptr(out), ms, _stream_ptr(self.device))
         if st != OK:
             raise NTDError(st, "ntd_apply_profile")
-        return float(ms[0]), float(ms[1]), float(ms[2])
+        return tuple(float(v) for v in ms)
 
     def spmv(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         _check_vec(x, self.shape, self.device, "x")

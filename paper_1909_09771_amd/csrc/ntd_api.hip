@@ -286,14 +286,17 @@ int ntd_apply_ilu0(ntd_handle *h, const double *r, double *z, void *stream) {
 int ntd_apply_profile(ntd_handle *h, const double *r, double *z, float *ms, void *stream) {
     if (!h || !r || !z || r == z || !ms) return NTD_EINVAL;
     hipStream_t s = S(stream);
-    hipEvent_t ev[4];
+    hipEvent_t ev[5];  // ev[0]: before the smoother part; ev[1..4] bracket the sweeps
     int made = 0, st = NTD_OK;
-    for (; made < 4; ++made)
+    for (; made < 5; ++made)
         if (hipEventCreate(&ev[made]) != hipSuccess) { st = NTD_EHIP; break; }
-    if (st == NTD_OK) st = apply_internal(h, r, z, nullptr, s, ev);  // the NTD sweeps alone
-    if (st == NTD_OK && hipEventSynchronize(ev[3]) != hipSuccess) st = NTD_EHIP;
+    if (st == NTD_OK && hipEventRecord(ev[0], s) != hipSuccess) st = NTD_EHIP;
+    // The preconditioner as the PCG loop launches it, r.z partials included.
+    if (st == NTD_OK) st = precond_internal(h, r, z, h->partials, s, ev + 1);
+    if (st == NTD_OK && hipEventSynchronize(ev[4]) != hipSuccess) st = NTD_EHIP;
     for (int i = 0; st == NTD_OK && i < 3; ++i)
-        if (hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]) != hipSuccess) st = NTD_EHIP;
+        if (hipEventElapsedTime(&ms[i], ev[i + 1], ev[i + 2]) != hipSuccess) st = NTD_EHIP;
+    if (st == NTD_OK && hipEventElapsedTime(&ms[3], ev[0], ev[1]) != hipSuccess) st = NTD_EHIP;
     for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
     return st;
 }

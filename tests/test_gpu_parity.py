@@ -322,3 +322,19 @@ def test_pcg_combination_parity(prec):
     assert abs(it - ito) <= (1 if prec == "fp64" else ito // 4 + 3)
     d = O.spmv(bands, C(x) - xo)
     assert np.linalg.norm(d) <= 2.01e-8 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("smoother", ["none", "ilu0"])
+def test_apply_profile_matches_apply(smoother):
+    """The timed preconditioner (as PCG launches it) gives the same output as
+    the plain entry point and reports non-negative launch durations."""
+    shape = (12, 10, 40)
+    kappa, bc = case(shape, "jump")
+    S = ntd().Solver(G(kappa), bc, prec="mixed", schur="newton", smoother=smoother)
+    r = G(np.random.default_rng(37).uniform(-1, 1, shape))
+    z = torch.empty_like(r)
+    ms = S.apply_profile(r, z)
+    assert len(ms) == 4 and min(ms) >= 0.0
+    if smoother == "ilu0":
+        assert ms[3] > 0.0
+    np.testing.assert_array_equal(C(z), C(S.apply(r)))
