@@ -20,8 +20,8 @@ struct ntd_handle {
     double *d, *ax, *ay, *az;                 // bands of A
     double *e1, *mv, *f2, *dT, *dP, *xP;      // factors (FP64, natural layout) and setup state
     double *r, *z, *p, *q;                    // PCG vectors
-    void *pmv, *pa, *pu, *pf2, *pg3, *pZ;     // packed apply arrays (float in MIXED, else double)
-    double *tw;                               // FP64 twist records, 4 per line
+    void *rec;                                // line records of the apply (float in MIXED)
+    void *pZ, *rp;                            // packed result and right-hand side
     void *scratch;                            // setup planes / packed apply planes
     double *partials;
     Scalars *sc;
@@ -50,10 +50,13 @@ struct Carver {
 bool grid_ok(int nx, int ny, int nz) {
     if (nx < 1 || ny < 1 || nz < 1) return false;
     if (nx > NTD_MAX_NX || ntd::epl_for(nx) == 0) return false;
-    // the sweeps address FP64 arrays (natural and packed) with 32-bit byte offsets
-    long long N = (long long)nx * ny * nz;
-    long long npack = (long long)ny * nz * 64 * ntd::epl_for(nx);
-    return N * 8 < 0x7fffffffLL && npack * 8 < 0x7fffffffLL;
+    // FP64 arrays are addressed with 32-bit byte offsets, the records and packed
+    // vectors of one plane too
+    const int epl = ntd::epl_for(nx);
+    const long long N = (long long)nx * ny * nz;
+    const long long npack = (long long)ny * nz * 64 * epl;
+    const long long plane_rec = (long long)ny * ntd::rec_bytes(sizeof(double), epl);
+    return N * 8 < 0x7fffffffLL && npack * 8 < 0x7fffffffLL && plane_rec < 0x7fffffffLL;
 }
 
 size_t layout(ntd_handle *h, void *ws, int nx, int ny, int nz, int prec, int smoother) {
@@ -65,9 +68,9 @@ size_t layout(ntd_handle *h, void *ws, int nx, int ny, int nz, int prec, int smo
     double **f64[] = {&h->d, &h->ax, &h->ay, &h->az, &h->e1, &h->mv, &h->f2,
                       &h->dT, &h->dP, &h->xP, &h->r, &h->z, &h->p, &h->q};
     for (double **a : f64) *a = c.take<double>(N);
-    void **pk[] = {&h->pmv, &h->pa, &h->pu, &h->pf2, &h->pg3, &h->pZ};
-    for (void **a : pk) *a = (void *)c.take<char>(npack * tsz);
-    h->tw = c.take<double>(4 * (size_t)ny * nz);
+    h->rec = (void *)c.take<char>((size_t)ny * nz * ntd::rec_bytes((unsigned)tsz, ntd::epl_for(nx)));
+    h->pZ = (void *)c.take<char>(npack * tsz);
+    h->rp = (void *)c.take<char>(npack * tsz);
     h->dt = h->dtinv = h->zi = h->tv = nullptr;
     if (smoother == NTD_SMOOTHER_ILU0) {
         double **ilu[] = {&h->dt, &h->dtinv, &h->zi, &h->tv};
@@ -76,7 +79,7 @@ size_t layout(ntd_handle *h, void *ws, int nx, int ny, int nz, int prec, int smo
     const size_t setup_scr = 6 * (size_t)nxy * sizeof(double);
     const size_t apply_scr = 2 * (size_t)ny * lane_slots * tsz;
     h->scratch = (void *)c.take<char>(setup_scr > apply_scr ? setup_scr : apply_scr);
-    h->partials = c.take<double>(ntd::kMaxBlocks + ntd::kApplySlots);
+    h->partials = c.take<double>(ntd::kMaxBlocks);
     h->sc = c.take<Scalars>(1);
     h->flag = c.take<int>(4);
     return c.off;
@@ -96,42 +99,81 @@ ntd::Grid grid_of(const ntd_handle *h) {
 }
 
 template <typename T>
-ntd::ApplyArgs<T> apply_args(const ntd_handle *h, const double *r, double *z, double *partials) {
+ntd::ApplyArgs<T> apply_args(const ntd_handle *h) {
     ntd::ApplyArgs<T> a;
     a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
-    a.pmv = (const T *)h->pmv; a.pa = (const T *)h->pa; a.pu = (const T *)h->pu;
-    a.pf2 = (const T *)h->pf2; a.pg3 = (const T *)h->pg3; a.tw = h->tw;
-    a.r = r; a.Z = (T *)h->pZ; a.zout = z; a.scratch = (T *)h->scratch; a.partials = partials;
+    a.rec = h->rec; a.rp = (const T *)h->rp; a.Z = (T *)h->pZ; a.scratch = (T *)h->scratch;
     return a;
 }
 
-template <typename T>
-ntd::PackArgs<T> pack_args(const ntd_handle *h) {
-    ntd::PackArgs<T> p;
-    p.nx = h->nx; p.nlines = (long long)h->ny * h->nz;
+ntd::PackArgs pack_args(const ntd_handle *h) {
+    ntd::PackArgs p;
+    p.nx = h->nx; p.ny = h->ny; p.nz = h->nz;
     p.e1 = h->e1; p.mv = h->mv; p.f2 = h->f2; p.g3 = h->az;
-    p.pmv = (T *)h->pmv; p.pa = (T *)h->pa; p.pu = (T *)h->pu; p.pf2 = (T *)h->pf2;
-    p.pg3 = (T *)h->pg3; p.tw = h->tw;
+    p.rec = h->rec;
     return p;
 }
 
-// z = B^{-1} r; partials (if not null) receive the 6 per-wave partials of r.z;
-// ev (if not null, 4 events) brackets the three launches.
-int apply_internal(ntd_handle *h, const double *r, double *z, double *partials, hipStream_t s,
-                   hipEvent_t *ev = nullptr, const double *zbase = nullptr,
-                   const double *rdot = nullptr) {
-    if (h->prec == NTD_PREC_FP64) {
-        auto a = apply_args<double>(h, r, z, partials);
-        a.zbase = zbase;
-        a.rdot = rdot;
-        CK(ntd::launch_apply_f64(a, h->epl, s, ev));
-    } else {
-        auto a = apply_args<float>(h, r, z, partials);
-        a.zbase = zbase;
-        a.rdot = rdot;
-        CK(ntd::launch_apply_f32(a, h->epl, s, ev));
-    }
+template <typename T>
+ntd::XferArgs<T> xfer_args(const ntd_handle *h) {
+    ntd::XferArgs<T> x;
+    x.nx = h->nx; x.ny = h->ny; x.nz = h->nz;
+    x.r = nullptr; x.zi = nullptr;
+    x.d = h->d; x.ax = h->ax; x.ay = h->ay; x.az = h->az;
+    x.rp = (T *)h->rp; x.Z = (const T *)h->pZ; x.zout = nullptr; x.partials = nullptr;
+    return x;
+}
+
+// z = B^{-1} rhs with rhs = r, or r - A zi when zi is given (then z = zi +
+// B^{-1}(r - A zi)): pack the right-hand side, run the three sweep launches,
+// unpack.  With partials, the unpack also writes per-block partials of r.z and
+// *np their count.  ev (if not null, 6 events): ev[0] before the pack, ev[1..4]
+// bracket the sweeps, ev[5] after the unpack.
+// Launchers of one precision, picked by overload.
+hipError_t pack_rhs(const ntd::XferArgs<float> &x, int epl, hipStream_t s) {
+    return ntd::launch_pack_rhs_f32(x, epl, s);
+}
+hipError_t pack_rhs(const ntd::XferArgs<double> &x, int epl, hipStream_t s) {
+    return ntd::launch_pack_rhs_f64(x, epl, s);
+}
+hipError_t sweeps(const ntd::ApplyArgs<float> &a, int epl, hipStream_t s, hipEvent_t *ev) {
+    return ntd::launch_apply_f32(a, epl, s, ev);
+}
+hipError_t sweeps(const ntd::ApplyArgs<double> &a, int epl, hipStream_t s, hipEvent_t *ev) {
+    return ntd::launch_apply_f64(a, epl, s, ev);
+}
+hipError_t unpack(const ntd::XferArgs<float> &x, int epl, hipStream_t s, int *np) {
+    return ntd::launch_unpack_f32(x, epl, s, np);
+}
+hipError_t unpack(const ntd::XferArgs<double> &x, int epl, hipStream_t s, int *np) {
+    return ntd::launch_unpack_f64(x, epl, s, np);
+}
+
+// z = B^{-1} rhs with rhs = r, or r - A zi when zi is given (then z = zi +
+// B^{-1}(r - A zi)): pack the right-hand side, run the three sweep launches,
+// unpack.  With partials, the unpack also writes per-block partials of r.z and
+// *np their count.  ev (if not null, 6 events): ev[0] before the pack, ev[1..4]
+// bracket the sweeps, ev[5] after the unpack.
+template <typename T>
+int ntd_solve(ntd_handle *h, const double *r, const double *zi, double *z, double *partials,
+              int *np, hipStream_t s, hipEvent_t *ev) {
+    ntd::XferArgs<T> x = xfer_args<T>(h);
+    x.r = r;
+    x.zi = zi;
+    if (ev) CK(hipEventRecord(ev[0], s));
+    CK(pack_rhs(x, h->epl, s));
+    CK(sweeps(apply_args<T>(h), h->epl, s, ev ? ev + 1 : nullptr));
+    x.zout = z;
+    x.partials = partials;
+    CK(unpack(x, h->epl, s, np));
+    if (ev) CK(hipEventRecord(ev[5], s));
     return NTD_OK;
+}
+
+int ntd_solve_any(ntd_handle *h, const double *r, const double *zi, double *z, double *partials,
+                  int *np, hipStream_t s, hipEvent_t *ev) {
+    if (h->prec == NTD_PREC_FP64) return ntd_solve<double>(h, r, zi, z, partials, np, s, ev);
+    return ntd_solve<float>(h, r, zi, z, partials, np, s, ev);
 }
 
 // z = B_ILU^{-1} r (block-diagonal ILU(0)).
@@ -141,24 +183,28 @@ int ilu_internal(ntd_handle *h, const double *r, double *z, hipStream_t s) {
 }
 
 // The handle's preconditioner: B^{-1} r, or with the smoother the combination
-// of eq. com evaluated as z = B_ILU^{-1} r + B^{-1}(r - A B_ILU^{-1} r), the sum
-// and the partials of r.z fused into the last sweep.
-int precond_internal(ntd_handle *h, const double *r, double *z, double *partials, hipStream_t s,
-                     hipEvent_t *ev = nullptr) {
-    if (h->smoother != NTD_SMOOTHER_ILU0) return apply_internal(h, r, z, partials, s, ev);
+// of eq. com evaluated as z = B_ILU^{-1} r + B^{-1}(r - A B_ILU^{-1} r).
+// ev: as for ntd_solve, with ev[0] recorded before the ILU(0) sweeps.
+int precond_internal(ntd_handle *h, const double *r, double *z, double *partials, int *np,
+                     hipStream_t s, hipEvent_t *ev = nullptr) {
+    if (h->smoother != NTD_SMOOTHER_ILU0) return ntd_solve_any(h, r, nullptr, z, partials, np, s, ev);
+    if (ev) CK(hipEventRecord(ev[0], s));
     int st = ilu_internal(h, r, h->zi, s);
     if (st != NTD_OK) return st;
-    ntd::Grid g = grid_of(h);
-    CK(ntd::launch_spmv_residual(g, h->d, h->ax, h->ay, h->az, h->zi, r, h->tv, s));
-    return apply_internal(h, h->tv, z, partials, s, ev, h->zi, r);
+    hipEvent_t ev2[6];
+    if (ev) {
+        for (int i = 1; i < 6; ++i) ev2[i] = ev[i];
+        ev2[0] = ev[6];  // a spare event: the pack start inside the smoother region
+    }
+    return ntd_solve_any(h, r, h->zi, z, partials, np, s, ev ? ev2 : nullptr);
 }
 
-// Pack the FP64 natural-layout factors into the apply layout and precision.
+// Pack the FP64 natural-layout factors into the line records of the apply.
 int pack_factors(ntd_handle *h, hipStream_t s) {
     if (h->prec == NTD_PREC_FP64) {
-        CK(ntd::launch_pack_f64(pack_args<double>(h), h->epl, s));
+        CK(ntd::launch_pack_f64(pack_args(h), h->epl, s));
     } else {
-        CK(ntd::launch_pack_f32(pack_args<float>(h), h->epl, s));
+        CK(ntd::launch_pack_f32(pack_args(h), h->epl, s));
     }
     return NTD_OK;
 }
@@ -258,6 +304,10 @@ int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const 
     HK(hipStreamSynchronize(s));
     if (hflag & ntd::kFlagNotSPD) FAIL(NTD_ENOTSPD);
     if ((st = pack_factors(h, s)) != NTD_OK) goto fail;
+    // unused slots of the packed right-hand side are never written by the
+    // packing of a right-hand side and must read as 0
+    HK(ntd::launch_fill((double *)h->rp, 0.0,
+                        h->npack * (h->prec == NTD_PREC_FP64 ? 8 : 4) / 8, s));
     HK(hipStreamSynchronize(s));
     *out = h;
     return NTD_OK;
@@ -270,12 +320,12 @@ fail:
 
 int ntd_apply_precond(ntd_handle *h, const double *r, double *z, void *stream) {
     if (!h || !r || !z || r == z) return NTD_EINVAL;
-    return precond_internal(h, r, z, nullptr, S(stream));
+    return precond_internal(h, r, z, nullptr, nullptr, S(stream));
 }
 
 int ntd_apply_ntd(ntd_handle *h, const double *r, double *z, void *stream) {
     if (!h || !r || !z || r == z) return NTD_EINVAL;
-    return apply_internal(h, r, z, nullptr, S(stream));
+    return ntd_solve_any(h, r, nullptr, z, nullptr, nullptr, S(stream), nullptr);
 }
 
 int ntd_apply_ilu0(ntd_handle *h, const double *r, double *z, void *stream) {
@@ -286,17 +336,21 @@ int ntd_apply_ilu0(ntd_handle *h, const double *r, double *z, void *stream) {
 int ntd_apply_profile(ntd_handle *h, const double *r, double *z, float *ms, void *stream) {
     if (!h || !r || !z || r == z || !ms) return NTD_EINVAL;
     hipStream_t s = S(stream);
-    hipEvent_t ev[5];  // ev[0]: before the smoother part; ev[1..4] bracket the sweeps
-    int made = 0, st = NTD_OK;
-    for (; made < 5; ++made)
+    // ev[0]: start; ev[1..4] bracket the sweeps; ev[5]: end; ev[6]: spare
+    hipEvent_t ev[7];
+    int made = 0, st = NTD_OK, np = 0;
+    for (; made < 7; ++made)
         if (hipEventCreate(&ev[made]) != hipSuccess) { st = NTD_EHIP; break; }
-    if (st == NTD_OK && hipEventRecord(ev[0], s) != hipSuccess) st = NTD_EHIP;
     // The preconditioner as the PCG loop launches it, r.z partials included.
-    if (st == NTD_OK) st = precond_internal(h, r, z, h->partials, s, ev + 1);
-    if (st == NTD_OK && hipEventSynchronize(ev[4]) != hipSuccess) st = NTD_EHIP;
+    if (st == NTD_OK) st = precond_internal(h, r, z, h->partials, &np, s, ev);
+    if (st == NTD_OK && hipEventSynchronize(ev[5]) != hipSuccess) st = NTD_EHIP;
     for (int i = 0; st == NTD_OK && i < 3; ++i)
         if (hipEventElapsedTime(&ms[i], ev[i + 1], ev[i + 2]) != hipSuccess) st = NTD_EHIP;
-    if (st == NTD_OK && hipEventElapsedTime(&ms[3], ev[0], ev[1]) != hipSuccess) st = NTD_EHIP;
+    float pre = 0.0f, post = 0.0f;
+    if (st == NTD_OK && (hipEventElapsedTime(&pre, ev[0], ev[1]) != hipSuccess ||
+                         hipEventElapsedTime(&post, ev[4], ev[5]) != hipSuccess))
+        st = NTD_EHIP;
+    ms[3] = pre + post;
     for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
     return st;
 }
@@ -330,7 +384,7 @@ int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int max
     ntd::Grid g = grid_of(h);
     *iters = 0;
     *relres = 0.0;
-    int st;
+    int st, np = 0;
     double bb = 0.0;
     CK(hipMemsetAsync(h->sc, 0, sizeof(Scalars), s));
     if ((st = norm2(h, b, &bb, s)) != NTD_OK) return st;
@@ -341,10 +395,10 @@ int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int max
         CK(hipStreamSynchronize(s));
         return NTD_OK;
     }
-    if ((st = precond_internal(h, h->r, h->z, h->partials, s)) != NTD_OK) return st;
-    CK(ntd::launch_finalize(h->partials, 6, h->sc, ntd::kOpRhoInit, s));
+    if ((st = precond_internal(h, h->r, h->z, h->partials, &np, s)) != NTD_OK) return st;
+    CK(ntd::launch_finalize(h->partials, np, h->sc, ntd::kOpRhoInit, s));
     CK(ntd::launch_copy(h->p, h->z, N, s));
-    int it = 0, status = NTD_OK, np = 0;
+    int it = 0, status = NTD_OK;
     Scalars hs;
     for (;;) {
         if (it >= maxit) { status = NTD_ENOCONV; break; }
@@ -360,8 +414,8 @@ int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int max
             if ((st = true_relres(h, b, x, bn, &tr, s)) != NTD_OK) return st;
             if (tr <= tol) break;
         }
-        if ((st = precond_internal(h, h->r, h->z, h->partials, s)) != NTD_OK) return st;
-        CK(ntd::launch_finalize(h->partials, 6, h->sc, ntd::kOpBeta, s));
+        if ((st = precond_internal(h, h->r, h->z, h->partials, &np, s)) != NTD_OK) return st;
+        CK(ntd::launch_finalize(h->partials, np, h->sc, ntd::kOpBeta, s));
         CK(ntd::launch_xpay(h->p, h->z, h->sc, N, s));
     }
     *iters = it;

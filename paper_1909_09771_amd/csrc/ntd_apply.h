@@ -1,0 +1,593 @@
+// ntd_apply.h -- the preconditioner apply z = B^{-1} r (arXiv:1909.09771, Sec. 2.2,
+// Algorithms 1-7) on packed line records, the packing of the factors into
+// those records, and the moves of right-hand side and result between the
+// natural FP64 layout and the packed one.
+//
+// A line step is a chain of dependent operations run by one wavefront, and a
+// wavefront issues at most one instruction every four cycles, so the step time
+// is its instruction count.  Everything here serves to keep that count low:
+//   * one record per line holds every factor the step reads (one buffer
+//     descriptor, one scalar offset per line, no per-array address updates);
+//   * the lane-level products of the recurrence coefficients do not depend on
+//     the right-hand side, so the multipliers of every scan stage are
+//     precomputed at packing: a stage is one zero-filling DPP move and one FMA;
+//   * the twist row (FP64) exchanges its neighbours with one permlane32 swap
+//     each way, and the twist and chain-B seed are inserted without branches;
+//   * the sweeps read a packed right-hand side in the sweep precision and write
+//     packed results only; the FP64 natural-layout gather, the ILU(0) base and
+//     the r.z partials live in bandwidth-bound kernels before and after them.
+#pragma once
+
+#include "ntd_sweep.h"
+
+namespace ntd {
+
+namespace {
+
+constexpr int kApplyThreads = 128;  // two wavefronts: the two level-2 half chains
+constexpr int kRowNewBcast0 = 0x150;  // broadcast lane 0 of each row within the row
+
+// ---------------------------------------------------------------------------
+// Cross-lane moves of the apply.
+// ---------------------------------------------------------------------------
+
+// DPP move in which a lane whose source lane does not exist reads 0.
+template <int CTRL>
+__device__ __forceinline__ float zmov(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double zmov(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, true);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// permlane32 swap of v with itself: .lo gives every lane of the low half the
+// value of the lane 32 above it, .hi gives every lane of the high half the value
+// of the lane 32 below it.
+struct Swap32f { float lo, hi; };
+__device__ __forceinline__ Swap32f swap32(float v) {
+    const unsigned u = __builtin_bit_cast(unsigned, v);
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return {__builtin_bit_cast(float, (unsigned)r[1]), __builtin_bit_cast(float, (unsigned)r[0])};
+}
+struct Swap32d { double lo, hi; };
+__device__ __forceinline__ Swap32d swap32(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned l = (unsigned)u, h = (unsigned)(u >> 32);
+    const auto rl = __builtin_amdgcn_permlane32_swap(l, l, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(h, h, false, false);
+    const unsigned long long lo = ((unsigned long long)(unsigned)rh[1] << 32) | (unsigned)rl[1];
+    const unsigned long long hi = ((unsigned long long)(unsigned)rh[0] << 32) | (unsigned)rl[0];
+    return {__builtin_bit_cast(double, lo), __builtin_bit_cast(double, hi)};
+}
+
+// Rows 0 and 2 receive rows 1 and 3 (lane i gets lane i+16); rows 1 and 3
+// keep their own values.
+__device__ __forceinline__ float rows_down16(float v) {
+    const unsigned u = __builtin_bit_cast(unsigned, v);
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return __builtin_bit_cast(float, (unsigned)r[1]);
+}
+__device__ __forceinline__ double rows_down16(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned l = (unsigned)u, h = (unsigned)(u >> 32);
+    const auto rl = __builtin_amdgcn_permlane16_swap(l, l, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(h, h, false, false);
+    return __builtin_bit_cast(double,
+                              ((unsigned long long)(unsigned)rh[1] << 32) | (unsigned)rl[1]);
+}
+
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---------------------------------------------------------------------------
+// Level 1: the twisted solve of one line on the packed layout.
+// ---------------------------------------------------------------------------
+
+// Per-lane multipliers (kRecMul values) of the two 32-lane scans.  With A_l the
+// product of the lane's lower-sweep coefficients a and U_l that of its upper
+// coefficients u, entry q < 4 of the forward set is the product of A over the
+// 2^q lanes ending at this one (clipped at the start of its 16-lane row), entry
+// 4 the product over the row up to this lane (0 in rows 0 and 2, which the
+// cross-row step does not feed); the backward set 5..9 is the same over the
+// lanes starting at this one toward the end of the row (entry 9 is 0 in rows 1
+// and 3).  Entry 10 is the chain-B seed: in lane 63 the coefficient u of
+// element j+1 (its coupling to the twist value), 0 elsewhere; in the packed u
+// array that coefficient is replaced by 0.
+template <typename T>
+__device__ __forceinline__ T scan_fwd(T B, const T (&m)[kRecMul]) {
+    B = fmad(zmov<kRowShr1>(B), m[0], B);
+    B = fmad(zmov<kRowShr2>(B), m[1], B);
+    B = fmad(zmov<kRowShr4>(B), m[2], B);
+    B = fmad(zmov<kRowShr8>(B), m[3], B);
+    return fmad(zmov<kRowBcast15>(B), m[4], B);
+}
+
+template <typename T>
+__device__ __forceinline__ T scan_bwd(T G, const T (&m)[kRecMul]) {
+    G = fmad(zmov<kRowShl1>(G), m[5], G);
+    G = fmad(zmov<kRowShl2>(G), m[6], G);
+    G = fmad(zmov<kRowShl4>(G), m[7], G);
+    G = fmad(zmov<kRowShl8>(G), m[8], G);
+    return fmad(zmov<kRowNewBcast0>(rows_down16(G)), m[9], G);
+}
+
+// x = T^{-1} y for the line held by the wavefront (layout of LineGeom), given
+// per slot a, 1/M and u as packed, the lane's multipliers, and the FP64 twist
+// row (1/M_j and the couplings of element j to j-1 and j+1).
+// Lower sweep: g_c = a_c g_{c-1} + y_c/M_c along each chain toward the twist,
+// the twist row taking both neighbours in FP64; upper sweep: x_c = u_c x_{c+1}
+// + g_c from the twist outward.
+template <typename T, int EPL>
+__device__ __forceinline__ void solve_rec(const T (&a)[EPL], const T (&mv)[EPL], const T (&u)[EPL],
+                                          const T (&m)[kRecMul], double mvj, double cpj, double cnj,
+                                          const T (&y)[EPL], T (&x)[EPL]) {
+    constexpr int L = EPL - 1;
+    const int lane = threadIdx.x & 63;
+    T g[EPL];
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) g[s] = mv[s] * y[s];
+    T B = g[0];
+#pragma unroll
+    for (int s = 1; s < EPL; ++s) B = fmad(a[s], B, g[s]);
+    B = scan_fwd(B, m);
+    // lane 0 reads 0; lane 32 reads the end of chain A, which the zero a of
+    // chain B's first element (or the unused slots before it) discards
+    T carry = zmov<kWaveShr1>(B);
+    T gm1 = carry;
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) {
+        if (s == L) gm1 = carry;
+        g[s] = fmad(a[s], carry, g[s]);
+        carry = g[s];
+    }
+    // twist element j: lane 31, slot L; element j+1 ends chain B in lane 63
+    const T gB = swap32(g[L]).lo;
+    const double gj = mvj * ((double)y[L] - cpj * (double)gm1 - cnj * (double)gB);
+    const T xj = (T)gj;
+    g[L] = lane == 31 ? xj : g[L];
+    g[L] = fmad(m[10], swap32(xj).hi, g[L]);
+    T G = g[L];
+#pragma unroll
+    for (int s = L - 1; s >= 0; --s) G = fmad(u[s], G, g[s]);
+    G = scan_bwd(G, m);
+    // lane 63 reads 0; lane 31 reads chain B, discarded by u = 0 at the twist
+    T xn = zmov<kWaveShl1>(G);
+#pragma unroll
+    for (int s = L; s >= 0; --s) {
+        x[s] = fmad(u[s], xn, g[s]);
+        xn = x[s];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The packed format seen by plane_solve.
+// ---------------------------------------------------------------------------
+
+template <typename T, int EPL>
+struct RecFmt {
+    using Ty = T;
+    static constexpr int kEPL = EPL;
+    static constexpr unsigned kArr = rec_arr_bytes(sizeof(T), EPL);
+    static constexpr unsigned kMul = rec_mul_off(sizeof(T), EPL);
+    static constexpr unsigned kTw = rec_tw_off(sizeof(T), EPL);
+    static constexpr unsigned kRec = rec_bytes(sizeof(T), EPL);
+    static constexpr unsigned kLine = 64u * EPL * sizeof(T);
+    rsrc_t rec;       // the records of the plane
+    rsrc_t W;         // lower-sweep results of the plane
+    unsigned vA;      // this lane's byte offset inside a packed array
+    unsigned vM;      // this lane's multipliers inside a record
+    __device__ RecFmt() {
+        const unsigned lane = threadIdx.x & 63;
+        vA = lane * EPL * (unsigned)sizeof(T);
+        vM = kMul + lane * kRecMul * (unsigned)sizeof(T);
+    }
+    __device__ void load_coef(int m, LineIn<T, EPL> &in) const {
+        const unsigned so = (unsigned)m * kRec;
+        vload(rec, vA + kRecMv * kArr, so, in.c0);
+        vload(rec, vA + kRecA * kArr, so, in.c1);
+        vload(rec, vA + kRecU * kArr, so, in.c2);
+        vload(rec, vM, so, in.mul);
+        double tw[2];
+        vload(rec, kTw, so, tw);
+        in.mvj = tw[0];
+        in.cpj = tw[1];
+        in.cnj = bload((double *)nullptr, rec, kTw + 16u, so);
+    }
+    // y-coupling of line m to line m+1 (up) or m-1 (down)
+    __device__ void load_fc(int m, bool up, T (&f)[EPL]) const {
+        vload(rec, vA + (up ? kRecFup : kRecFdn) * kArr, (unsigned)m * kRec, f);
+    }
+    __device__ void load_w(int m, T (&w)[EPL]) const { vload(W, vA, (unsigned)m * kLine, w); }
+    __device__ void store_w(int m, const T (&w)[EPL]) const {
+        vstore(W, vA, (unsigned)m * kLine, w);
+    }
+    __device__ void solve(const LineIn<T, EPL> &in, const T (&y)[EPL], T (&x)[EPL]) const {
+        solve_rec(in.c1, in.c0, in.c2, in.mul, in.mvj, in.cpj, in.cnj, y, x);
+    }
+};
+
+// Prefetch depth of the sweeps: two lines ahead while three input buffers fit
+// the register file comfortably, else one.
+template <typename T, int EPL>
+constexpr int kApplyDepth = (sizeof(T) * EPL <= 16) ? 2 : 1;
+
+// ---------------------------------------------------------------------------
+// Level 3: three launches over the packed vectors.
+// ---------------------------------------------------------------------------
+
+template <typename T, int EPL>
+__device__ __forceinline__ rsrc_t plane_rsrc(const T *base, int k, int ny) {
+    return make_rsrc(base + (size_t)k * ny * 64 * EPL);
+}
+
+template <typename T, int EPL>
+__device__ __forceinline__ RecFmt<T, EPL> rec_fmt(const ApplyArgs<T> &a, int k, rsrc_t W) {
+    RecFmt<T, EPL> F;
+    F.rec = make_rsrc((const char *)a.rec + (size_t)k * a.ny * RecFmt<T, EPL>::kRec);
+    F.W = W;
+    return F;
+}
+
+// Lower level-3 step of plane k: rhs = r_k - g * z_kn, with g the z-coupling of
+// plane k toward its finished neighbour kn (absent for the first plane).
+template <typename T, int EPL, bool HAS>
+struct PolLower {
+    rsrc_t rp, Zn, Zk;
+    unsigned vA, vG;  // lane offsets: in a packed line; of the coupling array in a record
+    __device__ void load_rhs(int m, const RecFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
+        constexpr unsigned kLine = RecFmt<T, EPL>::kLine;
+        vload(rp, vA, (unsigned)m * kLine, in.a2);
+        if constexpr (HAS) {
+            vload(F.rec, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.a0);
+            vload(Zn, vA, (unsigned)m * kLine, in.a1);
+        }
+    }
+    __device__ T rhs(const LineIn<T, EPL> &in, int s) const {
+        if constexpr (HAS) return fmad(-in.a0[s], in.a1[s], in.a2[s]);
+        else return in.a2[s];
+    }
+    __device__ void load_out(int, const RecFmt<T, EPL> &, LineIn<T, EPL> &) const {}
+    __device__ void out(int m, const RecFmt<T, EPL> &, const T (&x)[EPL], const LineIn<T, EPL> &) {
+        vstore(Zk, vA, (unsigned)m * RecFmt<T, EPL>::kLine, x);
+    }
+};
+
+// The twist plane: rhs = r - g_dn * z_{k-1} - g_up * z_{k+1}; the result is final.
+template <typename T, int EPL>
+struct PolTwist {
+    rsrc_t rp, Zlo, Zhi, Zk;
+    unsigned vA, vGdn, vGup;
+    bool lo_nb, hi_nb;
+    __device__ void load_rhs(int m, const RecFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
+        constexpr unsigned kLine = RecFmt<T, EPL>::kLine;
+        const unsigned so = (unsigned)m * RecFmt<T, EPL>::kRec;
+        vload(rp, vA, (unsigned)m * kLine, in.a2);
+        if (lo_nb) {
+            vload(F.rec, vGdn, so, in.a0);
+            vload(Zlo, vA, (unsigned)m * kLine, in.a1);
+        } else {
+            zero_line(in.a0);
+            zero_line(in.a1);
+        }
+        if (hi_nb) {
+            vload(F.rec, vGup, so, in.a3);
+            vload(Zhi, vA, (unsigned)m * kLine, in.w);
+        } else {
+            zero_line(in.a3);
+            zero_line(in.w);
+        }
+    }
+    __device__ T rhs(const LineIn<T, EPL> &in, int s) const {
+        return fmad(-in.a3[s], in.w[s], fmad(-in.a0[s], in.a1[s], in.a2[s]));
+    }
+    __device__ void load_out(int, const RecFmt<T, EPL> &, LineIn<T, EPL> &) const {}
+    __device__ void out(int m, const RecFmt<T, EPL> &, const T (&x)[EPL], const LineIn<T, EPL> &) {
+        vstore(Zk, vA, (unsigned)m * RecFmt<T, EPL>::kLine, x);
+    }
+};
+
+// Upper level-3 step of plane k: c = Pt_k^{-1}(g * x_kn) with kn the final
+// neighbour toward the twist plane; x_k = z_k - c over Z.
+template <typename T, int EPL>
+struct PolUpper {
+    rsrc_t Zn, Zk;
+    unsigned vA, vG;
+    __device__ void load_rhs(int m, const RecFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
+        vload(F.rec, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.a0);
+        vload(Zn, vA, (unsigned)m * RecFmt<T, EPL>::kLine, in.a1);
+    }
+    __device__ T rhs(const LineIn<T, EPL> &in, int s) const { return in.a0[s] * in.a1[s]; }
+    __device__ void load_out(int m, const RecFmt<T, EPL> &, LineIn<T, EPL> &in) const {
+        vload(Zk, vA, (unsigned)m * RecFmt<T, EPL>::kLine, in.a2);
+    }
+    __device__ void out(int m, const RecFmt<T, EPL> &, const T (&c)[EPL], const LineIn<T, EPL> &in) {
+        T xv[EPL];
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) xv[s] = in.a2[s] - c[s];
+        vstore(Zk, vA, (unsigned)m * RecFmt<T, EPL>::kLine, xv);
+    }
+};
+
+template <typename T, int EPL, bool HAS>
+__device__ __forceinline__ void lower_plane(const ApplyArgs<T> &a, int k, int kn, T *lds) {
+    constexpr unsigned kArr = RecFmt<T, EPL>::kArr;
+    PolLower<T, EPL, HAS> pol;
+    pol.rp = plane_rsrc<T, EPL>(a.rp, k, a.ny);
+    pol.Zk = plane_rsrc<T, EPL>(a.Z, k, a.ny);
+    pol.Zn = plane_rsrc<T, EPL>(a.Z, HAS ? kn : k, a.ny);
+    const RecFmt<T, EPL> F = rec_fmt<T, EPL>(a, k, pol.Zk);
+    pol.vA = F.vA;
+    pol.vG = F.vA + (kn < k ? kRecGdn : kRecGup) * kArr;
+    plane_solve<kApplyDepth<T, EPL>>(a.ny, F, pol, lds);
+}
+
+// Lower level-3 sweep of one half: block 0 takes planes 0..j3-1 upward, block 1
+// planes nz-1..j3+1 downward; z_k = Pt_k^{-1}(r_k - g * z_{k-+1}) into Z.
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_lower(ApplyArgs<T> a) {
+    __shared__ T lds[2 * 64 * EPL];
+    const int nz = a.nz, j3 = (nz - 1) / 2;
+    const int h = blockIdx.x;
+    const int dk = h == 0 ? 1 : -1;
+    const int k0 = h == 0 ? 0 : nz - 1;
+    if (h == 0 ? k0 >= j3 : k0 <= j3) return;
+    lower_plane<T, EPL, false>(a, k0, k0, lds);
+    for (int k = k0 + dk; h == 0 ? k < j3 : k > j3; k += dk) lower_plane<T, EPL, true>(a, k, k - dk, lds);
+}
+
+// The twist plane j3 takes both neighbours; its result is final.
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_twist(ApplyArgs<T> a) {
+    __shared__ T lds[2 * 64 * EPL];
+    constexpr unsigned kArr = RecFmt<T, EPL>::kArr;
+    const int nz = a.nz, k = (nz - 1) / 2;
+    PolTwist<T, EPL> pol;
+    pol.rp = plane_rsrc<T, EPL>(a.rp, k, a.ny);
+    pol.Zk = plane_rsrc<T, EPL>(a.Z, k, a.ny);
+    pol.lo_nb = k > 0;
+    pol.hi_nb = k < nz - 1;
+    pol.Zlo = plane_rsrc<T, EPL>(a.Z, pol.lo_nb ? k - 1 : k, a.ny);
+    pol.Zhi = plane_rsrc<T, EPL>(a.Z, pol.hi_nb ? k + 1 : k, a.ny);
+    const RecFmt<T, EPL> F = rec_fmt<T, EPL>(a, k, pol.Zk);
+    pol.vA = F.vA;
+    pol.vGdn = F.vA + kRecGdn * kArr;
+    pol.vGup = F.vA + kRecGup * kArr;
+    plane_solve<kApplyDepth<T, EPL>>(a.ny, F, pol, lds);
+}
+
+// Upper level-3 sweep: block 0 takes planes j3-1..0, block 1 planes j3+1..nz-1;
+// x_k = z_k - Pt_k^{-1}(g * x_{k+-1}), written over Z.
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_upper(ApplyArgs<T> a) {
+    __shared__ T lds[2 * 64 * EPL];
+    constexpr unsigned kArr = RecFmt<T, EPL>::kArr;
+    const int ny = a.ny, nz = a.nz, j3 = (nz - 1) / 2;
+    const int h = blockIdx.x;
+    const int dk = h == 0 ? -1 : 1;
+    const rsrc_t W = make_rsrc(a.scratch + (size_t)h * ny * 64 * EPL);
+    for (int k = j3 + dk; k >= 0 && k < nz; k += dk) {
+        const int kn = k - dk;  // final neighbour, toward the twist plane
+        PolUpper<T, EPL> pol;
+        pol.Zk = plane_rsrc<T, EPL>(a.Z, k, ny);
+        pol.Zn = plane_rsrc<T, EPL>(a.Z, kn, ny);
+        const RecFmt<T, EPL> F = rec_fmt<T, EPL>(a, k, W);
+        pol.vA = F.vA;
+        pol.vG = F.vA + (kn < k ? kRecGdn : kRecGup) * kArr;
+        plane_solve<kApplyDepth<T, EPL>>(ny, F, pol, lds);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Packing of the factors into the line records (one wavefront per line).
+// ---------------------------------------------------------------------------
+
+template <typename T, int EPL>
+__global__ void __launch_bounds__(256) k_pack(PackArgs p) {
+    using R = RecFmt<T, EPL>;
+    const long long line = blockIdx.x * 4LL + (threadIdx.x >> 6);
+    if (line >= (long long)p.ny * p.nz) return;  // whole wavefronts; no barrier below
+    const int n = p.nx, ny = p.ny;
+    const int k = (int)(line / ny), m = (int)(line - (long long)k * ny);
+    const long long nxy = (long long)n * ny;
+    const LineGeom G(n, EPL);
+    const int lane = threadIdx.x & 63;
+    const int j = G.ca - 1;
+    const long long base = line * n;
+    double v[kRecArrays][EPL];
+    double seed = 0.0;
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) {
+        const int c = G.pos(s, EPL);
+        if (!G.ok(c)) {  // identity slot
+            v[kRecMv][s] = 0.0; v[kRecA][s] = 1.0; v[kRecU][s] = 0.0;
+            v[kRecFdn][s] = v[kRecFup][s] = v[kRecGdn][s] = v[kRecGup][s] = 0.0;
+            continue;
+        }
+        const int e = G.elem(c);
+        const double M = p.mv[base + e];
+        double cp, cn;
+        if (G.half == 0) {
+            cp = c > 0 ? p.e1[base + e - 1] : 0.0;
+            cn = e == j ? 0.0 : p.e1[base + e];
+        } else {
+            cp = c > 0 ? p.e1[base + e] : 0.0;
+            cn = p.e1[base + e - 1];
+        }
+        v[kRecMv][s] = M;
+        v[kRecA][s] = -M * cp;
+        v[kRecU][s] = -M * cn;
+        if (G.half == 1 && c == G.cb - 1) {  // element j+1: its coupling seeds chain B
+            seed = v[kRecU][s];
+            v[kRecU][s] = 0.0;
+        }
+        v[kRecFdn][s] = m > 0 ? p.f2[base - n + e] : 0.0;
+        v[kRecFup][s] = m < ny - 1 ? p.f2[base + e] : 0.0;
+        v[kRecGdn][s] = k > 0 ? p.g3[base - nxy + e] : 0.0;
+        v[kRecGup][s] = k < p.nz - 1 ? p.g3[base + e] : 0.0;
+    }
+    // scan multipliers
+    double A = 1.0, U = 1.0;
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) {
+        A *= v[kRecA][s];
+        U *= v[kRecU][s];
+    }
+    double mul[kRecMul];
+    mul[0] = A;
+    mul[1] = mul[0] * dpp<kRowShr1>(1.0, mul[0]);
+    mul[2] = mul[1] * dpp<kRowShr2>(1.0, mul[1]);
+    mul[3] = mul[2] * dpp<kRowShr4>(1.0, mul[2]);
+    mul[4] = mul[3] * dpp<kRowShr8>(1.0, mul[3]);
+    mul[5] = U;
+    mul[6] = mul[5] * dpp<kRowShl1>(1.0, mul[5]);
+    mul[7] = mul[6] * dpp<kRowShl2>(1.0, mul[6]);
+    mul[8] = mul[7] * dpp<kRowShl4>(1.0, mul[7]);
+    mul[9] = mul[8] * dpp<kRowShl8>(1.0, mul[8]);
+    const int row = lane >> 4;
+    if ((row & 1) == 0) mul[4] = 0.0;  // the forward cross-row step feeds rows 1 and 3
+    else mul[9] = 0.0;                  // the backward one rows 0 and 2
+    mul[10] = lane == 63 ? seed : 0.0;
+    mul[11] = 0.0;
+    char *rec = (char *)p.rec + (size_t)line * R::kRec;
+#pragma unroll
+    for (int q = 0; q < kRecArrays; ++q) {
+        T *arr = (T *)(rec + q * R::kArr);
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) arr[lane * EPL + s] = (T)v[q][s];
+    }
+    T *mt = (T *)(rec + R::kMul);
+#pragma unroll
+    for (int q = 0; q < kRecMul; ++q) mt[lane * kRecMul + q] = (T)mul[q];
+    if (lane == 0) {
+        double *tw = (double *)(rec + R::kTw);
+        tw[0] = p.mv[base + j];
+        tw[1] = j > 0 ? p.e1[base + j - 1] : 0.0;
+        tw[2] = j < n - 1 ? p.e1[base + j] : 0.0;
+        tw[3] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Natural FP64 <-> packed moves (one thread per grid point).
+// ---------------------------------------------------------------------------
+
+// Packed slot of element i of a line (layout of LineGeom).
+template <int EPL>
+__device__ __forceinline__ int slot_of(int i, int n) {
+    const int ca = (n + 1) / 2, cb = n - ca;
+    if (i < ca) return i + 32 * EPL - ca;
+    return 32 * EPL + (n - 1 - i) + 32 * EPL - cb;
+}
+
+// rp = r (or r - A zi), packed in the sweep precision.  Grids hold fewer than
+// 2^28 points, so 32-bit indices suffice.
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kBlock) k_pack_rhs(XferArgs<T> x) {
+    const unsigned nx = (unsigned)x.nx, ny = (unsigned)x.ny, nz = (unsigned)x.nz;
+    const unsigned nxy = nx * ny, N = nxy * nz;
+    for (unsigned p = blockIdx.x * kBlock + threadIdx.x; p < N; p += gridDim.x * kBlock) {
+        const unsigned line = p / nx;
+        const unsigned i = p - line * nx;
+        double v = x.r[p];
+        if (x.zi) {
+            const unsigned jj = line % ny, kk = line / ny;
+            const double *z = x.zi;
+            double s = x.d[p] * z[p];
+            if (i > 0) s += x.ax[p - 1] * z[p - 1];
+            if (i + 1 < nx) s += x.ax[p] * z[p + 1];
+            if (jj > 0) s += x.ay[p - nx] * z[p - nx];
+            if (jj + 1 < ny) s += x.ay[p] * z[p + nx];
+            if (kk > 0) s += x.az[p - nxy] * z[p - nxy];
+            if (kk + 1 < nz) s += x.az[p] * z[p + nxy];
+            v -= s;
+        }
+        x.rp[line * (64u * EPL) + slot_of<EPL>((int)i, (int)nx)] = (T)v;
+    }
+}
+
+// Fixed-order block reduction of one double per thread; thread 0 gets the sum.
+__device__ __forceinline__ double block_sum_apply(double v) {
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// zout = Z (+ zi), natural FP64; per-block partials of r.zout.
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kBlock) k_unpack(XferArgs<T> x) {
+    const unsigned nx = (unsigned)x.nx;
+    const unsigned N = nx * (unsigned)x.ny * (unsigned)x.nz;
+    double acc = 0.0;
+    for (unsigned p = blockIdx.x * kBlock + threadIdx.x; p < N; p += gridDim.x * kBlock) {
+        const unsigned line = p / nx;
+        const unsigned i = p - line * nx;
+        double z = (double)x.Z[line * (64u * EPL) + slot_of<EPL>((int)i, (int)nx)];
+        if (x.zi) z += x.zi[p];
+        x.zout[p] = z;
+        if (x.partials) acc += x.r[p] * z;
+    }
+    if (x.partials) {
+        const double t = block_sum_apply(acc);
+        if (threadIdx.x == 0) x.partials[blockIdx.x] = t;
+    }
+}
+
+inline int xfer_blocks(long long N) {
+    long long b = (N + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > kMaxBlocks) b = kMaxBlocks;
+    return (int)b;
+}
+
+// The apply as three stream-ordered launches; ev (optional, 4 events) brackets
+// them for per-launch timing.
+template <typename T, int EPL>
+hipError_t apply_impl(const ApplyArgs<T> &a, hipStream_t s, hipEvent_t *ev) {
+    if (ev) (void)hipEventRecord(ev[0], s);
+    hipLaunchKernelGGL((k_apply_lower<T, EPL>), dim3(2), dim3(kApplyThreads), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    hipLaunchKernelGGL((k_apply_twist<T, EPL>), dim3(1), dim3(kApplyThreads), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[2], s);
+    hipLaunchKernelGGL((k_apply_upper<T, EPL>), dim3(2), dim3(kApplyThreads), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[3], s);
+    return hipGetLastError();
+}
+
+template <typename T, int EPL>
+hipError_t pack_impl(const PackArgs &p, hipStream_t s) {
+    const long long nlines = (long long)p.ny * p.nz;
+    hipLaunchKernelGGL((k_pack<T, EPL>), dim3((unsigned)((nlines + 3) / 4)), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+template <typename T, int EPL>
+hipError_t pack_rhs_impl(const XferArgs<T> &x, hipStream_t s) {
+    const long long N = (long long)x.nx * x.ny * x.nz;
+    hipLaunchKernelGGL((k_pack_rhs<T, EPL>), dim3(xfer_blocks(N)), dim3(kBlock), 0, s, x);
+    return hipGetLastError();
+}
+
+template <typename T, int EPL>
+hipError_t unpack_impl(const XferArgs<T> &x, hipStream_t s, int *np) {
+    const long long N = (long long)x.nx * x.ny * x.nz;
+    const int nb = xfer_blocks(N);
+    if (np) *np = x.partials ? nb : 0;
+    hipLaunchKernelGGL((k_unpack<T, EPL>), dim3(nb), dim3(kBlock), 0, s, x);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+}  // namespace ntd

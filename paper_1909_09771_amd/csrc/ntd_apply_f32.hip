@@ -1,5 +1,6 @@
-// ntd_apply_f32.hip -- instantiation of the preconditioner apply in float.
-#include "ntd_sweep.h"
+// ntd_apply_f32.hip -- instantiation of the preconditioner apply, the factor
+// packing and the natural/packed moves in float.
+#include "ntd_apply.h"
 
 namespace ntd {
 
@@ -12,9 +13,27 @@ hipError_t launch_apply_f32(const ApplyArgs<float> &a, int epl, hipStream_t s, h
     }
 }
 
-hipError_t launch_pack_f32(const PackArgs<float> &p, int epl, hipStream_t s) {
+hipError_t launch_pack_f32(const PackArgs &p, int epl, hipStream_t s) {
     switch (epl) {
 #define NTD_CASE(E) case E: return pack_impl<float, E>(p, s);
+        NTD_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pack_rhs_f32(const XferArgs<float> &x, int epl, hipStream_t s) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return pack_rhs_impl<float, E>(x, s);
+        NTD_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_unpack_f32(const XferArgs<float> &x, int epl, hipStream_t s, int *np) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return unpack_impl<float, E>(x, s, np);
         NTD_EPL_LIST(NTD_CASE)
 #undef NTD_CASE
     default: return hipErrorInvalidValue;

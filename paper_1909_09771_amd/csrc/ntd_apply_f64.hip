@@ -1,5 +1,6 @@
-// ntd_apply_f64.hip -- instantiation of the preconditioner apply in double.
-#include "ntd_sweep.h"
+// ntd_apply_f64.hip -- instantiation of the preconditioner apply, the factor
+// packing and the natural/packed moves in double.
+#include "ntd_apply.h"
 
 namespace ntd {
 
@@ -12,9 +13,27 @@ hipError_t launch_apply_f64(const ApplyArgs<double> &a, int epl, hipStream_t s, 
     }
 }
 
-hipError_t launch_pack_f64(const PackArgs<double> &p, int epl, hipStream_t s) {
+hipError_t launch_pack_f64(const PackArgs &p, int epl, hipStream_t s) {
     switch (epl) {
 #define NTD_CASE(E) case E: return pack_impl<double, E>(p, s);
+        NTD_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pack_rhs_f64(const XferArgs<double> &x, int epl, hipStream_t s) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return pack_rhs_impl<double, E>(x, s);
+        NTD_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_unpack_f64(const XferArgs<double> &x, int epl, hipStream_t s, int *np) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return unpack_impl<double, E>(x, s, np);
         NTD_EPL_LIST(NTD_CASE)
 #undef NTD_CASE
     default: return hipErrorInvalidValue;

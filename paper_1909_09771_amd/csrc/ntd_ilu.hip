@@ -90,29 +90,6 @@ __global__ void __launch_bounds__(256) k_ilu_bwd_level(IluGrid g, const double *
     });
 }
 
-// out = b - A x (7-point bands).
-__global__ void __launch_bounds__(256) k_spmv_residual(Grid g, const double *__restrict__ d,
-                                                       const double *__restrict__ ax,
-                                                       const double *__restrict__ ay,
-                                                       const double *__restrict__ az,
-                                                       const double *__restrict__ x,
-                                                       const double *__restrict__ b,
-                                                       double *__restrict__ out) {
-    for (long long p = blockIdx.x * 256LL + threadIdx.x; p < g.N; p += (long long)gridDim.x * 256) {
-        const int i = (int)(p % g.nx);
-        const int j = (int)((p / g.nx) % g.ny);
-        const int k = (int)(p / g.nxy);
-        double s = d[p] * x[p];
-        if (i > 0) s += ax[p - 1] * x[p - 1];
-        if (i < g.nx - 1) s += ax[p] * x[p + 1];
-        if (j > 0) s += ay[p - g.nx] * x[p - g.nx];
-        if (j < g.ny - 1) s += ay[p] * x[p + g.nx];
-        if (k > 0) s += az[p - g.nxy] * x[p - g.nxy];
-        if (k < g.nz - 1) s += az[p] * x[p + g.nxy];
-        out[p] = b[p] - s;
-    }
-}
-
 inline int level_blocks(const IluGrid &g) {
     const long long t = (long long)g.ny * g.nz;
     return (int)((t + 255) / 256);
@@ -153,16 +130,6 @@ hipError_t launch_ilu_apply(const IluGrid &g, const double *ax, const double *ay
         hipLaunchKernelGGL(k_ilu_fwd_level, dim3(nb), dim3(256), 0, s, g, ax, ay, az, dtinv, r, z, l);
     for (int l = g.levels - 1; l >= 0; --l)
         hipLaunchKernelGGL(k_ilu_bwd_level, dim3(nb), dim3(256), 0, s, g, ax, ay, az, dtinv, z, l);
-    return hipGetLastError();
-}
-
-hipError_t launch_spmv_residual(const Grid &g, const double *d, const double *ax, const double *ay,
-                                const double *az, const double *x, const double *b, double *out,
-                                hipStream_t s) {
-    long long nb = (g.N + 255) / 256;
-    if (nb > kMaxBlocks) nb = kMaxBlocks;
-    hipLaunchKernelGGL(k_spmv_residual, dim3((unsigned)nb), dim3(256), 0, s, g, d, ax, ay, az, x, b,
-                       out);
     return hipGetLastError();
 }
 

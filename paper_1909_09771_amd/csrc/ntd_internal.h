@@ -21,9 +21,8 @@ struct Scalars {
 };
 
 // Reduction partial slots: vector kernels write one partial per block (at most
-// kMaxBlocks); the preconditioner apply writes kApplySlots per-wave partials.
+// kMaxBlocks).
 constexpr int kMaxBlocks = 2048;
-constexpr int kApplySlots = 8;
 constexpr int kBlock = 256;
 
 enum FinalizeOp : int {
@@ -46,23 +45,54 @@ struct Grid {
 // Packed ("lane order") layout of the apply: every grid line (nx elements) is
 // stored as 64*EPL slots, slot lane*EPL + s holding the element that lane's
 // position s solves (lanes 0-31: elements 0..j, lanes 32-63: elements nx-1 down
-// to j+1, j = floor((nx-1)/2), both right-aligned in their half); unused slots
-// hold identity values.  Line L = k*ny + m starts at slot L*64*EPL.
+// to j+1, j = floor((nx-1)/2), both right-aligned in their half).  Vectors in
+// this layout (the packed right-hand side and results) take 64*EPL*sizeof(T)
+// bytes per line, line L = k*ny + m at L*64*EPL slots.
+//
+// The factors of line L form one record of rec_bytes() bytes: seven packed
+// arrays (1/M; a = -cp/M, the coupling to the chain predecessor; u = -cn/M,
+// toward the twist; the y-couplings f to lines m-1 and m+1; the z-couplings g
+// to planes k-1 and k+1), then per lane kRecMul scan multipliers, then the FP64
+// twist row (1/M_j, e1[j-1], e1[j], 0).
+constexpr int kRecArrays = 7;
+constexpr int kRecMul = 12;  // forward stage multipliers 0-4, backward 0-4, chain-B seed, pad
+enum RecArray : int { kRecMv = 0, kRecA = 1, kRecU = 2, kRecFdn = 3, kRecFup = 4, kRecGdn = 5,
+                      kRecGup = 6 };
+
+__host__ __device__ constexpr unsigned rec_arr_bytes(unsigned tsz, int epl) {
+    return 64u * (unsigned)epl * tsz;
+}
+__host__ __device__ constexpr unsigned rec_mul_off(unsigned tsz, int epl) {
+    return kRecArrays * rec_arr_bytes(tsz, epl);
+}
+__host__ __device__ constexpr unsigned rec_tw_off(unsigned tsz, int epl) {
+    return rec_mul_off(tsz, epl) + 64u * kRecMul * tsz;
+}
+__host__ __device__ constexpr unsigned rec_bytes(unsigned tsz, int epl) {
+    return (rec_tw_off(tsz, epl) + 32u + 255u) & ~255u;
+}
 
 // Arguments of the nested sweeps (apply) in the sweep precision T.
 template <typename T>
 struct ApplyArgs {
     int nx, ny, nz;
-    const T *pmv, *pa, *pu;       // packed 1/M, a = -cp/M, u = -cn/M
-    const T *pf2, *pg3;           // packed y-band of P and z-band of A
-    const double *tw;             // per line: 1/M_j, e1[j-1], e1[j], 0 (FP64 twist row)
-    const double *r;              // right-hand side (FP64, natural layout)
-    T *Z;                         // packed intermediate / final result
-    double *zout;                 // final result (FP64, natural layout)
+    const void *rec;              // line records (rec_bytes each)
+    const T *rp;                  // packed right-hand side
+    T *Z;                         // packed intermediate, then final result
     T *scratch;                   // two packed plane buffers (one per half chain)
-    double *partials;             // kApplySlots partial sums of rdot.z (may be null)
-    const double *zbase;          // if not null, the output is zbase + B^{-1} r
-    const double *rdot;           // vector dotted with the output (null: r)
+};
+
+// Arguments of the moves between the natural FP64 layout and the packed one.
+template <typename T>
+struct XferArgs {
+    int nx, ny, nz;
+    const double *r;              // pack: right-hand side; unpack: dot operand (may be null)
+    const double *zi;             // pack: rhs = r - A zi if set; unpack: added to the output
+    const double *d, *ax, *ay, *az;  // bands of A (pack with zi)
+    T *rp;                        // pack output
+    const T *Z;                   // unpack input
+    double *zout;                 // unpack output
+    double *partials;             // unpack: per-block partials of r.zout (may be null)
 };
 
 // Geometry of the ILU(0) level schedule: rows split at M (nblocks = 2) or not.
@@ -73,14 +103,11 @@ struct IluGrid {
     int levels;   // number of hyperplane levels
 };
 
-// Arguments of the packing of FP64 natural-layout factors into the apply layout.
-template <typename T>
+// Arguments of the packing of FP64 natural-layout factors into the line records.
 struct PackArgs {
-    int nx;
-    long long nlines;             // ny*nz
+    int nx, ny, nz;
     const double *e1, *mv, *f2, *g3;
-    T *pmv, *pa, *pu, *pf2, *pg3;
-    double *tw;
+    void *rec;
 };
 
 // Arguments of the factorization.
@@ -97,9 +124,14 @@ struct SetupArgs {
 int epl_for(int nx);  // elements per lane of a half-wave chain, 0 if unsupported
 hipError_t launch_apply_f64(const ApplyArgs<double> &a, int epl, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_apply_f32(const ApplyArgs<float> &a, int epl, hipStream_t s, hipEvent_t *ev);
+hipError_t launch_pack_rhs_f64(const XferArgs<double> &x, int epl, hipStream_t s);
+hipError_t launch_pack_rhs_f32(const XferArgs<float> &x, int epl, hipStream_t s);
+// np receives the number of partials written (0 when x.partials is null)
+hipError_t launch_unpack_f64(const XferArgs<double> &x, int epl, hipStream_t s, int *np);
+hipError_t launch_unpack_f32(const XferArgs<float> &x, int epl, hipStream_t s, int *np);
 hipError_t launch_setup(const SetupArgs &a, int epl, hipStream_t s);
-hipError_t launch_pack_f64(const PackArgs<double> &p, int epl, hipStream_t s);
-hipError_t launch_pack_f32(const PackArgs<float> &p, int epl, hipStream_t s);
+hipError_t launch_pack_f64(const PackArgs &p, int epl, hipStream_t s);
+hipError_t launch_pack_f32(const PackArgs &p, int epl, hipStream_t s);
 
 IluGrid ilu_grid(int nx, int ny, int nz, int nblocks);
 hipError_t launch_ilu_factor(const IluGrid &g, const double *d, const double *ax, const double *ay,
@@ -107,9 +139,6 @@ hipError_t launch_ilu_factor(const IluGrid &g, const double *d, const double *ax
                              hipStream_t s);
 hipError_t launch_ilu_apply(const IluGrid &g, const double *ax, const double *ay, const double *az,
                             const double *dtinv, const double *r, double *z, hipStream_t s);
-hipError_t launch_spmv_residual(const Grid &g, const double *d, const double *ax, const double *ay,
-                                const double *az, const double *x, const double *b, double *out,
-                                hipStream_t s);
 
 hipError_t launch_check_positive(const double *kappa, const double *t, long long N, int *flag,
                                  hipStream_t s);

@@ -1,5 +1,8 @@
-// ntd_sweep.h -- device templates of the nested twisted sweeps of the preconditioner
-// (arXiv:1909.09771, Sec. 2.2, Algorithms 1-7) and its factorization (Sec. 2.1).
+// ntd_sweep.h -- device templates shared by the nested twisted sweeps of the
+// preconditioner (arXiv:1909.09771, Sec. 2.2, Algorithms 1-7) and its
+// factorization (Sec. 2.1): line geometry, buffer I/O, cross-lane primitives,
+// the level-2 plane solve, and the factorization kernels.  The apply's own
+// layout and kernels are in ntd_apply.h.
 //
 // Execution model on gfx950.  The sweeps are one long chain of dependent line
 // solves: plane k of a level-3 sweep needs the finished plane k-1, line m of a
@@ -32,7 +35,6 @@ namespace ntd {
 
 namespace {
 
-constexpr int kApplyThreads = 128;  // two wavefronts: the two level-2 half chains
 constexpr int kSetupThreads = 256;  // two chain wavefronts + two helpers for plane-wide work
 
 // ---------------------------------------------------------------------------
@@ -404,6 +406,7 @@ struct LineIn {
     T f[EPL], w[EPL];
     T a0[EPL], a1[EPL], a2[EPL], a3[EPL];
     double d0[EPL], d1[EPL], d2[EPL];
+    T mul[kRecMul];  // packed: the lane's scan multipliers
     double mvj, cpj, cnj;
 };
 
@@ -418,7 +421,8 @@ struct NatFmt {
     rsrc_t e1, mv, f2, W;
     const double *mv64;  // FP64 1/M of the plane
     unsigned soT, soW, lineB;
-    __device__ NatFmt(int nx) : G(nx, EPL), S(G) {}
+    int ny;
+    __device__ NatFmt(int nx) : G(nx, EPL), S(G), ny(1) {}
     __device__ void load_coef(int m, LineIn<T, EPL> &in) const {
         const unsigned so = soT + (unsigned)m * lineB;
 #pragma unroll
@@ -429,8 +433,11 @@ struct NatFmt {
         }
         in.mvj = mv64[(long long)m * G.n + G.ca - 1];
     }
-    __device__ void load_f(int lc, T (&f)[EPL]) const {
-        bload_line(S, f2, soT + (unsigned)lc * lineB, f);
+    // y-coupling of line m to line m+1 (up) or m-1 (down); 0 past the plane edge
+    __device__ void load_fc(int m, bool up, T (&f)[EPL]) const {
+        const int lc = up ? m : m - 1;
+        if (lc < 0 || lc >= ny - 1) zero_line(f);
+        else bload_line(S, f2, soT + (unsigned)lc * lineB, f);
     }
     __device__ void load_w(int m, T (&w)[EPL]) const {
         bload_line(S, W, soW + (unsigned)m * lineB, w);
@@ -451,46 +458,6 @@ struct NatFmt {
         const double cpj = (double)(G.half ? in.c1[L] : in.c2[L]);
         const double cnj = (double)(G.half ? in.c2[L] : in.c1[L]);
         solve_core(a, in.c0, u, in.mvj, cpj, cnj, y, x);
-    }
-};
-
-// Packed layout (the apply): every line is 64*EPL slots in lane order, the
-// slot of lane l and position s holding the element LineGeom assigns to it;
-// unused slots hold 1/M = 0, a = 1, u = 0, f = g3 = 0.  The FP64 twist record
-// of line m is (1/M_j, e1[j-1], e1[j], 0).
-template <typename T, int EPL>
-struct PackFmt {
-    using Ty = T;
-    static constexpr int kEPL = EPL;
-    LineGeom G;
-    Slots<EPL> S;        // natural-layout offsets, for r and the FP64 output
-    rsrc_t mv, a, u, f2, W;
-    const double *tw;    // twist records of the plane, 4 doubles per line
-    unsigned soT, soW;   // byte offset of the plane in the packed arrays / in W
-    unsigned lineB;      // bytes of one packed line
-    unsigned laneB;      // byte offset of this lane inside a packed line
-    __device__ explicit PackFmt(int nx) : G(nx, EPL), S(G) {
-        lineB = 64u * EPL * (unsigned)sizeof(T);
-        laneB = (unsigned)(threadIdx.x & 63) * EPL * (unsigned)sizeof(T);
-    }
-    __device__ void load_coef(int m, LineIn<T, EPL> &in) const {
-        const unsigned so = soT + (unsigned)m * lineB;
-        vload(mv, laneB, so, in.c0);
-        vload(a, laneB, so, in.c1);
-        vload(u, laneB, so, in.c2);
-        in.mvj = tw[4 * m + 0];
-        in.cpj = tw[4 * m + 1];
-        in.cnj = tw[4 * m + 2];
-    }
-    __device__ void load_f(int lc, T (&f)[EPL]) const {
-        vload(f2, laneB, soT + (unsigned)lc * lineB, f);
-    }
-    __device__ void load_w(int m, T (&w)[EPL]) const { vload(W, laneB, soW + (unsigned)m * lineB, w); }
-    __device__ void store_w(int m, const T (&w)[EPL]) const {
-        vstore(W, laneB, soW + (unsigned)m * lineB, w);
-    }
-    __device__ void solve(const LineIn<T, EPL> &in, const T (&y)[EPL], T (&x)[EPL]) const {
-        solve_core(in.c1, in.c0, in.c2, in.mvj, in.cpj, in.cnj, y, x);
     }
 };
 
@@ -524,22 +491,24 @@ __device__ void plane_solve(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty *
     zero_line(prev);
 
     // inputs of the lower step of line m, coupled to its chain predecessor
-    // through the f2 line lc (lc < 0: first line of the chain)
-    auto load_lower = [&](int m, int lc, LineIn<T, EPL> &in) {
+    // m+1 (up) or m-1 (down)
+    auto load_lower = [&](int m, bool up, LineIn<T, EPL> &in) {
         pol.load_rhs(m, fmt, in);
-        if (lc >= 0) fmt.load_f(lc, in.f);
-        else zero_line(in.f);
+        fmt.load_fc(m, up, in.f);
         fmt.load_coef(m, in);
     };
     // inputs of the upper step of line m, coupled to its final neighbour toward
-    // the twist through the f2 line lc
-    auto load_upper = [&](int m, int lc, LineIn<T, EPL> &in) {
+    // the twist, m+1 (up) or m-1 (down)
+    auto load_upper = [&](int m, bool up, LineIn<T, EPL> &in) {
         fmt.load_w(m, in.w);
-        fmt.load_f(lc, in.f);
+        fmt.load_fc(m, up, in.f);
         fmt.load_coef(m, in);
         pol.load_out(m, fmt, in);
     };
+    // Each step starts with a scheduling barrier: work of the next step moved
+    // into this one would wait for loads issued only one step earlier.
     auto lower_step = [&](int m, const LineIn<T, EPL> &in) {
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < EPL; ++s) y[s] = pol.rhs(in, s) - in.f[s] * prev[s];
         fmt.solve(in, y, w);
@@ -548,6 +517,7 @@ __device__ void plane_solve(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty *
         for (int s = 0; s < EPL; ++s) prev[s] = w[s];
     };
     auto upper_step = [&](int m, const LineIn<T, EPL> &in) {
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < EPL; ++s) y[s] = in.f[s] * prev[s];
         fmt.solve(in, y, w);
@@ -561,18 +531,24 @@ __device__ void plane_solve(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty *
     // the inputs of steps i+1 and i+2 are in flight while step i runs; DEPTH 1:
     // two buffers, one step ahead.  With `tail`, the inputs of step `count` are
     // issued too and left in A; with `pre`, those of step 0 are already in A.
+    // Inside the loop every load is issued, past the end of the chain on its
+    // last line again: a conditional load would make the wait counts at the
+    // loop's merge points assume it was skipped and wait for the newest loads.
     auto chain = [&](int count, bool tail, bool pre, auto &&load, auto &&step) {
         const int nl = count + (tail ? 1 : 0);
-        if (nl > 0 && !pre) load(0, A);
+        if (nl <= 0) return;
+        const int last = nl - 1;
+        auto cl = [last](int q) { return q < last ? q : last; };
+        if (!pre) load(0, A);
         if constexpr (DEPTH == 2) {
-            if (nl > 1) load(1, B);
+            load(cl(1), B);
             int i = 0;
             for (; i + 2 < count; i += 3) {
-                load(i + 2, C);
+                load(cl(i + 2), C);
                 step(i, A);
-                if (i + 3 < nl) load(i + 3, A);
+                load(cl(i + 3), A);
                 step(i + 1, B);
-                if (i + 4 < nl) load(i + 4, B);
+                load(cl(i + 4), B);
                 step(i + 2, C);
             }
             const int rest = count - i;  // 0, 1 or 2 steps left, in A then B
@@ -588,9 +564,9 @@ __device__ void plane_solve(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty *
         } else {
             int i = 0;
             for (; i + 1 < count; i += 2) {
-                load(i + 1, B);
+                load(cl(i + 1), B);
                 step(i, A);
-                if (i + 2 < nl) load(i + 2, A);
+                load(cl(i + 2), A);
                 step(i + 1, B);
             }
             if (i < count) {
@@ -604,22 +580,18 @@ __device__ void plane_solve(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty *
     if (wv == 0) {
         // lines 0..j2-1 upward, then the inputs of the twist line j2 in A
         chain(j2, true, false,
-              [&](int i, LineIn<T, EPL> &in) { load_lower(i, i - 1, in); },
+              [&](int i, LineIn<T, EPL> &in) { load_lower(i, false, in); },
               [&](int i, const LineIn<T, EPL> &in) { lower_step(i, in); });
         pol.load_out(j2, fmt, A);
-        if (j2 < ny - 1) fmt.load_f(j2, fhi);
-        else zero_line(fhi);
+        fmt.load_fc(j2, true, fhi);
     } else if (wv == 1) {
         // lines ny-1..j2+1 downward (line m couples to m+1 through f2 line m)
         chain(ny - 1 - j2, false, false,
-              [&](int i, LineIn<T, EPL> &in) {
-                  const int m = ny - 1 - i;
-                  load_lower(m, i == 0 ? -1 : m, in);
-              },
+              [&](int i, LineIn<T, EPL> &in) { load_lower(ny - 1 - i, true, in); },
               [&](int i, const LineIn<T, EPL> &in) { lower_step(ny - 1 - i, in); });
 #pragma unroll
         for (int s = 0; s < EPL; ++s) lds[64 * EPL + lane * EPL + s] = prev[s];
-        if (j2 + 1 < ny) load_upper(j2 + 1, j2, A);
+        if (j2 + 1 < ny) load_upper(j2 + 1, false, A);
     }
     __syncthreads();
     if (wv == 0) {  // twist line: both neighbours
@@ -633,7 +605,7 @@ __device__ void plane_solve(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty *
             prev[s] = w[s];
             lds[lane * EPL + s] = w[s];
         }
-        if (j2 > 0) load_upper(j2 - 1, j2 - 1, A);
+        if (j2 > 0) load_upper(j2 - 1, true, A);
     }
     __syncthreads();
     if (wv == 1) {
@@ -641,312 +613,13 @@ __device__ void plane_solve(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty *
         for (int s = 0; s < EPL; ++s) prev[s] = lds[lane * EPL + s];
         // lines j2+1..ny-1 upward (line m couples to m-1 through f2 line m-1)
         chain(ny - 1 - j2, false, true,
-              [&](int i, LineIn<T, EPL> &in) {
-                  const int m = j2 + 1 + i;
-                  load_upper(m, m - 1, in);
-              },
+              [&](int i, LineIn<T, EPL> &in) { load_upper(j2 + 1 + i, false, in); },
               [&](int i, const LineIn<T, EPL> &in) { upper_step(j2 + 1 + i, in); });
     } else if (wv == 0) {
         // lines j2-1..0 downward (line m couples to m+1 through f2 line m)
         chain(j2, false, true,
-              [&](int i, LineIn<T, EPL> &in) {
-                  const int m = j2 - 1 - i;
-                  load_upper(m, m, in);
-              },
+              [&](int i, LineIn<T, EPL> &in) { load_upper(j2 - 1 - i, true, in); },
               [&](int i, const LineIn<T, EPL> &in) { upper_step(j2 - 1 - i, in); });
-    }
-}
-
-// Prefetch depth of the apply sweeps: two lines ahead while the three input
-// buffers fit the register file (float up to 8 and double up to 4 elements per
-// lane), else one.
-template <typename T, int EPL>
-constexpr int kApplyDepth = (sizeof(T) * EPL <= 32) ? 2 : 1;
-
-// Wave-level sum (fixed butterfly order) of a double.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// ---------------------------------------------------------------------------
-// Level 3: the apply z = B^{-1} r as three launches, on the packed layout.
-// ---------------------------------------------------------------------------
-
-template <typename T, int EPL>
-__device__ __forceinline__ PackFmt<T, EPL> pack_fmt(const ApplyArgs<T> &a, int k, rsrc_t W,
-                                                    unsigned soW) {
-    PackFmt<T, EPL> F(a.nx);
-    F.mv = make_rsrc(a.pmv);
-    F.a = make_rsrc(a.pa);
-    F.u = make_rsrc(a.pu);
-    F.f2 = make_rsrc(a.pf2);
-    F.W = W;
-    F.tw = a.tw + 4LL * k * a.ny;
-    F.soT = (unsigned)k * (unsigned)a.ny * F.lineB;
-    F.soW = soW;
-    return F;
-}
-
-// A natural-layout FP64 line (r, the dot operand or the base) into v.
-template <typename T, int EPL>
-__device__ __forceinline__ void load_r(const PackFmt<T, EPL> &F, rsrc_t r, unsigned so8,
-                                       double (&v)[EPL]) {
-#pragma unroll
-    for (int s = 0; s < EPL; ++s) v[s] = bload((double *)nullptr, r, F.S.o8[s], so8);
-}
-
-// Lower level-3 step of plane k: rhs = r_k - g3 * z_kn (kn = the finished
-// neighbour toward the chain start, if any); the result z_k goes to Z.
-template <typename T, int EPL>
-struct PolLower {
-    rsrc_t r, g3, Z;
-    unsigned so8k;  // byte offset of plane k in r (natural FP64)
-    unsigned soPk;  // byte offset of plane k in the packed arrays
-    unsigned soPc;  // byte offset of the coupling plane min(k, kn) in packed g3
-    unsigned soPn;  // byte offset of plane kn in packed Z
-    unsigned line8;
-    bool has;
-    __device__ void load_rhs(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
-        load_r(F, r, so8k + m * line8, in.d0);
-        if (has) {
-            vload(g3, F.laneB, soPc + m * F.lineB, in.a0);
-            vload(Z, F.laneB, soPn + m * F.lineB, in.a1);
-        }
-    }
-    __device__ T rhs(const LineIn<T, EPL> &in, int s) const {
-        T v = (T)in.d0[s];
-        if (has) v -= in.a0[s] * in.a1[s];
-        return v;
-    }
-    __device__ void load_out(int, const PackFmt<T, EPL> &, LineIn<T, EPL> &) const {}
-    __device__ void out(int m, const PackFmt<T, EPL> &F, const T (&x)[EPL],
-                        const LineIn<T, EPL> &) {
-        vstore(Z, F.laneB, soPk + m * F.lineB, x);
-    }
-};
-
-// The twist plane: rhs = r - g3_lo * z_lo - g3_hi * z_hi; the result is final.
-template <typename T, int EPL>
-struct PolTwist {
-    rsrc_t r, g3, Z, zout, rdot, zbase;
-    unsigned so8k, soPk, soPlo, soPhi;  // plane k, plane k-1 and plane k+1 (packed Z, g3)
-    unsigned line8;
-    bool lo_nb, hi_nb, has_base;
-    double acc;
-    __device__ void load_rhs(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
-        load_r(F, r, so8k + m * line8, in.d0);
-        if (lo_nb) {
-            vload(g3, F.laneB, soPlo + m * F.lineB, in.a0);
-            vload(Z, F.laneB, soPlo + m * F.lineB, in.a1);
-        }
-        if (hi_nb) {
-            vload(g3, F.laneB, soPk + m * F.lineB, in.a2);
-            vload(Z, F.laneB, soPhi + m * F.lineB, in.a3);
-        }
-    }
-    __device__ T rhs(const LineIn<T, EPL> &in, int s) const {
-        T v = (T)in.d0[s];
-        if (lo_nb) v -= in.a0[s] * in.a1[s];
-        if (hi_nb) v -= in.a2[s] * in.a3[s];
-        return v;
-    }
-    // d0 still holds the right-hand side when this runs (the twist line is
-    // loaded ahead of its solve), so the dot operand and base go to d1, d2.
-    __device__ void load_out(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
-        load_r(F, rdot, so8k + m * line8, in.d1);
-        if (has_base) load_r(F, zbase, so8k + m * line8, in.d2);
-    }
-    __device__ void out(int m, const PackFmt<T, EPL> &F, const T (&x)[EPL],
-                        const LineIn<T, EPL> &in) {
-        vstore(Z, F.laneB, soPk + m * F.lineB, x);
-        double xd[EPL];
-#pragma unroll
-        for (int s = 0; s < EPL; ++s) {
-            xd[s] = (double)x[s];
-            if (has_base) xd[s] += in.d2[s];
-            acc += in.d1[s] * xd[s];  // both 0 on unused slots
-        }
-        bstore_line(F.S, zout, so8k + m * line8, xd);
-    }
-};
-
-// Upper level-3 step of plane k: the correction c = Pt_k^{-1}(g3 * x_kn) with
-// kn the final neighbour toward the twist plane; x_k = z_k - c over Z.
-template <typename T, int EPL>
-struct PolUpper {
-    rsrc_t r, g3, Z, zout, rdot, zbase;
-    unsigned so8k, soPk, soPc, soPn;
-    unsigned line8;
-    bool has_base;
-    double acc;
-    __device__ void load_rhs(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
-        vload(g3, F.laneB, soPc + m * F.lineB, in.a0);
-        vload(Z, F.laneB, soPn + m * F.lineB, in.a1);
-    }
-    __device__ T rhs(const LineIn<T, EPL> &in, int s) const { return in.a0[s] * in.a1[s]; }
-    __device__ void load_out(int m, const PackFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
-        vload(Z, F.laneB, soPk + m * F.lineB, in.a2);
-        load_r(F, rdot, so8k + m * line8, in.d0);
-        if (has_base) load_r(F, zbase, so8k + m * line8, in.d1);
-    }
-    __device__ void out(int m, const PackFmt<T, EPL> &F, const T (&cv)[EPL],
-                        const LineIn<T, EPL> &in) {
-        T xv[EPL];
-        double xd[EPL];
-#pragma unroll
-        for (int s = 0; s < EPL; ++s) {
-            xv[s] = in.a2[s] - cv[s];
-            xd[s] = (double)xv[s];
-            if (has_base) xd[s] += in.d1[s];
-            acc += in.d0[s] * xd[s];
-        }
-        vstore(Z, F.laneB, soPk + m * F.lineB, xv);
-        bstore_line(F.S, zout, so8k + m * line8, xd);
-    }
-};
-
-// Lower level-3 sweep of one half: block 0 takes planes 0..j3-1 upward, block 1
-// planes nz-1..j3+1 downward; z_k = Pt_k^{-1}(r_k - g3 * z_{k-+1}) into Z.
-template <typename T, int EPL>
-__global__ void __launch_bounds__(kApplyThreads) k_apply_lower(ApplyArgs<T> a) {
-    __shared__ T lds[2 * 64 * EPL];
-    const int ny = a.ny, nz = a.nz;
-    const int j3 = (nz - 1) / 2;
-    const int h = blockIdx.x;
-    const int dk = h == 0 ? 1 : -1;
-    const unsigned planeP = (unsigned)ny * 64u * EPL * (unsigned)sizeof(T);
-    PolLower<T, EPL> pol;
-    pol.r = make_rsrc(a.r);
-    pol.g3 = make_rsrc(a.pg3);
-    pol.Z = make_rsrc(a.Z);
-    pol.line8 = (unsigned)a.nx * 8u;
-    for (int k = h == 0 ? 0 : nz - 1; h == 0 ? k < j3 : k > j3; k += dk) {
-        const int kn = k - dk;  // neighbour already solved (toward the chain start)
-        pol.has = (kn >= 0 && kn < nz);
-        pol.so8k = (unsigned)k * (unsigned)ny * pol.line8;
-        pol.soPk = (unsigned)k * planeP;
-        pol.soPc = pol.has ? (unsigned)(k < kn ? k : kn) * planeP : 0u;
-        pol.soPn = pol.has ? (unsigned)kn * planeP : 0u;
-        const PackFmt<T, EPL> F = pack_fmt<T, EPL>(a, k, pol.Z, pol.soPk);
-        plane_solve<kApplyDepth<T, EPL>>(ny, F, pol, lds);
-    }
-}
-
-// The twist plane j3 takes both neighbours; its result is final.
-template <typename T, int EPL>
-__global__ void __launch_bounds__(kApplyThreads) k_apply_twist(ApplyArgs<T> a) {
-    __shared__ T lds[2 * 64 * EPL];
-    const int ny = a.ny, nz = a.nz;
-    const int k = (nz - 1) / 2;
-    const unsigned planeP = (unsigned)ny * 64u * EPL * (unsigned)sizeof(T);
-    PolTwist<T, EPL> pol;
-    pol.r = make_rsrc(a.r);
-    pol.g3 = make_rsrc(a.pg3);
-    pol.Z = make_rsrc(a.Z);
-    pol.zout = make_rsrc(a.zout);
-    pol.rdot = make_rsrc(a.rdot ? a.rdot : a.r);
-    pol.zbase = make_rsrc(a.zbase ? a.zbase : a.r);
-    pol.has_base = a.zbase != nullptr;
-    pol.lo_nb = k > 0;
-    pol.hi_nb = k < nz - 1;
-    pol.line8 = (unsigned)a.nx * 8u;
-    pol.so8k = (unsigned)k * (unsigned)ny * pol.line8;
-    pol.soPk = (unsigned)k * planeP;
-    pol.soPlo = pol.lo_nb ? (unsigned)(k - 1) * planeP : 0u;
-    pol.soPhi = pol.hi_nb ? (unsigned)(k + 1) * planeP : 0u;
-    pol.acc = 0.0;
-    const PackFmt<T, EPL> F = pack_fmt<T, EPL>(a, k, pol.Z, pol.soPk);
-    plane_solve<kApplyDepth<T, EPL>>(ny, F, pol, lds);
-    if (a.partials) {
-        const double sum = wave_sum(pol.acc);
-        if ((threadIdx.x & 63) == 0) a.partials[threadIdx.x >> 6] = sum;
-    }
-}
-
-// Upper level-3 sweep: block 0 takes planes j3-1..0, block 1 planes j3+1..nz-1;
-// x_k = z_k - Pt_k^{-1}(g3 * x_{k+-1}), written over Z and to the FP64 output.
-template <typename T, int EPL>
-__global__ void __launch_bounds__(kApplyThreads) k_apply_upper(ApplyArgs<T> a) {
-    __shared__ T lds[2 * 64 * EPL];
-    const int ny = a.ny, nz = a.nz;
-    const int j3 = (nz - 1) / 2;
-    const int h = blockIdx.x;
-    const int dk = h == 0 ? -1 : 1;
-    const unsigned planeP = (unsigned)ny * 64u * EPL * (unsigned)sizeof(T);
-    const rsrc_t W = make_rsrc(a.scratch);
-    PolUpper<T, EPL> pol;
-    pol.r = make_rsrc(a.r);
-    pol.g3 = make_rsrc(a.pg3);
-    pol.Z = make_rsrc(a.Z);
-    pol.zout = make_rsrc(a.zout);
-    pol.rdot = make_rsrc(a.rdot ? a.rdot : a.r);
-    pol.zbase = make_rsrc(a.zbase ? a.zbase : a.r);
-    pol.has_base = a.zbase != nullptr;
-    pol.line8 = (unsigned)a.nx * 8u;
-    pol.acc = 0.0;
-    for (int k = j3 + dk; k >= 0 && k < nz; k += dk) {
-        const int kn = k - dk;  // final neighbour, toward the twist plane
-        pol.so8k = (unsigned)k * (unsigned)ny * pol.line8;
-        pol.soPk = (unsigned)k * planeP;
-        pol.soPc = (unsigned)(k < kn ? k : kn) * planeP;
-        pol.soPn = (unsigned)kn * planeP;
-        const PackFmt<T, EPL> F = pack_fmt<T, EPL>(a, k, W, (unsigned)h * planeP);
-        plane_solve<kApplyDepth<T, EPL>>(ny, F, pol, lds);
-    }
-    if (a.partials) {
-        const double sum = wave_sum(pol.acc);
-        if ((threadIdx.x & 63) == 0) a.partials[2 + 2 * h + (threadIdx.x >> 6)] = sum;
-    }
-}
-
-// Packing of the factors into the apply's layout (one thread per packed slot):
-// 1/M, a = -cp/M, u = -cn/M (0 at the twist row), f2 and g3 at the slot's
-// element, identity values on unused slots, and the FP64 twist record.
-template <typename T, int EPL>
-__global__ void __launch_bounds__(256) k_pack(PackArgs<T> p) {
-    const long long nslot = 64LL * EPL;
-    const long long total = (long long)p.nlines * nslot;
-    const int n = p.nx;
-    const int ca = (n + 1) / 2, cb = n - ca, j = ca - 1;
-    for (long long q = blockIdx.x * 256LL + threadIdx.x; q < total; q += (long long)gridDim.x * 256) {
-        const long long line = q / nslot;
-        const int slot = (int)(q - line * nslot);
-        const int lane = slot / EPL, s = slot - lane * EPL;
-        const int half = lane >> 5, hl = lane & 31;
-        const int cnt = half ? cb : ca;
-        const int c = hl * EPL + s - (32 * EPL - cnt);
-        const long long base = line * n;
-        T mv = T(0), av = T(1), uv = T(0), fv = T(0), gv = T(0);
-        if (c >= 0) {
-            const int e = half ? n - 1 - c : c;
-            const double m = p.mv[base + e];
-            double cp, cn;
-            if (half == 0) {
-                cp = e > 0 ? p.e1[base + e - 1] : 0.0;
-                cn = e == j ? 0.0 : p.e1[base + e];
-            } else {
-                cp = p.e1[base + e];
-                cn = p.e1[base + e - 1];
-            }
-            mv = (T)m;
-            av = (T)(-m * cp);
-            uv = (T)(-m * cn);
-            fv = (T)p.f2[base + e];
-            gv = (T)p.g3[base + e];
-        }
-        p.pmv[q] = mv;
-        p.pa[q] = av;
-        p.pu[q] = uv;
-        p.pf2[q] = fv;
-        p.pg3[q] = gv;
-        if (slot == 0) {
-            p.tw[4 * line + 0] = p.mv[base + j];
-            p.tw[4 * line + 1] = j > 0 ? p.e1[base + j - 1] : 0.0;
-            p.tw[4 * line + 2] = j < n - 1 ? p.e1[base + j] : 0.0;
-            p.tw[4 * line + 3] = 0.0;
-        }
     }
 }
 
@@ -1154,6 +827,7 @@ __device__ void plane_setup(const SetupArgs &a, int k, int nnb, int nb0, int nb1
         F.soT = 0;
         F.soW = 0;
         F.lineB = (unsigned)nx * 8u;
+        F.ny = ny;
         plane_solve<1>(ny, F, pol, lds_x);
         __syncthreads();
         const double *dPn = a.dP + pn, *xPn = a.xP + pn, *yPn = a.f2 + pn;
@@ -1221,29 +895,6 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup_twist(SetupArgs a) {
     if (j3 < a.nz - 1) { if (nnb == 0) n0 = j3 + 1; else n1 = j3 + 1; ++nnb; }
     plane_setup<EPL>(a, j3, nnb, n0, n1, a.scratch + 4 * nxy, a.scratch + 5 * nxy, lds_lines,
                      lds_x);
-}
-
-// The apply as three stream-ordered launches; ev (optional, 4 events) brackets
-// them for per-launch timing.
-template <typename T, int EPL>
-hipError_t apply_impl(const ApplyArgs<T> &a, hipStream_t s, hipEvent_t *ev) {
-    if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL((k_apply_lower<T, EPL>), dim3(2), dim3(kApplyThreads), 0, s, a);
-    if (ev) (void)hipEventRecord(ev[1], s);
-    hipLaunchKernelGGL((k_apply_twist<T, EPL>), dim3(1), dim3(kApplyThreads), 0, s, a);
-    if (ev) (void)hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL((k_apply_upper<T, EPL>), dim3(2), dim3(kApplyThreads), 0, s, a);
-    if (ev) (void)hipEventRecord(ev[3], s);
-    return hipGetLastError();
-}
-
-template <typename T, int EPL>
-hipError_t pack_impl(const PackArgs<T> &p, hipStream_t s) {
-    const long long total = (long long)p.nlines * 64 * EPL;
-    long long nb = (total + 255) / 256;
-    if (nb > 65535) nb = 65535;
-    hipLaunchKernelGGL((k_pack<T, EPL>), dim3((unsigned)nb), dim3(256), 0, s, p);
-    return hipGetLastError();
 }
 
 template <int EPL>
