@@ -9,12 +9,19 @@
 //   dt_p = d_p - sum over kept lower neighbours q of a_pq^2 / dt_q,
 // and B_ILU = (Dt + L) Dt^{-1} (Dt + U).
 //
-// Scheduling: row p depends only on its lower neighbours p-1, p-nx, p-nx*ny, so
-// all rows on one hyperplane i + j + (k - k0) = level (k0 = 0 in the first
-// block, k0 = the plane of row M in the second) are independent.  One launch
-// per level processes both blocks at once; a thread owns one (j, k) pair and
-// the row of each block that falls on the level.
-#include "ntd_internal.h"
+// Scheduling.  Row p depends only on its lower neighbours p-1, p-nx, p-nx*ny.
+// The factorization (once per setup) takes all rows of a hyperplane
+// i + j + (k - k0) = level (k0 = 0 in the first block, the plane of row M in
+// the second) in one launch, both blocks at once.  The sweeps of every
+// application are tiled instead: an x-line (j, k) depends on lines (j-1, k)
+// and (j, k-1) only through elementwise terms, and along x it is a first-order
+// linear recurrence, solved by one wavefront as a 64-lane affine scan.  A
+// workgroup of kIluTile wavefronts owns a tile of kIluTile x kIluTile lines
+// and walks its line anti-diagonals with one barrier each, passing each line
+// to its successors through LDS; tiles on one anti-diagonal of the tile grid
+// (both blocks) form one launch, so a sweep takes about (ny + nz/2)/kIluTile
+// launches instead of nx + ny + nz/2.
+#include "ntd_sweep.h"
 
 namespace ntd {
 
@@ -59,35 +66,378 @@ __global__ void __launch_bounds__(256) k_ilu_factor_level(IluGrid g, const doubl
     });
 }
 
-// Forward sweep (Dt + L) y = r.
-__global__ void __launch_bounds__(256) k_ilu_fwd_level(IluGrid g, const double *__restrict__ ax,
-                                                       const double *__restrict__ ay,
-                                                       const double *__restrict__ az,
-                                                       const double *__restrict__ dtinv,
-                                                       const double *__restrict__ r,
-                                                       double *__restrict__ y, int level) {
-    for_level_rows(g, level, [&](long long p, int i, int j, int k) {
-        double v = r[p];
-        if (i > 0 && kept(p - 1, p, g)) v -= ax[p - 1] * y[p - 1];
-        if (j > 0 && kept(p - g.nx, p, g)) v -= ay[p - g.nx] * y[p - g.nx];
-        if (k > 0 && kept(p - g.nxy, p, g)) v -= az[p - g.nxy] * y[p - g.nxy];
-        y[p] = v * dtinv[p];
-    });
+constexpr int kIluThreads = 64 * kIluTile;  // one wavefront per tile row
+constexpr int kRowBcast31 = 0x143;
+
+// x_c = a_c x_{c-1} + b_c over the 64*E positions c = lane*E + s of the
+// wavefront (x_{-1} = 0), in place of b: lane composites, a 64-lane scan of
+// affine maps (rows, then rows 1 and 3 from lanes 15 and 47, then rows 2 and 3
+// from lane 31), then the lane-local recurrence from the exclusive carry.
+template <int E>
+__device__ __forceinline__ void line_recurrence(const double (&a)[E], double (&b)[E]) {
+    double A = 1.0, B = 0.0;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        B = a[s] * B + b[s];
+        A = a[s] * A;
+    }
+#define NTD_ILU_STEP(CTRL, RM)                                                   \
+    {                                                                            \
+        const double Ap = dpp<CTRL, RM>(1.0, A), Bp = dpp<CTRL, RM>(0.0, B);     \
+        B = A * Bp + B;                                                          \
+        A = A * Ap;                                                              \
+    }
+    NTD_ILU_STEP(kRowShr1, 0xF)
+    NTD_ILU_STEP(kRowShr2, 0xF)
+    NTD_ILU_STEP(kRowShr4, 0xF)
+    NTD_ILU_STEP(kRowShr8, 0xF)
+    NTD_ILU_STEP(kRowBcast15, 0xA)
+#undef NTD_ILU_STEP
+    B = A * dpp<kRowBcast31, 0xC>(0.0, B) + B;
+    double carry = dpp<kWaveShr1>(0.0, B);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        b[s] = a[s] * carry + b[s];
+        carry = b[s];
+    }
 }
 
-// Backward sweep (I + Dt^{-1} U) z = y, in place (z holds y on entry).
-__global__ void __launch_bounds__(256) k_ilu_bwd_level(IluGrid g, const double *__restrict__ ax,
-                                                       const double *__restrict__ ay,
-                                                       const double *__restrict__ az,
-                                                       const double *__restrict__ dtinv,
-                                                       double *__restrict__ z, int level) {
-    for_level_rows(g, level, [&](long long p, int i, int j, int k) {
-        double v = 0.0;
-        if (i < g.nx - 1 && kept(p, p + 1, g)) v += ax[p] * z[p + 1];
-        if (j < g.ny - 1 && kept(p, p + g.nx, g)) v += ay[p] * z[p + g.nx];
-        if (k < g.nz - 1 && kept(p, p + g.nxy, g)) v += az[p] * z[p + g.nxy];
-        z[p] -= v * dtinv[p];
-    });
+// Tile (block b, ty, tz) of tile anti-diagonal L served by this workgroup.
+__device__ __forceinline__ bool tile_of(const IluGrid &g, int L, int &b, int &ty, int &tz) {
+    int idx = blockIdx.x;
+    for (b = 0; b < 2; ++b) {
+        const int lo = L - (g.TY - 1) > 0 ? L - (g.TY - 1) : 0;
+        const int hi = L < g.TZ[b] - 1 ? L : g.TZ[b] - 1;
+        const int cnt = hi >= lo ? hi - lo + 1 : 0;
+        if (idx < cnt) {
+            tz = lo + idx;
+            ty = L - tz;
+            return true;
+        }
+        idx -= cnt;
+    }
+    return false;
+}
+
+__device__ __forceinline__ bool in_block(long long p, int b, const IluGrid &g) {
+    return g.nblocks == 1 || ((p >= g.M) == (b == 1));
+}
+
+// Grid line (j, k) at tile row w, line anti-diagonal ll of tile (b, ty, tz),
+// or false if it does not exist.
+__device__ __forceinline__ bool tile_line(const IluGrid &g, int b, int ty, int tz, int w, int ll,
+                                          int &j, int &k) {
+    const int kl = ll - w;
+    j = ty * kIluTile + w;
+    k = g.kb0[b] + tz * kIluTile + kl;
+    return kl >= 0 && kl < kIluTile && j < g.ny && k <= g.kb1[b];
+}
+
+// Does row M (the block split) fall strictly inside the x-line starting at base?
+__device__ __forceinline__ bool cut_by_split(const IluGrid &g, long long base) {
+    return g.nblocks == 2 && base < g.M && g.M < base + g.nx;
+}
+
+// Element offsets of the positions c = lane*E + s of a line: element i = c
+// (forward) or i = 64E - 1 - c (backward), 8*i bytes, or kOOB past the line.
+// With VEC (nx a multiple of E) a lane's elements are one aligned chunk, at
+// byte offset co (kOOB when outside the line).
+template <int E, bool REV>
+struct IluLanes {
+    unsigned eo[E];
+    unsigned co;
+    __device__ IluLanes(int nx) {
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int c = lane * E + s;
+            const int i = REV ? 64 * E - 1 - c : c;
+            eo[s] = i < nx ? 8u * (unsigned)i : kOOB;
+        }
+        const int i0 = REV ? 64 * E - E - lane * E : lane * E;
+        co = i0 + E - 1 < nx ? 8u * (unsigned)i0 : kOOB;
+    }
+    __device__ int elem(int s) const {
+        const int c = (threadIdx.x & 63) * E + s;
+        return REV ? 64 * E - 1 - c : c;
+    }
+};
+
+template <int E, bool REV, bool VEC>
+__device__ __forceinline__ void ld(rsrc_t r, unsigned so, const IluLanes<E, REV> &L,
+                                   double (&v)[E]) {
+    if constexpr (VEC) {
+        double t[E];
+        vload(r, L.co, so, t);
+#pragma unroll
+        for (int s = 0; s < E; ++s) v[s] = REV ? t[E - 1 - s] : t[s];
+    } else {
+#pragma unroll
+        for (int s = 0; s < E; ++s) v[s] = bload((double *)nullptr, r, L.eo[s], so);
+    }
+}
+
+template <int E, bool REV, bool VEC>
+__device__ __forceinline__ void st(rsrc_t r, unsigned so, const IluLanes<E, REV> &L,
+                                   const double (&v)[E]) {
+    if constexpr (VEC) {
+        double t[E];
+#pragma unroll
+        for (int s = 0; s < E; ++s) t[REV ? E - 1 - s : s] = v[s];
+        vstore(r, L.co, so, t);
+    } else {
+#pragma unroll
+        for (int s = 0; s < E; ++s) bstore(v[s], r, L.eo[s], so);
+    }
+}
+
+// Inputs of one line of a tiled sweep that do not depend on the sweep's own
+// results inside the tile (loaded one anti-diagonal ahead): the right-hand
+// side (forward) or forward result (backward), 1/dt, the couplings, and the
+// neighbour lines that lie in earlier tiles (zero when absent).
+template <int E>
+struct IluLine {
+    double rv[E], di[E], cx[E], cy[E], cz[E], vy[E], vz[E];
+};
+
+struct IluPtrs {
+    const double *ax, *ay, *az, *di, *r;
+    double *y;
+};
+
+struct IluBufs {
+    rsrc_t ax, ay, az, di, r, y;
+    __device__ explicit IluBufs(const IluPtrs &p)
+        : ax(make_rsrc(p.ax)), ay(make_rsrc(p.ay)), az(make_rsrc(p.az)), di(make_rsrc(p.di)),
+          r(make_rsrc(p.r)), y(make_rsrc(p.y)) {}
+};
+
+// Rows of the x-lines starting at base and base2 lie in the same block.
+__device__ __forceinline__ bool same_block(const IluGrid &g, long long base, long long base2) {
+    return g.nblocks == 1 || ((base >= g.M) == (base2 >= g.M));
+}
+
+// Forward sweep (Dt + L) y = r on the tiles of anti-diagonal L:
+// y_p = (r_p - sum over kept lower neighbours q of a_qp y_q) / dt_p.
+template <int E, bool VEC>
+__global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, IluPtrs P) {
+    extern __shared__ double lds[];  // two anti-diagonals of kIluTile lines, [s][lane]
+    int b, ty, tz;
+    if (!tile_of(g, L, b, ty, tz)) return;
+    const IluBufs B(P);
+    // the wavefront index is uniform per wavefront; say so, or every buffer
+    // access with an offset derived from it becomes a per-lane loop
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int nx = g.nx;
+    const unsigned nx8 = 8u * nx, nxy8 = 8u * (unsigned)g.nxy;
+    const IluLanes<E, false> Ln(nx);
+    auto load = [&](int ll, IluLine<E> &d) {
+        int j, k;
+        if (!tile_line(g, b, ty, tz, w, ll, j, k)) return;
+        const unsigned so = 8u * (unsigned)(((long long)k * g.ny + j) * nx);
+        ld<E, false, VEC>(B.r, so, Ln, d.rv);
+        ld<E, false, VEC>(B.di, so, Ln, d.di);
+        // ax of element i-1 (0 at i = 0 and past the line)
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const unsigned o = (Ln.eo[s] != kOOB && Ln.elem(s) > 0) ? Ln.eo[s] - 8u : kOOB;
+            d.cx[s] = bload((double *)nullptr, B.ax, o, so);
+        }
+        if (j > 0) {
+            ld<E, false, VEC>(B.ay, so - nx8, Ln, d.cy);
+            if (w == 0) ld<E, false, VEC>(B.y, so - nx8, Ln, d.vy);  // tile ty-1
+        }
+        if (k > 0) {
+            ld<E, false, VEC>(B.az, so - nxy8, Ln, d.cz);
+            if (ll - w == 0) ld<E, false, VEC>(B.y, so - nxy8, Ln, d.vz);  // tile tz-1
+        }
+    };
+    auto solve = [&](int ll, const IluLine<E> &d) {
+        int j, k;
+        if (!tile_line(g, b, ty, tz, w, ll, j, k)) return;
+        const int kl = ll - w;
+        const long long base = ((long long)k * g.ny + j) * nx;
+        const unsigned so = 8u * (unsigned)base;
+        double *cur = lds + (ll & 1) * kIluTile * 64 * E;
+        const double *prv = lds + ((ll + 1) & 1) * kIluTile * 64 * E;
+        double a[E], v[E], ny_[E], nz_[E];
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            ny_[s] = w > 0 ? prv[((w - 1) * E + s) * 64 + lane] : d.vy[s];
+            nz_[s] = kl > 0 ? prv[(w * E + s) * 64 + lane] : d.vz[s];
+        }
+        const bool generic = cut_by_split(g, base) || cut_by_split(g, base - nx) ||
+                             cut_by_split(g, base - g.nxy);
+        if (!generic) {
+            // the line and its neighbour lines lie wholly on one side of row M
+            const bool mine = g.nblocks == 1 || ((base >= g.M) == (b == 1));
+            if (!mine) return;  // only in the plane shared by the two blocks
+            const bool yk = j > 0 && same_block(g, base, base - nx);
+            const bool zk = k > 0 && same_block(g, base, base - g.nxy);
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                double c = d.rv[s];
+                if (yk) c -= d.cy[s] * ny_[s];
+                if (zk) c -= d.cz[s] * nz_[s];
+                v[s] = Ln.eo[s] != kOOB ? d.di[s] * c : 0.0;
+                a[s] = -d.di[s] * d.cx[s];
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const int i = Ln.elem(s);
+                const long long p = base + i;
+                a[s] = 0.0;
+                v[s] = 0.0;
+                if (i < nx && in_block(p, b, g)) {
+                    double c = d.rv[s];
+                    if (j > 0 && kept(p - nx, p, g)) c -= d.cy[s] * ny_[s];
+                    if (k > 0 && kept(p - g.nxy, p, g)) c -= d.cz[s] * nz_[s];
+                    v[s] = d.di[s] * c;
+                    if (i > 0 && kept(p - 1, p, g)) a[s] = -d.di[s] * d.cx[s];
+                }
+            }
+        }
+        line_recurrence<E>(a, v);
+#pragma unroll
+        for (int s = 0; s < E; ++s) cur[(w * E + s) * 64 + lane] = v[s];
+        if (!generic) {
+            st<E, false, VEC>(B.y, so, Ln, v);
+        } else {
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const int i = Ln.elem(s);
+                if (i < nx && in_block(base + i, b, g)) bstore(v[s], B.y, Ln.eo[s], so);
+            }
+        }
+    };
+    constexpr int NL = 2 * kIluTile - 1;
+    IluLine<E> A, Bq;
+#pragma unroll
+    for (int s = 0; s < E; ++s) A.cy[s] = A.cz[s] = A.vy[s] = A.vz[s] = Bq.cy[s] = Bq.cz[s] =
+        Bq.vy[s] = Bq.vz[s] = 0.0;
+    load(0, A);
+    for (int ll = 0; ll < NL; ll += 2) {
+        if (ll + 1 < NL) load(ll + 1, Bq);
+        solve(ll, A);
+        __syncthreads();
+        if (ll + 1 < NL) {
+            if (ll + 2 < NL) load(ll + 2, A);
+            solve(ll + 1, Bq);
+            __syncthreads();
+        }
+    }
+}
+
+// Backward sweep (I + Dt^{-1} U) z = y in place on the tiles of anti-diagonal L
+// (visited in decreasing order): z_p = y_p - (sum over kept upper neighbours q
+// of a_pq z_q) / dt_p.  Lanes take the positions of the line in reverse
+// (c = 0 is element nx-1 padded to 64*E), so the recurrence runs forward in c.
+template <int E, bool VEC>
+__global__ void __launch_bounds__(kIluThreads) k_ilu_bwd_tile(IluGrid g, int L, IluPtrs P) {
+    extern __shared__ double lds[];
+    int b, ty, tz;
+    if (!tile_of(g, L, b, ty, tz)) return;
+    const IluBufs B(P);
+    // the wavefront index is uniform per wavefront; say so, or every buffer
+    // access with an offset derived from it becomes a per-lane loop
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int nx = g.nx;
+    const unsigned nx8 = 8u * nx, nxy8 = 8u * (unsigned)g.nxy;
+    const IluLanes<E, true> Ln(nx);
+    auto load = [&](int ll, IluLine<E> &d) {
+        int j, k;
+        if (!tile_line(g, b, ty, tz, w, ll, j, k)) return;
+        const unsigned so = 8u * (unsigned)(((long long)k * g.ny + j) * nx);
+        ld<E, true, VEC>(B.y, so, Ln, d.rv);  // the forward result of this line
+        ld<E, true, VEC>(B.di, so, Ln, d.di);
+        ld<E, true, VEC>(B.ax, so, Ln, d.cx);
+        if (j < g.ny - 1) {
+            ld<E, true, VEC>(B.ay, so, Ln, d.cy);
+            if (w == kIluTile - 1) ld<E, true, VEC>(B.y, so + nx8, Ln, d.vy);  // tile ty+1
+        }
+        if (k < g.nz - 1) {
+            ld<E, true, VEC>(B.az, so, Ln, d.cz);
+            if (ll - w == kIluTile - 1) ld<E, true, VEC>(B.y, so + nxy8, Ln, d.vz);  // tile tz+1
+        }
+    };
+    auto solve = [&](int ll, const IluLine<E> &d) {
+        int j, k;
+        if (!tile_line(g, b, ty, tz, w, ll, j, k)) return;
+        const int kl = ll - w;
+        const long long base = ((long long)k * g.ny + j) * nx;
+        const unsigned so = 8u * (unsigned)base;
+        double *cur = lds + (ll & 1) * kIluTile * 64 * E;
+        const double *prv = lds + ((ll + 1) & 1) * kIluTile * 64 * E;
+        double a[E], v[E], ny_[E], nz_[E];
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            ny_[s] = w < kIluTile - 1 ? prv[((w + 1) * E + s) * 64 + lane] : d.vy[s];
+            nz_[s] = kl < kIluTile - 1 ? prv[(w * E + s) * 64 + lane] : d.vz[s];
+        }
+        const bool generic = cut_by_split(g, base) || cut_by_split(g, base + nx) ||
+                             cut_by_split(g, base + g.nxy);
+        if (!generic) {
+            const bool mine = g.nblocks == 1 || ((base >= g.M) == (b == 1));
+            if (!mine) return;
+            const bool yk = j < g.ny - 1 && same_block(g, base, base + nx);
+            const bool zk = k < g.nz - 1 && same_block(g, base, base + g.nxy);
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const int i = Ln.elem(s);
+                double c = 0.0;
+                if (yk) c += d.cy[s] * ny_[s];
+                if (zk) c += d.cz[s] * nz_[s];
+                v[s] = Ln.eo[s] != kOOB ? d.rv[s] - d.di[s] * c : 0.0;
+                a[s] = i < nx - 1 ? -d.di[s] * d.cx[s] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const int i = Ln.elem(s);
+                const long long p = base + i;
+                a[s] = 0.0;
+                v[s] = 0.0;
+                if (i < nx && in_block(p, b, g)) {
+                    double c = 0.0;
+                    if (j < g.ny - 1 && kept(p, p + nx, g)) c += d.cy[s] * ny_[s];
+                    if (k < g.nz - 1 && kept(p, p + g.nxy, g)) c += d.cz[s] * nz_[s];
+                    v[s] = d.rv[s] - d.di[s] * c;
+                    if (i < nx - 1 && kept(p, p + 1, g)) a[s] = -d.di[s] * d.cx[s];
+                }
+            }
+        }
+        line_recurrence<E>(a, v);
+#pragma unroll
+        for (int s = 0; s < E; ++s) cur[(w * E + s) * 64 + lane] = v[s];
+        if (!generic) {
+            st<E, true, VEC>(B.y, so, Ln, v);
+        } else {
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const int i = Ln.elem(s);
+                if (i < nx && in_block(base + i, b, g)) bstore(v[s], B.y, Ln.eo[s], so);
+            }
+        }
+    };
+    constexpr int NL = 2 * kIluTile - 1;
+    IluLine<E> A, Bq;
+#pragma unroll
+    for (int s = 0; s < E; ++s) A.cy[s] = A.cz[s] = A.vy[s] = A.vz[s] = Bq.cy[s] = Bq.cz[s] =
+        Bq.vy[s] = Bq.vz[s] = 0.0;
+    load(NL - 1, A);
+    for (int ll = NL - 1; ll >= 0; ll -= 2) {
+        if (ll - 1 >= 0) load(ll - 1, Bq);
+        solve(ll, A);
+        __syncthreads();
+        if (ll - 1 >= 0) {
+            if (ll - 2 >= 0) load(ll - 2, A);
+            solve(ll - 1, Bq);
+            __syncthreads();
+        }
+    }
 }
 
 inline int level_blocks(const IluGrid &g) {
@@ -108,6 +458,18 @@ IluGrid ilu_grid(int nx, int ny, int nz, int nblocks) {
     // highest level of either block, plus one
     const int span = nblocks == 2 ? (g.kz > nz - 1 - g.kz ? g.kz : nz - 1 - g.kz) : nz - 1;
     g.levels = nx + ny - 2 + span + 1;
+    g.kb0[0] = 0;
+    g.kb1[0] = nblocks == 2 ? (g.M > 0 ? (int)((g.M - 1) / g.nxy) : -1) : nz - 1;
+    g.kb0[1] = nblocks == 2 ? (int)(g.M / g.nxy) : 0;
+    g.kb1[1] = nblocks == 2 ? nz - 1 : -1;
+    g.TY = (ny + kIluTile - 1) / kIluTile;
+    int tzmax = 0;
+    for (int b = 0; b < 2; ++b) {
+        const int np = g.kb1[b] >= g.kb0[b] ? g.kb1[b] - g.kb0[b] + 1 : 0;
+        g.TZ[b] = (np + kIluTile - 1) / kIluTile;
+        if (g.TZ[b] > tzmax) tzmax = g.TZ[b];
+    }
+    g.tlevels = tzmax > 0 ? g.TY + tzmax - 1 : 0;
     return g;
 }
 
@@ -123,14 +485,55 @@ hipError_t launch_ilu_factor(const IluGrid &g, const double *d, const double *ax
     return launch_recip(dtinv, dt, g.N, s);
 }
 
+namespace {
+
+int tiles_on(const IluGrid &g, int L) {
+    int n = 0;
+    for (int b = 0; b < 2; ++b) {
+        const int lo = L - (g.TY - 1) > 0 ? L - (g.TY - 1) : 0;
+        const int hi = L < g.TZ[b] - 1 ? L : g.TZ[b] - 1;
+        if (hi >= lo) n += hi - lo + 1;
+    }
+    return n;
+}
+
+template <int E, bool VEC>
+hipError_t ilu_apply_e(const IluGrid &g, const double *ax, const double *ay, const double *az,
+                       const double *dtinv, const double *r, double *z, hipStream_t s) {
+    const size_t sh = 2 * (size_t)kIluTile * 64 * E * sizeof(double);
+    if (sh > 65536) {
+        (void)hipFuncSetAttribute((const void *)k_ilu_fwd_tile<E, VEC>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        (void)hipFuncSetAttribute((const void *)k_ilu_bwd_tile<E, VEC>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    }
+    IluPtrs fb{ax, ay, az, dtinv, r, z};
+    for (int L = 0; L < g.tlevels; ++L)
+        hipLaunchKernelGGL((k_ilu_fwd_tile<E, VEC>), dim3(tiles_on(g, L)), dim3(kIluThreads), sh,
+                           s, g, L, fb);
+    for (int L = g.tlevels - 1; L >= 0; --L)
+        hipLaunchKernelGGL((k_ilu_bwd_tile<E, VEC>), dim3(tiles_on(g, L)), dim3(kIluThreads), sh,
+                           s, g, L, fb);
+    return hipGetLastError();
+}
+
+template <int E>
+hipError_t ilu_apply_v(const IluGrid &g, const double *ax, const double *ay, const double *az,
+                       const double *dtinv, const double *r, double *z, hipStream_t s) {
+    if (g.nx % E == 0) return ilu_apply_e<E, true>(g, ax, ay, az, dtinv, r, z, s);
+    return ilu_apply_e<E, false>(g, ax, ay, az, dtinv, r, z, s);
+}
+
+}  // namespace
+
 hipError_t launch_ilu_apply(const IluGrid &g, const double *ax, const double *ay, const double *az,
                             const double *dtinv, const double *r, double *z, hipStream_t s) {
-    const int nb = level_blocks(g);
-    for (int l = 0; l < g.levels; ++l)
-        hipLaunchKernelGGL(k_ilu_fwd_level, dim3(nb), dim3(256), 0, s, g, ax, ay, az, dtinv, r, z, l);
-    for (int l = g.levels - 1; l >= 0; --l)
-        hipLaunchKernelGGL(k_ilu_bwd_level, dim3(nb), dim3(256), 0, s, g, ax, ay, az, dtinv, z, l);
-    return hipGetLastError();
+    const int e = (g.nx + 63) / 64;
+    if (e <= 1) return ilu_apply_v<1>(g, ax, ay, az, dtinv, r, z, s);
+    if (e <= 2) return ilu_apply_v<2>(g, ax, ay, az, dtinv, r, z, s);
+    if (e <= 4) return ilu_apply_v<4>(g, ax, ay, az, dtinv, r, z, s);
+    if (e <= 8) return ilu_apply_v<8>(g, ax, ay, az, dtinv, r, z, s);
+    return ilu_apply_v<16>(g, ax, ay, az, dtinv, r, z, s);
 }
 
 }  // namespace ntd

@@ -100,8 +100,14 @@ struct IluGrid {
     int nx, ny, nz, nblocks;
     long long nxy, N, M;
     int kz;       // plane of row M (start plane of the second block's level frame)
-    int levels;   // number of hyperplane levels
+    int levels;   // number of point hyperplane levels (factorization)
+    // tiled sweeps: block b covers planes kb0[b]..kb1[b] (empty if kb1 < kb0),
+    // cut into tiles of kIluTile x kIluTile x-lines, TY along y, TZ[b] along z
+    int kb0[2], kb1[2];
+    int TY, TZ[2];
+    int tlevels;  // tile anti-diagonals
 };
+constexpr int kIluTile = 8;
 
 // Arguments of the packing of FP64 natural-layout factors into the line records.
 struct PackArgs {
