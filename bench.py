@@ -75,6 +75,11 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="run the preconditioner, the SpMV and a calibration copy, then exit")
     ap.add_argument("--reps", type=int, default=3, help="launches per kernel in --kernels-only")
+    ap.add_argument("--suite", default=None, choices=["paper"],
+                    help="paper: the test matrices of Sec. 3 (Types 1-3, 100^3/200^3/350^3, "
+                         "tol 1e-7 and 1e-10), one JSON line per case")
+    ap.add_argument("--sizes", default="100,200,350", help="cube sides of --suite paper")
+    ap.add_argument("--precs", default="mixed,fp64", help="precisions of --suite paper")
     return ap.parse_args()
 
 
@@ -153,12 +158,56 @@ def kernels_only(args, S, b, n):
                       "copy_bytes_each_way": src.numel() * 8}), flush=True)
 
 
+def paper_suite(args):
+    """The test matrices of Sec. 3 (Types 1-3 on n^3, Dirichlet on every face,
+    b ~ U[-1,1] seed 701 since the paper does not state b), solved to the two
+    tolerances of Table 1 with the Newton blocks and the ILU(0) combination:
+    setup time (assembly, factorization, ILU(0)), solve time and iterations,
+    one JSON line per case."""
+    import torch
+    import paper_1909_09771_amd as P
+    import workloads as W
+    dev = torch.device("cuda:0")
+    for n in [int(v) for v in args.sizes.split(",")]:
+        for typ in (1, 2, 3):
+            w = W.scaled_workload("paper%d" % typ, n)
+            kappa = torch.from_numpy(w["kappa"]).to(dev)
+            b = torch.from_numpy(w["b"]).to(dev)
+            del w
+            for tol in (1e-7, 1e-10):
+                for prec in args.precs.split(","):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    S = P.Solver(kappa, P_BC_ALL, prec=prec, schur=args.schur,
+                                 smoother=args.smoother)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    x, it, rr, st = S.pcg(b, tol=tol, maxit=args.maxit)
+                    torch.cuda.synchronize()
+                    t2 = time.perf_counter()
+                    line = {"suite": "paper", "type": typ, "n": n, "rows": n ** 3, "tol": tol,
+                            "prec": prec, "schur": args.schur, "smoother": args.smoother,
+                            "setup_s": round(t1 - t0, 4), "solve_s": round(t2 - t1, 4),
+                            "overall_s": round(t2 - t0, 4), "iters": it, "relres": rr,
+                            "status": st, "footprint_bytes": S.footprint_bytes}
+                    print(json.dumps(line), flush=True)
+                    del S, x
+                    torch.cuda.empty_cache()
+            del kappa, b
+
+
+P_BC_ALL = [0, 0, 0, 0, 0, 0]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: runs on one GPU only (--gpus 1); the level-3 twist split "
               "across two GPUs is a design, not built", file=sys.stderr)
         sys.exit(2)
+    if args.suite == "paper":
+        paper_suite(args)
+        return
     import torch
     import paper_1909_09771_amd as P
     import workloads as W

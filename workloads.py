@@ -174,4 +174,9 @@ def scaled_workload(name: str, n: int) -> dict:
     if name == "spheres":
         return dict(n=(n, n, n), kappa=kappa_spheres(n, n, n, 301), bc=BC_ALL_DIRICHLET.copy(),
                     b=np.ones((n, n, n)), t=None)
+    if name in ("paper1", "paper2", "paper3"):  # Sec. 3 test matrices, Dirichlet everywhere
+        kappa = {"paper1": kappa_paper_type1, "paper2": kappa_paper_type2,
+                 "paper3": lambda m: kappa_const(m, m, m)}[name](n)
+        return dict(n=(n, n, n), kappa=kappa, bc=BC_ALL_DIRICHLET.copy(),
+                    b=rhs_uniform(n, n, n, 701), t=None)
     raise KeyError(name)
