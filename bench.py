@@ -36,19 +36,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_traffic_jump256.json")
 SWEEP_SRCS = [os.path.join(ROOT, "paper_1909_09771_amd", "csrc", f)
               for f in ("ntd_sweep.h", "ntd_internal.h", "ntd_apply_f32.hip", "ntd_apply_f64.hip")]
 
-# Algorithmic HBM bytes per unknown of each sweep launch.  Lower: the FP64
-# right-hand side, the four factor arrays (e1, 1/M, f2, g3) and the
-# intermediate z written in the factor precision.  Upper: z read back, the four
-# factor arrays, the final FP64 output, r read again for the fused r.z partial,
-# and with the ILU(0) combination the base zi added to the output.
+# Algorithmic HBM bytes per unknown of each sweep launch (e = bytes of the
+# factor precision).  Lower: the packed right-hand side, the four factor arrays
+# (e1, 1/M, f2, g3) and the intermediate z written.  Upper: z read back, the
+# four factor arrays and the final x written.  The FP64 right-hand side and
+# output, the ILU(0) base and the r.z partials move in the pack and unpack
+# kernels around the sweeps.
 FACTOR_BYTES = {"mixed": 4, "fp64": 8}
 
 
 def apply_bytes(prec: str, smoother: str):
     e = FACTOR_BYTES[prec]
-    lower = 8 + 4 * e + e
-    upper = e + 4 * e + 8 + 8 + (8 if smoother == "ilu0" else 0)
-    return {"lower": lower, "upper": upper}
+    return {"lower": 6 * e, "upper": 6 * e}
 
 
 # The smoother part of the combination: the ILU(0) forward and backward level
