@@ -111,9 +111,11 @@ int ntd_apply_ilu0(ntd_handle *h, const double *r, double *z, void *stream);
  * the fused r.z partials), but synchronous; ms[0..3] (HOST) receive durations
  * in milliseconds measured with HIP events on `stream`: ms[0..2] the three
  * sweep launches (lower level-3 sweep of the two half chains, twist plane,
- * upper level-3 sweep), ms[3] the smoother part before them (ILU(0) sweeps and
- * the residual r - A zi; without a smoother only the gap between two
- * back-to-back events).  For benchmarking. */
+ * upper level-3 sweep), ms[3] the rest of the application: the ILU(0) sweeps
+ * when the handle has the smoother, the packing of the right-hand side into
+ * the sweep layout (with r - A zi fused in when there is a smoother) and the
+ * unpacking of the result to FP64 (with the r.z partials).  For
+ * benchmarking. */
 int ntd_apply_profile(ntd_handle *h, const double *r, double *z, float *ms, void *stream);
 
 /* y = A x with the assembled 7-point bands.  [N] device FP64, no overlap.

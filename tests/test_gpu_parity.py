@@ -275,7 +275,7 @@ def test_deterministic_repeat():
 # ---------------------------------------------------------------------------
 
 ILU_SHAPES = [((16, 12, 20), "jump"), ((7, 11, 37), "rand"), ((5, 4, 3), "rand"), ((1, 6, 9), "jump"),
-              ((9, 1, 1), "rand"), ((2, 2, 2), "poisson")]
+              ((9, 1, 1), "rand"), ((2, 2, 2), "poisson"), ((41, 35, 24), "jump")]
 
 
 @pytest.mark.parametrize("shape,kind", ILU_SHAPES)
