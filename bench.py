@@ -81,11 +81,19 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="run the preconditioner, the SpMV and a calibration copy, then exit")
     ap.add_argument("--reps", type=int, default=3, help="launches per kernel in --kernels-only")
-    ap.add_argument("--suite", default=None, choices=["paper"],
+    ap.add_argument("--suite", default=None, choices=["paper", "batch"],
                     help="paper: the test matrices of Sec. 3 (Types 1-3, 100^3/200^3/350^3, "
-                         "tol 1e-7 and 1e-10), one JSON line per case")
+                         "tol 1e-7 and 1e-10), one JSON line per case; batch: many independent "
+                         "systems solved together, one JSON line per batch size")
     ap.add_argument("--sizes", default="100,200,350", help="cube sides of --suite paper")
     ap.add_argument("--precs", default="mixed,fp64", help="precisions of --suite paper")
+    ap.add_argument("--batch-counts", default="64", help="systems per batch (--suite batch)")
+    ap.add_argument("--batch-rhs", type=int, default=4, help="right-hand sides per system")
+    ap.add_argument("--batch-n", type=int, default=None,
+                    help="one cube side for every system (default: U{32..96} per system)")
+    ap.add_argument("--batch-schur", default="diag", choices=["diag", "newton"])
+    ap.add_argument("--batch-seq", action="store_true",
+                    help="also solve the systems one at a time (one right-hand side each)")
     return ap.parse_args()
 
 
@@ -205,6 +213,84 @@ def paper_suite(args):
 P_BC_ALL = [0, 0, 0, 0, 0, 0]
 
 
+def batch_suite(args):
+    """Many independent systems solved together: `count` cubes of side
+    U{32..96} (or --batch-n), kappa constant on 8 z-slabs (10^U(-4,4)),
+    Dirichlet faces, nrhs right-hand sides each (workloads.batch_systems).  Times
+    the batch setup, the batched PCG to tol (the second of two solves; the first
+    captures the iteration graph), and the batched preconditioner apply with the
+    sweeps event-timed.  The roofline is that of the lower sweep launch:
+    algorithmic bytes = per system, over the unknowns outside the twist plane,
+    the four factor arrays once (4e) and the packed right-hand side and result
+    of every right-hand side (2e each)."""
+    import torch
+    import paper_1909_09771_amd as P
+    import workloads as W
+    dev = torch.device("cuda:0")
+    prec, schur, nrhs = args.prec, args.batch_schur, args.batch_rhs
+    e = FACTOR_BYTES[prec]
+    for count in [int(v) for v in args.batch_counts.split(",")]:
+        systems = W.batch_systems(count, nrhs, n_fixed=args.batch_n)
+        sides = [s["n"][0] for s in systems]
+        kappas = [torch.from_numpy(s["kappa"]).to(dev) for s in systems]
+        bs = [torch.from_numpy(b).to(dev) for s in systems for b in s["bs"]]
+        del systems
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B = P.Batch(kappas, P_BC_ALL, nrhs=nrhs, prec=prec, schur=schur)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        log("batch of %d systems x %d rhs: setup %.3f s" % (count, nrhs, t1 - t0))
+        B.pcg(bs, tol=args.tol, maxit=args.maxit, graph=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        xs, its, rrs, sts = B.pcg(bs, tol=args.tol, maxit=args.maxit, graph=True)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        log("batched PCG: %.3f s, iterations %d..%d" % (t3 - t2, min(its), max(its)))
+        zs = B.empty_like_entries()
+        B.apply_profile(bs, zs)
+        prof = [B.apply_profile(bs, zs) for _ in range(5)]
+        lower_ms, twist_ms, upper_ms, rest_ms = [sorted(p[i] for p in prof)[2] for i in range(4)]
+        units = sum(n ** 3 - n ** 2 for n in sides)
+        by = sum((n ** 3 - n ** 2) * (4 * e + 2 * e * nrhs) for n in sides)
+        achieved = by / (lower_ms * 1e-3) / 1e9
+        line = {"suite": "batch", "systems": count, "nrhs": nrhs, "entries": count * nrhs,
+                "sides": [min(sides), max(sides)], "unknowns": sum(n ** 3 for n in sides),
+                "prec": prec, "schur": schur, "tol": args.tol,
+                "setup_s": round(t1 - t0, 4), "solve_s": round(t3 - t2, 4),
+                "first_solve_s": round(t2 - t1, 4),
+                "iters": {"min": min(its), "max": max(its),
+                          "mean": round(sum(its) / len(its), 2)},
+                "max_relres": max(rrs), "all_ok": all(st == 0 for st in sts),
+                "apply_ms": {"lower": round(lower_ms, 4), "twist": round(twist_ms, 4),
+                             "upper": round(upper_ms, 4), "rest": round(rest_ms, 4)},
+                "roofline": {"kernel": "k_apply_lower_b", "bound": "hbm",
+                             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                             "unknowns_per_launch": units,
+                             "bytes_per_unknown": "4e + 2e x nrhs, e = %d" % e},
+                "footprint_bytes": B.footprint_bytes}
+        del xs, zs
+        B.close()
+        del B
+        torch.cuda.empty_cache()
+        if args.batch_seq:
+            # the same systems one at a time, first right-hand side only
+            t4 = time.perf_counter()
+            for s, kap in enumerate(kappas):
+                S = P.Solver(kap, P_BC_ALL, prec=prec, schur=schur)
+                S.pcg(bs[s * nrhs], tol=args.tol, maxit=args.maxit)
+                del S
+            torch.cuda.synchronize()
+            t5 = time.perf_counter()
+            line["sequential_one_rhs_s"] = round(t5 - t4, 4)
+            log("one system at a time (setup + PCG, one rhs each): %.3f s" % (t5 - t4))
+        print(json.dumps(line), flush=True)
+        del kappas, bs
+        torch.cuda.empty_cache()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -213,6 +299,9 @@ def main():
         sys.exit(2)
     if args.suite == "paper":
         paper_suite(args)
+        return
+    if args.suite == "batch":
+        batch_suite(args)
         return
     import torch
     import paper_1909_09771_amd as P

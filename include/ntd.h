@@ -155,6 +155,74 @@ size_t ntd_footprint_bytes(const ntd_handle *h);
 /* Release the host-side state of the handle (not the caller's workspace). */
 int ntd_destroy(ntd_handle *h);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent systems, each with several right-hand sides,
+ * preconditioned with B (Sec. 2; no smoother) and solved together.  Every
+ * launch of a batched step covers all right-hand sides of the batch, so the
+ * sweeps of B run as 4 * count * nrhs independent chains at once instead of 4.
+ * A batch entry computes the same operators as the single-system entry points
+ * for its system, up to rounding (its lines may carry pass-through slots, see
+ * ntd_batch_setup).
+ * ------------------------------------------------------------------------- */
+typedef struct ntd_batch ntd_batch;
+
+/* Most systems in one batch, most right-hand sides per system, and the
+ * longest line (the batched sweeps cover up to 8 elements per lane). */
+#define NTD_BATCH_MAX_SYSTEMS 4096
+#define NTD_BATCH_MAX_RHS 16
+#define NTD_BATCH_MAX_NX 512
+
+/* Flags of ntd_batch_pcg_solve. */
+#define NTD_BATCH_GRAPH 1  /* run the iterations as replays of one captured HIP graph */
+
+/* Bytes of device workspace for a batch of `count` systems with grid sizes
+ * dims[3*s + 0..2] = (nx, ny, nz) (HOST) and nrhs right-hand sides each.
+ * Returns 0 for invalid arguments. */
+size_t ntd_batch_workspace_bytes(int count, const int *dims, int nrhs, int prec);
+
+/* Set up every system of a batch as ntd_setup would (smoother none):
+ *   dims   [3*count] HOST grid sizes; nx <= NTD_BATCH_MAX_NX
+ *   kappa  [count] HOST array of device pointers, kappa[s] of N_s values
+ *   bc     [6*count] HOST face types, 6 per system
+ *   nrhs   1..NTD_BATCH_MAX_RHS; prec NTD_PREC_*; schur NTD_SCHUR_*
+ *   workspace device buffer of >= ntd_batch_workspace_bytes(), 256-byte
+ *          aligned, owned by the caller until ntd_batch_destroy
+ * Every system of the batch is packed with the elements per lane of its
+ * longest line (shorter lines carry pass-through slots), so that one launch
+ * runs all of them.  Synchronises `stream`.  On failure *out = NULL and the
+ * status of the first failing system is returned. */
+int ntd_batch_setup(int count, const int *dims, const double *const *kappa, const int *bc,
+                    int nrhs, int prec, int schur, void *workspace, size_t workspace_bytes,
+                    void *stream, ntd_batch **out);
+
+/* z[e] = B_s^{-1} r[e] for every entry e = s*nrhs + q (system s, right-hand
+ * side q).  r, z: [count*nrhs] HOST arrays of device pointers to [N_s] FP64
+ * vectors; r[e] and z[e] must not overlap.  Stream-ordered, asynchronous. */
+int ntd_batch_apply(ntd_batch *b, const double *const *r, double *const *z, void *stream);
+
+/* As ntd_batch_apply, but synchronous, with ms[0..3] (HOST) the durations in
+ * milliseconds of the lower sweep, the twist planes, the upper sweep and the
+ * rest (packing and unpacking), measured with HIP events on `stream`. */
+int ntd_batch_apply_profile(ntd_batch *b, const double *const *r, double *const *z, float *ms,
+                            void *stream);
+
+/* PCG for every entry (rules of ntd_pcg_solve, applied per entry): rhs[e] and
+ * x[e] as r and z above; iters, relres, status: [count*nrhs] HOST outputs per
+ * entry (iterations, final true relative residual, NTD_OK / NTD_ENOCONV /
+ * NTD_EBREAKDOWN).  Every entry keeps its scalars on the device and stops on
+ * its own; the host checks the batch between runs of iterations.  flags:
+ * NTD_BATCH_GRAPH or 0.  Returns NTD_OK when the batch ran (per-entry outcomes
+ * are in status) or an error.  Synchronises `stream`. */
+int ntd_batch_pcg_solve(ntd_batch *b, const double *const *rhs, double *const *x, double tol,
+                        int maxit, int flags, int *iters, double *relres, int *status,
+                        void *stream);
+
+/* Device bytes the batch keeps in use inside its workspace. */
+size_t ntd_batch_footprint_bytes(const ntd_batch *b);
+
+/* Release the host-side state of the batch (not the caller's workspace). */
+int ntd_batch_destroy(ntd_batch *b);
+
 /* Static text for a status code. */
 const char *ntd_strerror(int status);
 

@@ -70,6 +70,23 @@ def lib() -> ctypes.CDLL:
         L.ntd_destroy.restype = I
         L.ntd_strerror.argtypes = [I]
         L.ntd_strerror.restype = ctypes.c_char_p
+        PP = ctypes.POINTER(P)
+        L.ntd_batch_workspace_bytes.argtypes = [I, ctypes.POINTER(I), I, I]
+        L.ntd_batch_workspace_bytes.restype = Z
+        L.ntd_batch_setup.argtypes = [I, ctypes.POINTER(I), PP, ctypes.POINTER(I), I, I, I, P, Z, P,
+                                      ctypes.POINTER(P)]
+        L.ntd_batch_setup.restype = I
+        L.ntd_batch_apply.argtypes = [P, PP, PP, P]
+        L.ntd_batch_apply.restype = I
+        L.ntd_batch_apply_profile.argtypes = [P, PP, PP, ctypes.POINTER(ctypes.c_float), P]
+        L.ntd_batch_apply_profile.restype = I
+        L.ntd_batch_pcg_solve.argtypes = [P, PP, PP, D, I, I, ctypes.POINTER(I), ctypes.POINTER(D),
+                                          ctypes.POINTER(I), P]
+        L.ntd_batch_pcg_solve.restype = I
+        L.ntd_batch_footprint_bytes.argtypes = [P]
+        L.ntd_batch_footprint_bytes.restype = Z
+        L.ntd_batch_destroy.argtypes = [P]
+        L.ntd_batch_destroy.restype = I
         _lib = L
     return _lib
 
@@ -226,6 +243,131 @@ class Solver:
     def close(self):
         if getattr(self, "_h", None):
             lib().ntd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+BATCH_GRAPH = 1
+
+
+def _ptr_array(tensors):
+    return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+
+
+class Batch:
+    """Many independent systems, nrhs right-hand sides each, preconditioned with
+    B (no smoother) and solved together: every batched launch covers all
+    systems and right-hand sides.
+
+    kappas: list of float64 CUDA tensors (nz, ny, nx), one per system (sizes may
+    differ; nx <= 512).  bcs: one six-int face list per system, or a single list
+    for all.  Entry e = s * nrhs + q is right-hand side q of system s; the
+    methods take and return flat lists of [N_s] tensors in that order.
+    """
+
+    def __init__(self, kappas, bcs, nrhs: int = 1, prec: str = "mixed", schur: str = "diag"):
+        if len(kappas) == 0:
+            raise ValueError("a batch needs at least one system")
+        self.device = kappas[0].device
+        self.shapes = [tuple(k.shape) for k in kappas]
+        for k, sh in zip(kappas, self.shapes):
+            if k.dim() != 3:
+                raise ValueError("kappa must have shape (nz, ny, nx)")
+            _check_vec(k, sh, self.device, "kappa")
+        if len(bcs) > 0 and not hasattr(bcs[0], "__len__"):  # one face list for all
+            bcs = [bcs] * len(kappas)
+        if len(bcs) != len(kappas):
+            raise ValueError("one face list per system")
+        self.count, self.nrhs, self.prec, self.schur = len(kappas), int(nrhs), prec, schur
+        dims = []
+        for (nz, ny, nx) in self.shapes:
+            dims += [nx, ny, nz]
+        self._dims = (ctypes.c_int * len(dims))(*dims)
+        L = lib()
+        nbytes = int(L.ntd_batch_workspace_bytes(self.count, self._dims, self.nrhs, PREC[prec]))
+        if nbytes == 0:
+            raise NTDError(EINVAL, "ntd_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        bc_flat = [int(v) for bc in bcs for v in bc]
+        bc_arr = (ctypes.c_int * len(bc_flat))(*bc_flat)
+        self._kappas = list(kappas)  # kept alive only through setup
+        h = ctypes.c_void_p()
+        st = L.ntd_batch_setup(self.count, self._dims, _ptr_array(self._kappas), bc_arr, self.nrhs,
+                               PREC[prec], SCHUR[schur], _dptr(self.workspace), nbytes,
+                               _stream_ptr(self.device), ctypes.byref(h))
+        self._kappas = None
+        if st != OK:
+            raise NTDError(st, "ntd_batch_setup")
+        self._h = h
+
+    @property
+    def entries(self) -> int:
+        return self.count * self.nrhs
+
+    def entry_shape(self, e: int):
+        return self.shapes[e // self.nrhs]
+
+    def _check_list(self, vecs, name):
+        if len(vecs) != self.entries:
+            raise ValueError("%s: expected %d vectors (systems x rhs)" % (name, self.entries))
+        for e, v in enumerate(vecs):
+            _check_vec(v, self.entry_shape(e), self.device, "%s[%d]" % (name, e))
+
+    def empty_like_entries(self):
+        return [torch.empty(self.entry_shape(e), dtype=torch.float64, device=self.device)
+                for e in range(self.entries)]
+
+    def apply(self, rs, zs=None):
+        """z[e] = B_s^{-1} r[e] for every entry."""
+        self._check_list(rs, "r")
+        zs = self.empty_like_entries() if zs is None else zs
+        self._check_list(zs, "z")
+        st = lib().ntd_batch_apply(self._h, _ptr_array(rs), _ptr_array(zs),
+                                   _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_batch_apply")
+        return zs
+
+    def apply_profile(self, rs, zs):
+        """As apply, synchronous; returns the event-timed durations (ms) of the
+        lower sweep, the twist planes, the upper sweep and the rest."""
+        self._check_list(rs, "r")
+        self._check_list(zs, "z")
+        ms = (ctypes.c_float * 4)()
+        st = lib().ntd_batch_apply_profile(self._h, _ptr_array(rs), _ptr_array(zs), ms,
+                                           _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_batch_apply_profile")
+        return tuple(float(v) for v in ms)
+
+    def pcg(self, bs, tol: float = 1e-8, maxit: int = 1000, graph: bool = True, xs=None):
+        """PCG for every entry; returns (xs, iters, relres, status) with per-entry lists."""
+        self._check_list(bs, "b")
+        xs = self.empty_like_entries() if xs is None else xs
+        self._check_list(xs, "x")
+        n = self.entries
+        it = (ctypes.c_int * n)()
+        rr = (ctypes.c_double * n)()
+        stv = (ctypes.c_int * n)()
+        st = lib().ntd_batch_pcg_solve(self._h, _ptr_array(bs), _ptr_array(xs), float(tol),
+                                       int(maxit), BATCH_GRAPH if graph else 0, it, rr, stv,
+                                       _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_batch_pcg_solve")
+        return xs, list(it), list(rr), list(stv)
+
+    @property
+    def footprint_bytes(self) -> int:
+        return int(lib().ntd_batch_footprint_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ntd_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -7,70 +7,52 @@
 #include <string.h>
 
 #include "ntd.h"
-#include "ntd_internal.h"
+#include "ntd_handle.h"
 
 using ntd::Scalars;
 
-struct ntd_handle {
-    int nx, ny, nz, prec, schur, smoother, epl;
-    ntd::IluGrid ilu;                         // ILU(0) level schedule (smoother only)
-    double *dt, *dtinv, *zi, *tv;             // ILU(0) diagonal, its inverse, two work vectors
-    long long N, nxy, npack;                  // npack = ny*nz*64*epl packed slots
-    size_t used;
-    double *d, *ax, *ay, *az;                 // bands of A
-    double *e1, *mv, *f2, *dT, *dP, *xP;      // factors (FP64, natural layout) and setup state
-    double *r, *z, *p, *q;                    // PCG vectors
-    void *rec;                                // line records of the apply (float in MIXED)
-    void *pZ, *rp;                            // packed result and right-hand side
-    void *scratch;                            // setup planes / packed apply planes
-    double *partials;
-    Scalars *sc;
-    int *flag;
-};
+namespace ntd_host {
 
-namespace {
-
-constexpr size_t kAlign = 256;
-
-inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
-
-// Walks the workspace: identical for sizing (base == nullptr) and carving.
-struct Carver {
-    char *base;
-    size_t off = 0;
-    explicit Carver(void *b) : base((char *)b) {}
-    template <typename T>
-    T *take(size_t count) {
-        size_t o = off;
-        off = align_up(off + count * sizeof(T));
-        return base ? (T *)(base + o) : nullptr;
-    }
-};
-
-bool grid_ok(int nx, int ny, int nz) {
+bool grid_ok(int nx, int ny, int nz, int epl) {
     if (nx < 1 || ny < 1 || nz < 1) return false;
-    if (nx > NTD_MAX_NX || ntd::epl_for(nx) == 0) return false;
+    if (nx > NTD_MAX_NX || epl < ntd::epl_for(nx) || ntd::epl_for(nx) == 0) return false;
     // FP64 arrays are addressed with 32-bit byte offsets, the records and packed
     // vectors of one plane too
-    const int epl = ntd::epl_for(nx);
     const long long N = (long long)nx * ny * nz;
     const long long npack = (long long)ny * nz * 64 * epl;
     const long long plane_rec = (long long)ny * ntd::rec_bytes(sizeof(double), epl);
     return N * 8 < 0x7fffffffLL && npack * 8 < 0x7fffffffLL && plane_rec < 0x7fffffffLL;
 }
 
-size_t layout(ntd_handle *h, void *ws, int nx, int ny, int nz, int prec, int smoother) {
+}  // namespace ntd_host
+
+namespace {
+
+using ntd_host::Carver;
+using ntd_host::apply_args;
+using ntd_host::xfer_args;
+using ntd_host::kAlign;
+
+size_t layout(ntd_handle *h, void *ws, int nx, int ny, int nz, int prec, int smoother, int epl,
+              bool lean) {
     const long long N = (long long)nx * ny * nz, nxy = (long long)nx * ny;
-    const long long lane_slots = 64LL * ntd::epl_for(nx);
+    const long long lane_slots = 64LL * epl;
     const long long npack = (long long)ny * nz * lane_slots;
     const size_t tsz = prec == NTD_PREC_MIXED ? sizeof(float) : sizeof(double);
     Carver c(ws);
-    double **f64[] = {&h->d, &h->ax, &h->ay, &h->az, &h->e1, &h->mv, &h->f2,
-                      &h->dT, &h->dP, &h->xP, &h->r, &h->z, &h->p, &h->q};
+    double **f64[] = {&h->d, &h->ax, &h->ay, &h->az, &h->e1, &h->mv, &h->f2, &h->dT, &h->dP, &h->xP};
     for (double **a : f64) *a = c.take<double>(N);
-    h->rec = (void *)c.take<char>((size_t)ny * nz * ntd::rec_bytes((unsigned)tsz, ntd::epl_for(nx)));
-    h->pZ = (void *)c.take<char>(npack * tsz);
-    h->rp = (void *)c.take<char>(npack * tsz);
+    h->r = h->z = h->p = h->q = nullptr;
+    h->pZ = h->rp = nullptr;
+    if (!lean) {
+        double **vec[] = {&h->r, &h->z, &h->p, &h->q};
+        for (double **a : vec) *a = c.take<double>(N);
+    }
+    h->rec = (void *)c.take<char>((size_t)ny * nz * ntd::rec_bytes((unsigned)tsz, epl));
+    if (!lean) {
+        h->pZ = (void *)c.take<char>(npack * tsz);
+        h->rp = (void *)c.take<char>(npack * tsz);
+    }
     h->dt = h->dtinv = h->zi = h->tv = nullptr;
     if (smoother == NTD_SMOOTHER_ILU0) {
         double **ilu[] = {&h->dt, &h->dtinv, &h->zi, &h->tv};
@@ -98,14 +80,6 @@ ntd::Grid grid_of(const ntd_handle *h) {
     return g;
 }
 
-template <typename T>
-ntd::ApplyArgs<T> apply_args(const ntd_handle *h) {
-    ntd::ApplyArgs<T> a;
-    a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
-    a.rec = h->rec; a.rp = (const T *)h->rp; a.Z = (T *)h->pZ; a.scratch = (T *)h->scratch;
-    return a;
-}
-
 ntd::PackArgs pack_args(const ntd_handle *h) {
     ntd::PackArgs p;
     p.nx = h->nx; p.ny = h->ny; p.nz = h->nz;
@@ -114,21 +88,6 @@ ntd::PackArgs pack_args(const ntd_handle *h) {
     return p;
 }
 
-template <typename T>
-ntd::XferArgs<T> xfer_args(const ntd_handle *h) {
-    ntd::XferArgs<T> x;
-    x.nx = h->nx; x.ny = h->ny; x.nz = h->nz;
-    x.r = nullptr; x.zi = nullptr;
-    x.d = h->d; x.ax = h->ax; x.ay = h->ay; x.az = h->az;
-    x.rp = (T *)h->rp; x.Z = (const T *)h->pZ; x.zout = nullptr; x.partials = nullptr;
-    return x;
-}
-
-// z = B^{-1} rhs with rhs = r, or r - A zi when zi is given (then z = zi +
-// B^{-1}(r - A zi)): pack the right-hand side, run the three sweep launches,
-// unpack.  With partials, the unpack also writes per-block partials of r.z and
-// *np their count.  ev (if not null, 6 events): ev[0] before the pack, ev[1..4]
-// bracket the sweeps, ev[5] after the unpack.
 // Launchers of one precision, picked by overload.
 hipError_t pack_rhs(const ntd::XferArgs<float> &x, int epl, hipStream_t s) {
     return ntd::launch_pack_rhs_f32(x, epl, s);
@@ -242,21 +201,21 @@ int true_relres(ntd_handle *h, const double *b, const double *x, double bn, doub
 
 }  // namespace
 
-extern "C" {
+namespace ntd_host {
 
-size_t ntd_workspace_bytes(int nx, int ny, int nz, int prec, int smoother) {
-    if (!grid_ok(nx, ny, nz) || (prec != NTD_PREC_FP64 && prec != NTD_PREC_MIXED)) return 0;
+size_t handle_bytes(int nx, int ny, int nz, int prec, int smoother, int epl, bool lean) {
+    if (!grid_ok(nx, ny, nz, epl) || (prec != NTD_PREC_FP64 && prec != NTD_PREC_MIXED)) return 0;
     if (smoother != NTD_SMOOTHER_NONE && smoother != NTD_SMOOTHER_ILU0) return 0;
     ntd_handle tmp;
-    return layout(&tmp, nullptr, nx, ny, nz, prec, smoother);
+    return layout(&tmp, nullptr, nx, ny, nz, prec, smoother, epl, lean);
 }
 
-int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const double *t,
-              int prec, int schur, int smoother, void *workspace, size_t workspace_bytes,
-              void *stream, ntd_handle **out) {
+int setup_handle(int nx, int ny, int nz, const double *kappa, const int *bc, const double *t,
+                 int prec, int schur, int smoother, int epl, bool lean, void *workspace,
+                 size_t workspace_bytes, hipStream_t s, ntd_handle **out) {
     if (out) *out = nullptr;
     if (!out || !kappa || !bc || !workspace) return NTD_EINVAL;
-    if (!grid_ok(nx, ny, nz)) return NTD_EINVAL;
+    if (!grid_ok(nx, ny, nz, epl)) return NTD_EINVAL;
     if (prec != NTD_PREC_FP64 && prec != NTD_PREC_MIXED) return NTD_EINVAL;
     if (schur != NTD_SCHUR_NEWTON && schur != NTD_SCHUR_DIAG) return NTD_EINVAL;
     if (smoother != NTD_SMOOTHER_NONE && smoother != NTD_SMOOTHER_ILU0) return NTD_EINVAL;
@@ -267,19 +226,18 @@ int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const 
     }
     if (ndir == 0) return NTD_EINVAL;  // pure Neumann: A is singular
     if (((uintptr_t)workspace) % kAlign) return NTD_EINVAL;
-    if (workspace_bytes < ntd_workspace_bytes(nx, ny, nz, prec, smoother)) return NTD_EINVAL;
+    if (workspace_bytes < handle_bytes(nx, ny, nz, prec, smoother, epl, lean)) return NTD_EINVAL;
 
     ntd_handle *h = (ntd_handle *)calloc(1, sizeof(ntd_handle));
     if (!h) return NTD_ENOMEM;
     h->nx = nx; h->ny = ny; h->nz = nz; h->prec = prec; h->schur = schur;
     h->smoother = smoother;
-    h->epl = ntd::epl_for(nx);
+    h->epl = epl;
     h->N = (long long)nx * ny * nz;
     h->nxy = (long long)nx * ny;
     h->npack = (long long)ny * nz * 64 * h->epl;
-    h->used = layout(h, workspace, nx, ny, nz, prec, smoother);
+    h->used = layout(h, workspace, nx, ny, nz, prec, smoother, epl, lean);
     h->ilu = ntd::ilu_grid(nx, ny, nz, 2);
-    hipStream_t s = S(stream);
     int st = NTD_OK;
     int hflag = 0;
     ntd::Grid g = grid_of(h);
@@ -306,8 +264,9 @@ int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const 
     if ((st = pack_factors(h, s)) != NTD_OK) goto fail;
     // unused slots of the packed right-hand side are never written by the
     // packing of a right-hand side and must read as 0
-    HK(ntd::launch_fill((double *)h->rp, 0.0,
-                        h->npack * (h->prec == NTD_PREC_FP64 ? 8 : 4) / 8, s));
+    if (h->rp)
+        HK(ntd::launch_fill((double *)h->rp, 0.0,
+                            h->npack * (h->prec == NTD_PREC_FP64 ? 8 : 4) / 8, s));
     HK(hipStreamSynchronize(s));
     *out = h;
     return NTD_OK;
@@ -316,6 +275,25 @@ fail:
     return st;
 #undef FAIL
 #undef HK
+}
+
+}  // namespace ntd_host
+
+extern "C" {
+
+size_t ntd_workspace_bytes(int nx, int ny, int nz, int prec, int smoother) {
+    if (nx < 1) return 0;
+    return ntd_host::handle_bytes(nx, ny, nz, prec, smoother, ntd::epl_for(nx), false);
+}
+
+int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const double *t,
+              int prec, int schur, int smoother, void *workspace, size_t workspace_bytes,
+              void *stream, ntd_handle **out) {
+    if (out) *out = nullptr;
+    if (nx < 1) return NTD_EINVAL;
+    return ntd_host::setup_handle(nx, ny, nz, kappa, bc, t, prec, schur, smoother,
+                                  ntd::epl_for(nx), false, workspace, workspace_bytes,
+                                  S(stream), out);
 }
 
 int ntd_apply_precond(ntd_handle *h, const double *r, double *z, void *stream) {

@@ -327,13 +327,11 @@ __device__ __forceinline__ void lower_plane(const ApplyArgs<T> &a, int k, int kn
     plane_solve<kApplyDepth<T, EPL>>(a.ny, F, pol, lds);
 }
 
-// Lower level-3 sweep of one half: block 0 takes planes 0..j3-1 upward, block 1
+// Lower level-3 sweep of one half: half 0 takes planes 0..j3-1 upward, half 1
 // planes nz-1..j3+1 downward; z_k = Pt_k^{-1}(r_k - g * z_{k-+1}) into Z.
 template <typename T, int EPL>
-__global__ void __launch_bounds__(kApplyThreads) k_apply_lower(ApplyArgs<T> a) {
-    __shared__ T lds[2 * 64 * EPL];
+__device__ __forceinline__ void apply_lower(const ApplyArgs<T> &a, int h, T *lds) {
     const int nz = a.nz, j3 = (nz - 1) / 2;
-    const int h = blockIdx.x;
     const int dk = h == 0 ? 1 : -1;
     const int k0 = h == 0 ? 0 : nz - 1;
     if (h == 0 ? k0 >= j3 : k0 <= j3) return;
@@ -343,8 +341,7 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply_lower(ApplyArgs<T> a) {
 
 // The twist plane j3 takes both neighbours; its result is final.
 template <typename T, int EPL>
-__global__ void __launch_bounds__(kApplyThreads) k_apply_twist(ApplyArgs<T> a) {
-    __shared__ T lds[2 * 64 * EPL];
+__device__ __forceinline__ void apply_twist(const ApplyArgs<T> &a, T *lds) {
     constexpr unsigned kArr = RecFmt<T, EPL>::kArr;
     const int nz = a.nz, k = (nz - 1) / 2;
     PolTwist<T, EPL> pol;
@@ -361,14 +358,12 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply_twist(ApplyArgs<T> a) {
     plane_solve<kApplyDepth<T, EPL>>(a.ny, F, pol, lds);
 }
 
-// Upper level-3 sweep: block 0 takes planes j3-1..0, block 1 planes j3+1..nz-1;
+// Upper level-3 sweep: half 0 takes planes j3-1..0, half 1 planes j3+1..nz-1;
 // x_k = z_k - Pt_k^{-1}(g * x_{k+-1}), written over Z.
 template <typename T, int EPL>
-__global__ void __launch_bounds__(kApplyThreads) k_apply_upper(ApplyArgs<T> a) {
-    __shared__ T lds[2 * 64 * EPL];
+__device__ __forceinline__ void apply_upper(const ApplyArgs<T> &a, int h, T *lds) {
     constexpr unsigned kArr = RecFmt<T, EPL>::kArr;
     const int ny = a.ny, nz = a.nz, j3 = (nz - 1) / 2;
-    const int h = blockIdx.x;
     const int dk = h == 0 ? -1 : 1;
     const rsrc_t W = make_rsrc(a.scratch + (size_t)h * ny * 64 * EPL);
     for (int k = j3 + dk; k >= 0 && k < nz; k += dk) {
@@ -381,6 +376,99 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply_upper(ApplyArgs<T> a) {
         pol.vG = F.vA + (kn < k ? kRecGdn : kRecGup) * kArr;
         plane_solve<kApplyDepth<T, EPL>>(ny, F, pol, lds);
     }
+}
+
+// One system: blockIdx.x is the level-3 half (lower and upper sweeps).
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_lower(ApplyArgs<T> a) {
+    __shared__ T lds[2 * 64 * EPL];
+    apply_lower<T, EPL>(a, blockIdx.x, lds);
+}
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_twist(ApplyArgs<T> a) {
+    __shared__ T lds[2 * 64 * EPL];
+    apply_twist<T, EPL>(a, lds);
+}
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_upper(ApplyArgs<T> a) {
+    __shared__ T lds[2 * 64 * EPL];
+    apply_upper<T, EPL>(a, blockIdx.x, lds);
+}
+
+// A batch: a table of arguments in device memory, entry e = s*nrhs + q for
+// right-hand side q of system s; entries whose active flag is 0 (when active
+// is given) do nothing.  The entry is read once per block into scalar
+// registers, so the sweeps see wave-uniform arguments as above.
+template <typename S>
+__device__ __forceinline__ S load_uniform(const S *p) {
+    static_assert(sizeof(S) % 4 == 0, "word-sized descriptor");
+    S out;
+    const unsigned *src = (const unsigned *)p;
+    unsigned *dst = (unsigned *)&out;
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(S) / 4; ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return out;
+}
+
+__device__ __forceinline__ bool entry_active(const int *active, int e) {
+    return !active || __builtin_amdgcn_readfirstlane(active[e]) != 0;
+}
+
+// Workgroups are dispatched round-robin over the XCDs (workgroup id mod 8), and
+// each XCD has its own L2.  The sweeps of the right-hand sides of one system
+// (and level-3 half) read the same line records at nearly the same time, so
+// they are given workgroup ids that are equal mod 8: group g = s*halves + h
+// goes to XCD g mod 8, its nrhs members to consecutive ids of that XCD.  The
+// grid holds 8*nrhs*ceil(count*halves/8) workgroups; the padding ones exit.
+constexpr int kXcds = 8;
+
+struct BatchSlot {
+    int e, h;
+    bool ok;
+};
+
+__device__ __forceinline__ BatchSlot batch_slot(int count, int nrhs, int halves) {
+    const int w = blockIdx.x;
+    const int j = w / kXcds;
+    const int q = j % nrhs;
+    const int g = kXcds * (j / nrhs) + w % kXcds;
+    BatchSlot b;
+    b.ok = g < count * halves;
+    b.e = (g / halves) * nrhs + q;
+    b.h = g % halves;
+    return b;
+}
+
+inline unsigned batch_grid(int count, int nrhs, int halves) {
+    return (unsigned)(kXcds * nrhs * ((count * halves + kXcds - 1) / kXcds));
+}
+
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_lower_b(const ApplyArgs<T> *tab,
+                                                                 const int *active, int count,
+                                                                 int nrhs) {
+    __shared__ T lds[2 * 64 * EPL];
+    const BatchSlot b = batch_slot(count, nrhs, 2);
+    if (!b.ok || !entry_active(active, b.e)) return;
+    apply_lower<T, EPL>(load_uniform(tab + b.e), b.h, lds);
+}
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_twist_b(const ApplyArgs<T> *tab,
+                                                                 const int *active, int count,
+                                                                 int nrhs) {
+    __shared__ T lds[2 * 64 * EPL];
+    const BatchSlot b = batch_slot(count, nrhs, 1);
+    if (!b.ok || !entry_active(active, b.e)) return;
+    apply_twist<T, EPL>(load_uniform(tab + b.e), lds);
+}
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_upper_b(const ApplyArgs<T> *tab,
+                                                                 const int *active, int count,
+                                                                 int nrhs) {
+    __shared__ T lds[2 * 64 * EPL];
+    const BatchSlot b = batch_slot(count, nrhs, 2);
+    if (!b.ok || !entry_active(active, b.e)) return;
+    apply_upper<T, EPL>(load_uniform(tab + b.e), b.h, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -485,13 +573,14 @@ __device__ __forceinline__ int slot_of(int i, int n) {
     return 32 * EPL + (n - 1 - i) + 32 * EPL - cb;
 }
 
-// rp = r (or r - A zi), packed in the sweep precision.  Grids hold fewer than
-// 2^28 points, so 32-bit indices suffice.
+// rp = r (or r - A zi), packed in the sweep precision, over the points
+// blk*kBlock + t + i*nblk*kBlock.  Grids hold fewer than 2^28 points, so 32-bit
+// indices suffice.
 template <typename T, int EPL>
-__global__ void __launch_bounds__(kBlock) k_pack_rhs(XferArgs<T> x) {
+__device__ __forceinline__ void pack_rhs_body(const XferArgs<T> &x, unsigned blk, unsigned nblk) {
     const unsigned nx = (unsigned)x.nx, ny = (unsigned)x.ny, nz = (unsigned)x.nz;
     const unsigned nxy = nx * ny, N = nxy * nz;
-    for (unsigned p = blockIdx.x * kBlock + threadIdx.x; p < N; p += gridDim.x * kBlock) {
+    for (unsigned p = blk * kBlock + threadIdx.x; p < N; p += nblk * kBlock) {
         const unsigned line = p / nx;
         const unsigned i = p - line * nx;
         double v = x.r[p];
@@ -511,6 +600,11 @@ __global__ void __launch_bounds__(kBlock) k_pack_rhs(XferArgs<T> x) {
     }
 }
 
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kBlock) k_pack_rhs(XferArgs<T> x) {
+    pack_rhs_body<T, EPL>(x, blockIdx.x, gridDim.x);
+}
+
 // Fixed-order block reduction of one double per thread; thread 0 gets the sum.
 __device__ __forceinline__ double block_sum_apply(double v) {
     __shared__ double red[kBlock];
@@ -524,13 +618,14 @@ __device__ __forceinline__ double block_sum_apply(double v) {
     return red[0];
 }
 
-// zout = Z (+ zi), natural FP64; per-block partials of r.zout.
+// zout = Z (+ zi), natural FP64; the block's partial of r.zout into
+// partials[blk].
 template <typename T, int EPL>
-__global__ void __launch_bounds__(kBlock) k_unpack(XferArgs<T> x) {
+__device__ __forceinline__ void unpack_body(const XferArgs<T> &x, unsigned blk, unsigned nblk) {
     const unsigned nx = (unsigned)x.nx;
     const unsigned N = nx * (unsigned)x.ny * (unsigned)x.nz;
     double acc = 0.0;
-    for (unsigned p = blockIdx.x * kBlock + threadIdx.x; p < N; p += gridDim.x * kBlock) {
+    for (unsigned p = blk * kBlock + threadIdx.x; p < N; p += nblk * kBlock) {
         const unsigned line = p / nx;
         const unsigned i = p - line * nx;
         double z = (double)x.Z[line * (64u * EPL) + slot_of<EPL>((int)i, (int)nx)];
@@ -540,8 +635,25 @@ __global__ void __launch_bounds__(kBlock) k_unpack(XferArgs<T> x) {
     }
     if (x.partials) {
         const double t = block_sum_apply(acc);
-        if (threadIdx.x == 0) x.partials[blockIdx.x] = t;
+        if (threadIdx.x == 0) x.partials[blk] = t;
     }
+}
+
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kBlock) k_unpack(XferArgs<T> x) {
+    unpack_body<T, EPL>(x, blockIdx.x, gridDim.x);
+}
+
+// Batched moves: blockIdx.y selects the table entry, gridDim.x blocks per entry.
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kBlock) k_pack_rhs_b(const XferArgs<T> *tab, const int *active) {
+    if (!entry_active(active, blockIdx.y)) return;
+    pack_rhs_body<T, EPL>(load_uniform(tab + blockIdx.y), blockIdx.x, gridDim.x);
+}
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kBlock) k_unpack_b(const XferArgs<T> *tab, const int *active) {
+    if (!entry_active(active, blockIdx.y)) return;
+    unpack_body<T, EPL>(load_uniform(tab + blockIdx.y), blockIdx.x, gridDim.x);
 }
 
 inline int xfer_blocks(long long N) {
@@ -562,6 +674,38 @@ hipError_t apply_impl(const ApplyArgs<T> &a, hipStream_t s, hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[2], s);
     hipLaunchKernelGGL((k_apply_upper<T, EPL>), dim3(2), dim3(kApplyThreads), 0, s, a);
     if (ev) (void)hipEventRecord(ev[3], s);
+    return hipGetLastError();
+}
+
+// The sweeps of a batch of count systems x nrhs right-hand sides, as three
+// launches.
+template <typename T, int EPL>
+hipError_t apply_batch_impl(const ApplyArgs<T> *tab, const int *active, int count, int nrhs,
+                            hipStream_t s, hipEvent_t *ev) {
+    if (ev) (void)hipEventRecord(ev[0], s);
+    hipLaunchKernelGGL((k_apply_lower_b<T, EPL>), dim3(batch_grid(count, nrhs, 2)),
+                       dim3(kApplyThreads), 0, s, tab, active, count, nrhs);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    hipLaunchKernelGGL((k_apply_twist_b<T, EPL>), dim3(batch_grid(count, nrhs, 1)),
+                       dim3(kApplyThreads), 0, s, tab, active, count, nrhs);
+    if (ev) (void)hipEventRecord(ev[2], s);
+    hipLaunchKernelGGL((k_apply_upper_b<T, EPL>), dim3(batch_grid(count, nrhs, 2)),
+                       dim3(kApplyThreads), 0, s, tab, active, count, nrhs);
+    if (ev) (void)hipEventRecord(ev[3], s);
+    return hipGetLastError();
+}
+
+template <typename T, int EPL>
+hipError_t pack_rhs_batch_impl(const XferArgs<T> *tab, const int *active, int count, int gx,
+                               hipStream_t s) {
+    hipLaunchKernelGGL((k_pack_rhs_b<T, EPL>), dim3(gx, count), dim3(kBlock), 0, s, tab, active);
+    return hipGetLastError();
+}
+
+template <typename T, int EPL>
+hipError_t unpack_batch_impl(const XferArgs<T> *tab, const int *active, int count, int gx,
+                             hipStream_t s) {
+    hipLaunchKernelGGL((k_unpack_b<T, EPL>), dim3(gx, count), dim3(kBlock), 0, s, tab, active);
     return hipGetLastError();
 }
 

@@ -40,4 +40,34 @@ hipError_t launch_unpack_f32(const XferArgs<float> &x, int epl, hipStream_t s, i
     }
 }
 
+hipError_t launch_apply_batch_f32(const ApplyArgs<float> *tab, const int *active, int count,
+                                  int nrhs, int epl, hipStream_t s, hipEvent_t *ev) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return apply_batch_impl<float, E>(tab, active, count, nrhs, s, ev);
+        NTD_BATCH_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pack_rhs_batch_f32(const XferArgs<float> *tab, const int *active, int count,
+                                     int gx, int epl, hipStream_t s) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return pack_rhs_batch_impl<float, E>(tab, active, count, gx, s);
+        NTD_BATCH_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_unpack_batch_f32(const XferArgs<float> *tab, const int *active, int count,
+                                   int gx, int epl, hipStream_t s) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return unpack_batch_impl<float, E>(tab, active, count, gx, s);
+        NTD_BATCH_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace ntd

@@ -40,4 +40,34 @@ hipError_t launch_unpack_f64(const XferArgs<double> &x, int epl, hipStream_t s, 
     }
 }
 
+hipError_t launch_apply_batch_f64(const ApplyArgs<double> *tab, const int *active, int count,
+                                  int nrhs, int epl, hipStream_t s, hipEvent_t *ev) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return apply_batch_impl<double, E>(tab, active, count, nrhs, s, ev);
+        NTD_BATCH_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pack_rhs_batch_f64(const XferArgs<double> *tab, const int *active, int count,
+                                     int gx, int epl, hipStream_t s) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return pack_rhs_batch_impl<double, E>(tab, active, count, gx, s);
+        NTD_BATCH_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_unpack_batch_f64(const XferArgs<double> *tab, const int *active, int count,
+                                   int gx, int epl, hipStream_t s) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return unpack_batch_impl<double, E>(tab, active, count, gx, s);
+        NTD_BATCH_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace ntd

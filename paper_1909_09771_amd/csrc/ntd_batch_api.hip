@@ -1,0 +1,522 @@
+// ntd_batch_api.hip -- host side of the batched solve declared in include/ntd.h:
+// the layout of a batch in the caller's workspace, its argument tables in
+// device memory, the batched apply and the batched PCG driver.
+//
+// A batch holds one lean handle per system (bands, factors and line records,
+// all packed with the batch's elements per lane) and, per entry (system s,
+// right-hand side q), the PCG vectors, the packed right-hand side and result,
+// the plane scratch of the upper sweep, the reduction partials and the scalars.
+// Three tables in device memory describe the entries to the batched kernels:
+// the sweep arguments, the pack/unpack arguments of the PCG, and the CG
+// vectors.  The caller's vectors enter through a fourth table (batched apply)
+// or through the CG table (PCG), uploaded at each call.
+//
+// The PCG loop runs kIterChunk iterations between host checks.  Each entry
+// stops on its own (its active flag); the host only reads the flags after a
+// chunk, and when every entry has stopped it confirms the true residuals and
+// resumes the entries that do not meet the tolerance.  With NTD_BATCH_GRAPH the
+// chunk is captured once per batch as a HIP graph on a private stream (the
+// kernels read every call-dependent value from device memory, so the same graph
+// serves every call) and replayed; without it the same launches are issued one
+// by one.  The graph holds kernel launches only.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "ntd.h"
+#include "ntd_handle.h"
+
+namespace {
+
+constexpr int kIterChunk = 8;
+constexpr int kMaxGx = 512;
+
+using ntd_host::Carver;
+
+}  // namespace
+
+struct ntd_batch {
+    int count = 0, nrhs = 0, prec = 0, epl = 0, gx = 0, D = 0;
+    size_t used = 0;
+    std::vector<ntd_handle *> sys;
+    // device tables
+    void *tabA = nullptr;       // ApplyArgs<T>[D]
+    void *tabXp = nullptr;      // XferArgs<T>[D]: r -> rp, Z -> z with r.z partials
+    void *tabXu = nullptr;      // XferArgs<T>[D]: the caller's r and z (batched apply)
+    ntd::BatchVec *tabV = nullptr;
+    ntd::BatchCtl *ctl = nullptr;
+    int *active = nullptr;
+    // host mirrors of the tables written per call
+    std::vector<ntd::BatchVec> hV;
+    std::vector<char> hXu;
+    std::vector<int> hact;
+    std::vector<ntd::BatchCtl> hctl;
+    std::vector<const double *> last_r;
+    std::vector<double *> last_z;
+    // captured chunk of PCG iterations
+    hipStream_t gs = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+namespace {
+
+#define CK(expr)                                   \
+    do {                                           \
+        if ((expr) != hipSuccess) return NTD_EHIP; \
+    } while (0)
+
+inline hipStream_t S(void *s) { return (hipStream_t)s; }
+
+int batch_epl(int count, const int *dims) {
+    int epl = 0;
+    for (int s = 0; s < count; ++s) {
+        const int e = ntd::epl_for(dims[3 * s]);
+        if (e > epl) epl = e;
+    }
+    return epl;
+}
+
+long long points(const int *dims, int s) {
+    return (long long)dims[3 * s] * dims[3 * s + 1] * dims[3 * s + 2];
+}
+
+int gx_for(int count, const int *dims) {
+    long long nmax = 1;
+    for (int s = 0; s < count; ++s)
+        if (points(dims, s) > nmax) nmax = points(dims, s);
+    long long g = (nmax + 4LL * ntd::kBlock - 1) / (4LL * ntd::kBlock);
+    if (g < 1) g = 1;
+    if (g > kMaxGx) g = kMaxGx;
+    return (int)g;
+}
+
+bool args_ok(int count, const int *dims, int nrhs, int prec) {
+    if (count < 1 || count > NTD_BATCH_MAX_SYSTEMS || !dims) return false;
+    if (nrhs < 1 || nrhs > NTD_BATCH_MAX_RHS) return false;
+    if (prec != NTD_PREC_FP64 && prec != NTD_PREC_MIXED) return false;
+    for (int s = 0; s < count; ++s) {
+        const int nx = dims[3 * s], ny = dims[3 * s + 1], nz = dims[3 * s + 2];
+        if (nx < 1 || ny < 1 || nz < 1 || nx > NTD_BATCH_MAX_NX) return false;
+    }
+    const int epl = batch_epl(count, dims);
+    for (int s = 0; s < count; ++s)
+        if (!ntd_host::grid_ok(dims[3 * s], dims[3 * s + 1], dims[3 * s + 2], epl)) return false;
+    return true;
+}
+
+// Per-entry device arrays of the batch, in carving order.
+struct EntryArrays {
+    double *r, *z, *p, *q;
+    void *rp, *pZ, *scratch;
+    double *partials;
+    ntd::Scalars *sc;
+};
+
+// Walks the batch workspace: the lean handles' regions, the entry arrays, the
+// tables.  Sizing when base is null.
+struct BatchWalk {
+    size_t off_sys[NTD_BATCH_MAX_SYSTEMS];
+    size_t sys_bytes[NTD_BATCH_MAX_SYSTEMS];
+    std::vector<EntryArrays> ent;
+    void *tabA, *tabXp, *tabXu;
+    ntd::BatchVec *tabV;
+    ntd::BatchCtl *ctl;
+    int *active;
+};
+
+size_t batch_walk(BatchWalk &w, void *ws, int count, const int *dims, int nrhs, int prec) {
+    const int epl = batch_epl(count, dims);
+    const int gx = gx_for(count, dims);
+    const size_t tsz = prec == NTD_PREC_MIXED ? sizeof(float) : sizeof(double);
+    const int D = count * nrhs;
+    Carver c(ws);
+    for (int s = 0; s < count; ++s) {
+        const size_t hb = ntd_host::handle_bytes(dims[3 * s], dims[3 * s + 1], dims[3 * s + 2],
+                                                 prec, NTD_SMOOTHER_NONE, epl, true);
+        w.off_sys[s] = c.off;
+        w.sys_bytes[s] = hb;
+        c.take<char>(hb);
+    }
+    w.ent.resize(D);
+    for (int s = 0; s < count; ++s) {
+        const long long N = points(dims, s);
+        const long long ny = dims[3 * s + 1], nz = dims[3 * s + 2];
+        const long long npack = ny * nz * 64 * epl;
+        for (int q = 0; q < nrhs; ++q) {
+            EntryArrays &e = w.ent[s * nrhs + q];
+            e.r = c.take<double>(N);
+            e.z = c.take<double>(N);
+            e.p = c.take<double>(N);
+            e.q = c.take<double>(N);
+            e.rp = (void *)c.take<char>(npack * tsz);
+            e.pZ = (void *)c.take<char>(npack * tsz);
+            e.scratch = (void *)c.take<char>(2 * ny * 64 * epl * tsz);
+            e.partials = c.take<double>(gx);
+            e.sc = c.take<ntd::Scalars>(1);
+        }
+    }
+    const size_t xsz = prec == NTD_PREC_MIXED ? sizeof(ntd::XferArgs<float>)
+                                              : sizeof(ntd::XferArgs<double>);
+    const size_t asz = prec == NTD_PREC_MIXED ? sizeof(ntd::ApplyArgs<float>)
+                                              : sizeof(ntd::ApplyArgs<double>);
+    w.tabA = (void *)c.take<char>(D * asz);
+    w.tabXp = (void *)c.take<char>(D * xsz);
+    w.tabXu = (void *)c.take<char>(D * xsz);
+    w.tabV = c.take<ntd::BatchVec>(D);
+    w.ctl = c.take<ntd::BatchCtl>(D);
+    w.active = c.take<int>(D);
+    return c.off;
+}
+
+template <typename T>
+hipError_t upload_static_tables(ntd_batch *b, const BatchWalk &w, hipStream_t s) {
+    const int D = b->D;
+    std::vector<ntd::ApplyArgs<T>> A(D);
+    std::vector<ntd::XferArgs<T>> X(D);
+    for (int e = 0; e < D; ++e) {
+        const ntd_handle *h = b->sys[e / b->nrhs];
+        const EntryArrays &E = w.ent[e];
+        A[e] = ntd_host::apply_args<T>(h);
+        A[e].rp = (const T *)E.rp;
+        A[e].Z = (T *)E.pZ;
+        A[e].scratch = (T *)E.scratch;
+        X[e] = ntd_host::xfer_args<T>(h);
+        X[e].rp = (T *)E.rp;
+        X[e].Z = (const T *)E.pZ;
+        X[e].r = E.r;
+        X[e].zout = E.z;
+        X[e].partials = E.partials;
+        ntd::BatchVec &V = b->hV[e];
+        V.nx = h->nx; V.ny = h->ny; V.nz = h->nz; V.pad = 0;
+        V.d = h->d; V.ax = h->ax; V.ay = h->ay; V.az = h->az;
+        V.b = nullptr; V.x = nullptr;
+        V.r = E.r; V.z = E.z; V.p = E.p; V.q = E.q;
+        V.partials = E.partials;
+        V.sc = E.sc;
+    }
+    hipError_t err;
+    if ((err = hipMemcpyAsync(b->tabA, A.data(), D * sizeof(A[0]), hipMemcpyHostToDevice, s)))
+        return err;
+    if ((err = hipMemcpyAsync(b->tabXp, X.data(), D * sizeof(X[0]), hipMemcpyHostToDevice, s)))
+        return err;
+    // the caller's table starts as a copy; its r, zout are set per call
+    b->hXu.assign((const char *)X.data(), (const char *)X.data() + D * sizeof(X[0]));
+    return hipStreamSynchronize(s);
+}
+
+// The caller's r[e], z[e] into the batched-apply table (uploaded only when
+// they differ from the previous call's).
+template <typename T>
+hipError_t upload_user_xfer(ntd_batch *b, const double *const *r, double *const *z, hipStream_t s) {
+    bool same = (int)b->last_r.size() == b->D;
+    for (int e = 0; same && e < b->D; ++e) same = b->last_r[e] == r[e] && b->last_z[e] == z[e];
+    if (same) return hipSuccess;
+    // the previous upload from this mirror has completed before it changes
+    hipError_t err = hipStreamSynchronize(s);
+    if (err != hipSuccess) return err;
+    ntd::XferArgs<T> *X = (ntd::XferArgs<T> *)b->hXu.data();
+    for (int e = 0; e < b->D; ++e) {
+        X[e].r = r[e];
+        X[e].zout = z[e];
+        X[e].partials = nullptr;
+    }
+    b->last_r.assign(r, r + b->D);
+    b->last_z.assign(z, z + b->D);
+    return hipMemcpyAsync(b->tabXu, b->hXu.data(), b->hXu.size(), hipMemcpyHostToDevice, s);
+}
+
+hipError_t pack_b(const ntd_batch *b, const void *tab, const int *act, hipStream_t s) {
+    if (b->prec == NTD_PREC_FP64)
+        return ntd::launch_pack_rhs_batch_f64((const ntd::XferArgs<double> *)tab, act, b->D, b->gx,
+                                              b->epl, s);
+    return ntd::launch_pack_rhs_batch_f32((const ntd::XferArgs<float> *)tab, act, b->D, b->gx,
+                                          b->epl, s);
+}
+hipError_t sweeps_b(const ntd_batch *b, const int *act, hipStream_t s, hipEvent_t *ev) {
+    if (b->prec == NTD_PREC_FP64)
+        return ntd::launch_apply_batch_f64((const ntd::ApplyArgs<double> *)b->tabA, act, b->count,
+                                           b->nrhs, b->epl, s, ev);
+    return ntd::launch_apply_batch_f32((const ntd::ApplyArgs<float> *)b->tabA, act, b->count,
+                                       b->nrhs, b->epl, s, ev);
+}
+hipError_t unpack_b(const ntd_batch *b, const void *tab, const int *act, hipStream_t s) {
+    if (b->prec == NTD_PREC_FP64)
+        return ntd::launch_unpack_batch_f64((const ntd::XferArgs<double> *)tab, act, b->D, b->gx,
+                                            b->epl, s);
+    return ntd::launch_unpack_batch_f32((const ntd::XferArgs<float> *)tab, act, b->D, b->gx,
+                                        b->epl, s);
+}
+
+int fin(ntd_batch *b, int op, double tol, int maxit, hipStream_t s) {
+    CK(ntd::launch_batch_finalize(b->tabV, b->ctl, b->active, b->D, b->gx, op, tol, maxit, s));
+    return NTD_OK;
+}
+
+// z = B^{-1} r for the active entries, with the r.z partials.
+int precond_b(ntd_batch *b, hipStream_t s) {
+    CK(pack_b(b, b->tabXp, b->active, s));
+    CK(sweeps_b(b, b->active, s, nullptr));
+    CK(unpack_b(b, b->tabXp, b->active, s));
+    return NTD_OK;
+}
+
+// One PCG iteration of every active entry.
+int iterate(ntd_batch *b, hipStream_t s) {
+    int st;
+    CK(ntd::launch_batch_spmv(b->tabV, b->active, b->D, b->gx, 0, s));
+    if ((st = fin(b, ntd::kOpAlpha, 0.0, 0, s)) != NTD_OK) return st;
+    CK(ntd::launch_batch_axpy2(b->tabV, b->active, b->D, b->gx, s));
+    if ((st = fin(b, ntd::kOpRR, 0.0, 0, s)) != NTD_OK) return st;
+    if ((st = precond_b(b, s)) != NTD_OK) return st;
+    if ((st = fin(b, ntd::kOpBeta, 0.0, 0, s)) != NTD_OK) return st;
+    CK(ntd::launch_batch_xpay(b->tabV, b->active, b->D, b->gx, false, s));
+    return NTD_OK;
+}
+
+int ensure_graph(ntd_batch *b) {
+    if (b->gexec) return NTD_OK;
+    if (!b->gs) CK(hipStreamCreateWithFlags(&b->gs, hipStreamNonBlocking));
+    if (!b->ev_in) CK(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+    if (!b->ev_out) CK(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+    CK(hipStreamBeginCapture(b->gs, hipStreamCaptureModeThreadLocal));
+    int st = NTD_OK;
+    for (int k = 0; k < kIterChunk && st == NTD_OK; ++k) st = iterate(b, b->gs);
+    hipGraph_t g = nullptr;
+    const hipError_t end = hipStreamEndCapture(b->gs, &g);
+    if (st != NTD_OK || end != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != NTD_OK ? st : NTD_EHIP;
+    }
+    const hipError_t inst = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (inst != hipSuccess) {
+        b->gexec = nullptr;
+        return NTD_EHIP;
+    }
+    return NTD_OK;
+}
+
+// kIterChunk iterations on stream s (graph replay on the private stream,
+// ordered after and before the work of s).
+int run_chunk(ntd_batch *b, bool graph, hipStream_t s) {
+    if (!graph) {
+        for (int k = 0; k < kIterChunk; ++k) {
+            const int st = iterate(b, s);
+            if (st != NTD_OK) return st;
+        }
+        return NTD_OK;
+    }
+    const int st = ensure_graph(b);
+    if (st != NTD_OK) return st;
+    CK(hipEventRecord(b->ev_in, s));
+    CK(hipStreamWaitEvent(b->gs, b->ev_in, 0));
+    CK(hipGraphLaunch(b->gexec, b->gs));
+    CK(hipEventRecord(b->ev_out, b->gs));
+    CK(hipStreamWaitEvent(s, b->ev_out, 0));
+    return NTD_OK;
+}
+
+int any_active(ntd_batch *b, hipStream_t s, bool *any) {
+    CK(hipMemcpyAsync(b->hact.data(), b->active, b->D * sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    *any = false;
+    for (int e = 0; e < b->D; ++e) *any = *any || b->hact[e] != 0;
+    return NTD_OK;
+}
+
+void release(ntd_batch *b) {
+    if (!b) return;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->gs) (void)hipStreamDestroy(b->gs);
+    for (ntd_handle *h : b->sys) ntd_destroy(h);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ntd_batch_workspace_bytes(int count, const int *dims, int nrhs, int prec) {
+    if (!args_ok(count, dims, nrhs, prec)) return 0;
+    BatchWalk *w = new (std::nothrow) BatchWalk;
+    if (!w) return 0;
+    const size_t bytes = batch_walk(*w, nullptr, count, dims, nrhs, prec);
+    delete w;
+    return bytes;
+}
+
+int ntd_batch_setup(int count, const int *dims, const double *const *kappa, const int *bc,
+                    int nrhs, int prec, int schur, void *workspace, size_t workspace_bytes,
+                    void *stream, ntd_batch **out) {
+    if (out) *out = nullptr;
+    if (!out || !kappa || !bc || !workspace) return NTD_EINVAL;
+    if (!args_ok(count, dims, nrhs, prec)) return NTD_EINVAL;
+    if (schur != NTD_SCHUR_NEWTON && schur != NTD_SCHUR_DIAG) return NTD_EINVAL;
+    if (((uintptr_t)workspace) % ntd_host::kAlign) return NTD_EINVAL;
+    for (int s = 0; s < count; ++s)
+        if (!kappa[s]) return NTD_EINVAL;
+    BatchWalk *w = new (std::nothrow) BatchWalk;
+    if (!w) return NTD_ENOMEM;
+    const size_t need = batch_walk(*w, workspace, count, dims, nrhs, prec);
+    if (workspace_bytes < need) {
+        delete w;
+        return NTD_EINVAL;
+    }
+    ntd_batch *b = new (std::nothrow) ntd_batch;
+    if (!b) {
+        delete w;
+        return NTD_ENOMEM;
+    }
+    hipStream_t s = S(stream);
+    b->count = count;
+    b->nrhs = nrhs;
+    b->prec = prec;
+    b->epl = batch_epl(count, dims);
+    b->gx = gx_for(count, dims);
+    b->D = count * nrhs;
+    b->used = need;
+    b->tabA = w->tabA;
+    b->tabXp = w->tabXp;
+    b->tabXu = w->tabXu;
+    b->tabV = w->tabV;
+    b->ctl = w->ctl;
+    b->active = w->active;
+    b->hV.resize(b->D);
+    b->hact.resize(b->D);
+    b->hctl.resize(b->D);
+    int st = NTD_OK;
+    for (int sy = 0; sy < count && st == NTD_OK; ++sy) {
+        ntd_handle *h = nullptr;
+        st = ntd_host::setup_handle(dims[3 * sy], dims[3 * sy + 1], dims[3 * sy + 2], kappa[sy],
+                                    bc + 6 * sy, nullptr, prec, schur, NTD_SMOOTHER_NONE, b->epl,
+                                    true, (char *)workspace + w->off_sys[sy], w->sys_bytes[sy], s,
+                                    &h);
+        if (st == NTD_OK) b->sys.push_back(h);
+    }
+    if (st == NTD_OK) {
+        // unused slots of the packed right-hand sides must read as 0
+        const size_t tsz = prec == NTD_PREC_MIXED ? sizeof(float) : sizeof(double);
+        for (int e = 0; e < b->D && st == NTD_OK; ++e) {
+            const ntd_handle *h = b->sys[e / nrhs];
+            if (ntd::launch_fill((double *)w->ent[e].rp, 0.0, h->npack * tsz / 8, s) != hipSuccess)
+                st = NTD_EHIP;
+        }
+    }
+    if (st == NTD_OK) {
+        const hipError_t err = prec == NTD_PREC_MIXED ? upload_static_tables<float>(b, *w, s)
+                                                      : upload_static_tables<double>(b, *w, s);
+        if (err != hipSuccess) st = NTD_EHIP;
+    }
+    delete w;
+    if (st != NTD_OK) {
+        release(b);
+        return st;
+    }
+    *out = b;
+    return NTD_OK;
+}
+
+int ntd_batch_apply(ntd_batch *b, const double *const *r, double *const *z, void *stream) {
+    if (!b || !r || !z) return NTD_EINVAL;
+    for (int e = 0; e < b->D; ++e)
+        if (!r[e] || !z[e] || r[e] == z[e]) return NTD_EINVAL;
+    hipStream_t s = S(stream);
+    CK(b->prec == NTD_PREC_MIXED ? upload_user_xfer<float>(b, r, z, s)
+                                 : upload_user_xfer<double>(b, r, z, s));
+    CK(pack_b(b, b->tabXu, nullptr, s));
+    CK(sweeps_b(b, nullptr, s, nullptr));
+    CK(unpack_b(b, b->tabXu, nullptr, s));
+    return NTD_OK;
+}
+
+int ntd_batch_apply_profile(ntd_batch *b, const double *const *r, double *const *z, float *ms,
+                            void *stream) {
+    if (!b || !r || !z || !ms) return NTD_EINVAL;
+    for (int e = 0; e < b->D; ++e)
+        if (!r[e] || !z[e] || r[e] == z[e]) return NTD_EINVAL;
+    hipStream_t s = S(stream);
+    CK(b->prec == NTD_PREC_MIXED ? upload_user_xfer<float>(b, r, z, s)
+                                 : upload_user_xfer<double>(b, r, z, s));
+    hipEvent_t ev[6];
+    int made = 0, st = NTD_OK;
+    for (; made < 6; ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess) { st = NTD_EHIP; break; }
+    if (st == NTD_OK) {
+        if (hipEventRecord(ev[0], s) != hipSuccess || pack_b(b, b->tabXu, nullptr, s) != hipSuccess ||
+            sweeps_b(b, nullptr, s, ev + 1) != hipSuccess ||
+            unpack_b(b, b->tabXu, nullptr, s) != hipSuccess || hipEventRecord(ev[5], s) != hipSuccess ||
+            hipEventSynchronize(ev[5]) != hipSuccess)
+            st = NTD_EHIP;
+    }
+    float pre = 0.0f, post = 0.0f;
+    for (int i = 0; st == NTD_OK && i < 3; ++i)
+        if (hipEventElapsedTime(&ms[i], ev[i + 1], ev[i + 2]) != hipSuccess) st = NTD_EHIP;
+    if (st == NTD_OK && (hipEventElapsedTime(&pre, ev[0], ev[1]) != hipSuccess ||
+                         hipEventElapsedTime(&post, ev[4], ev[5]) != hipSuccess))
+        st = NTD_EHIP;
+    if (st == NTD_OK) ms[3] = pre + post;
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    return st;
+}
+
+int ntd_batch_pcg_solve(ntd_batch *b, const double *const *rhs, double *const *x, double tol,
+                        int maxit, int flags, int *iters, double *relres, int *status,
+                        void *stream) {
+    if (!b || !rhs || !x || !iters || !relres || !status) return NTD_EINVAL;
+    if (!(tol > 0.0) || maxit < 1 || (flags & ~NTD_BATCH_GRAPH)) return NTD_EINVAL;
+    for (int e = 0; e < b->D; ++e)
+        if (!rhs[e] || !x[e] || rhs[e] == x[e]) return NTD_EINVAL;
+    hipStream_t s = S(stream);
+    const bool graph = (flags & NTD_BATCH_GRAPH) != 0;
+    for (int e = 0; e < b->D; ++e) {
+        b->hV[e].b = rhs[e];
+        b->hV[e].x = x[e];
+    }
+    CK(hipMemcpyAsync(b->tabV, b->hV.data(), b->D * sizeof(ntd::BatchVec), hipMemcpyHostToDevice,
+                      s));
+    int st;
+    CK(ntd::launch_batch_init(b->tabV, b->D, b->gx, s));
+    if ((st = fin(b, ntd::kBOpInit, tol, maxit, s)) != NTD_OK) return st;
+    if ((st = precond_b(b, s)) != NTD_OK) return st;
+    if ((st = fin(b, ntd::kOpRhoInit, 0.0, 0, s)) != NTD_OK) return st;
+    CK(ntd::launch_batch_xpay(b->tabV, b->active, b->D, b->gx, true, s));
+    // every pass advances some entry by at least one iteration, and no entry
+    // passes maxit, so the loop ends; the bound guards against a logic error
+    const long long max_pass = (long long)b->D * maxit + 2;
+    bool any = true;
+    for (long long pass = 0; pass < max_pass; ++pass) {
+        if ((st = any_active(b, s, &any)) != NTD_OK) return st;
+        if (!any) {
+            CK(ntd::launch_batch_spmv(b->tabV, nullptr, b->D, b->gx, 1, s));
+            if ((st = fin(b, ntd::kBOpTrue, 0.0, 0, s)) != NTD_OK) return st;
+            if ((st = any_active(b, s, &any)) != NTD_OK) return st;
+            if (!any) break;
+        }
+        if ((st = run_chunk(b, graph, s)) != NTD_OK) return st;
+    }
+    if (any) return NTD_EHIP;
+    CK(hipMemcpyAsync(b->hctl.data(), b->ctl, b->D * sizeof(ntd::BatchCtl),
+                      hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    for (int e = 0; e < b->D; ++e) {
+        iters[e] = b->hctl[e].iters;
+        relres[e] = b->hctl[e].relres;
+        status[e] = b->hctl[e].status;
+    }
+    return NTD_OK;
+}
+
+size_t ntd_batch_footprint_bytes(const ntd_batch *b) { return b ? b->used : 0; }
+
+int ntd_batch_destroy(ntd_batch *b) {
+    release(b);
+    return NTD_OK;
+}
+
+}  // extern "C"

@@ -126,6 +126,34 @@ struct SetupArgs {
     int *flag;
 };
 
+// One right-hand side of a batched PCG: the bands of its system and its
+// vectors (device memory; one table entry per system and right-hand side).
+struct BatchVec {
+    int nx, ny, nz, pad;
+    const double *d, *ax, *ay, *az;  // bands of the system
+    const double *b;                 // right-hand side (caller's)
+    double *x;                       // solution (caller's)
+    double *r, *z, *p, *q;           // PCG vectors
+    double *partials;                // per-block partials (gx per entry)
+    Scalars *sc;
+};
+
+// Per right-hand side control state of a batched PCG.
+struct BatchCtl {
+    double bn;      // ||b||
+    double relres;  // recursive relative residual, then the true one at exit
+    double tol;
+    int maxit;
+    int iters;
+    int status;     // NTD_OK, NTD_EBREAKDOWN or NTD_ENOCONV
+    int pad;
+};
+
+enum BatchOp : int {
+    kBOpInit = 16,  // bn = sqrt(sum); reset the scalars; active = bn > 0
+    kBOpTrue = 17,  // true relative residual; reactivate if above tol with iterations left
+};
+
 // Host-side launchers (defined in the .hip files).
 int epl_for(int nx);  // elements per lane of a half-wave chain, 0 if unsupported
 hipError_t launch_apply_f64(const ApplyArgs<double> &a, int epl, hipStream_t s, hipEvent_t *ev);
@@ -138,6 +166,38 @@ hipError_t launch_unpack_f32(const XferArgs<float> &x, int epl, hipStream_t s, i
 hipError_t launch_setup(const SetupArgs &a, int epl, hipStream_t s);
 hipError_t launch_pack_f64(const PackArgs &p, int epl, hipStream_t s);
 hipError_t launch_pack_f32(const PackArgs &p, int epl, hipStream_t s);
+
+// Batched launches over the table entries e = s*nrhs + q of count systems
+// with nrhs right-hand sides each (the moves: `count` = all entries, one grid
+// row per entry); an entry whose active flag is 0 does nothing (active may be
+// null: all entries run).
+hipError_t launch_apply_batch_f32(const ApplyArgs<float> *tab, const int *active, int count,
+                                  int nrhs, int epl, hipStream_t s, hipEvent_t *ev);
+hipError_t launch_apply_batch_f64(const ApplyArgs<double> *tab, const int *active, int count,
+                                  int nrhs, int epl, hipStream_t s, hipEvent_t *ev);
+hipError_t launch_pack_rhs_batch_f32(const XferArgs<float> *tab, const int *active, int count,
+                                     int gx, int epl, hipStream_t s);
+hipError_t launch_pack_rhs_batch_f64(const XferArgs<double> *tab, const int *active, int count,
+                                     int gx, int epl, hipStream_t s);
+hipError_t launch_unpack_batch_f32(const XferArgs<float> *tab, const int *active, int count,
+                                   int gx, int epl, hipStream_t s);
+hipError_t launch_unpack_batch_f64(const XferArgs<double> *tab, const int *active, int count,
+                                   int gx, int epl, hipStream_t s);
+// x = 0, r = b, partials of b.b
+hipError_t launch_batch_init(const BatchVec *tab, int count, int gx, hipStream_t s);
+// which = 0: q = A p with partials of p.q; which = 1: q = b - A x with partials of q.q
+hipError_t launch_batch_spmv(const BatchVec *tab, const int *active, int count, int gx, int which,
+                             hipStream_t s);
+hipError_t launch_batch_axpy2(const BatchVec *tab, const int *active, int count, int gx,
+                              hipStream_t s);
+// p = z + beta p (or p = z when copy is set)
+hipError_t launch_batch_xpay(const BatchVec *tab, const int *active, int count, int gx, bool copy,
+                             hipStream_t s);
+// one block per entry: sums the entry's gx partials and applies op (a
+// FinalizeOp or a BatchOp); kBOpInit (which stores tol and maxit in the
+// entry's control state) and kBOpTrue run for every entry
+hipError_t launch_batch_finalize(const BatchVec *tab, BatchCtl *ctl, int *active, int count,
+                                 int gx, int op, double tol, int maxit, hipStream_t s);
 
 IluGrid ilu_grid(int nx, int ny, int nz, int nblocks);
 hipError_t launch_ilu_factor(const IluGrid &g, const double *d, const double *ax, const double *ay,

@@ -915,5 +915,7 @@ hipError_t setup_impl(const SetupArgs &a, hipStream_t s) {
 
 // Supported elements per lane: a half chain holds up to 32*EPL positions.
 #define NTD_EPL_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(10) X(12) X(14) X(16)
+// Elements per lane of the batched apply (lines of up to 512 points).
+#define NTD_BATCH_EPL_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
 
 }  // namespace ntd

@@ -88,3 +88,53 @@ def test_setup_rejects_small_or_misaligned_workspace(L):
                        ctypes.byref(out)) == 1
     assert L.ntd_setup(8, 8, 8, fake, bc_arr, None, 0, 5, 0, fake, need, None, ctypes.byref(out)) == 1
     assert L.ntd_setup(8, 8, 8, fake, bc_arr, None, 0, 0, 3, fake, need, None, ctypes.byref(out)) == 1
+
+
+def _dims(*sizes):
+    flat = [v for s in sizes for v in s]
+    return (ctypes.c_int * len(flat))(*flat)
+
+
+def test_batch_workspace_bytes(L):
+    f = L.ntd_batch_workspace_bytes
+    f.restype = ctypes.c_size_t
+    f.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int]
+    two = _dims((32, 32, 32), (40, 36, 20))
+    assert f(0, two, 1, 1) == 0                      # no systems
+    assert f(2, two, 0, 1) == 0                      # no right-hand side
+    assert f(2, two, 17, 1) == 0                     # beyond NTD_BATCH_MAX_RHS
+    assert f(2, two, 1, 9) == 0                      # bad precision
+    assert f(1, _dims((513, 2, 2)), 1, 1) == 0       # beyond NTD_BATCH_MAX_NX
+    assert f(1, _dims((0, 2, 2)), 1, 1) == 0
+    one, four = f(2, two, 1, 1), f(2, two, 4, 1)
+    n = 32 ** 3 + 40 * 36 * 20
+    assert one > 0 and four >= one + 3 * 4 * 8 * n   # r, z, p, q per extra right-hand side
+    assert f(2, two, 1, 0) > one                     # FP64 records and packed vectors
+
+
+def test_batch_setup_rejects_invalid_arguments_without_gpu(L):
+    P = ctypes.c_void_p
+    s = L.ntd_batch_setup
+    s.restype = ctypes.c_int
+    s.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(P),
+                  ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int, ctypes.c_int, P,
+                  ctypes.c_size_t, P, ctypes.POINTER(P)]
+    L.ntd_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.ntd_batch_workspace_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                            ctypes.c_int, ctypes.c_int]
+    dims = _dims((8, 8, 8), (12, 6, 4))
+    need = L.ntd_batch_workspace_bytes(2, dims, 2, 1)
+    kap = (P * 2)(4096, 8192)  # never dereferenced: validation fails first
+    bc = (ctypes.c_int * 12)(*([0] * 12))
+    ws = P(1 << 20)
+    out = P(123)
+    assert s(2, dims, kap, bc, 2, 1, 0, ws, need - 1, None, ctypes.byref(out)) == 1
+    assert out.value is None
+    assert s(2, dims, kap, bc, 2, 1, 0, P((1 << 20) + 8), need, None, ctypes.byref(out)) == 1
+    assert s(2, dims, kap, bc, 2, 1, 7, ws, need, None, ctypes.byref(out)) == 1       # schur
+    assert s(2, dims, (P * 2)(4096, None), bc, 2, 1, 0, ws, need, None, ctypes.byref(out)) == 1
+    assert s(2, dims, kap, bc, 0, 1, 0, ws, need, None, ctypes.byref(out)) == 1       # nrhs
+    for name in ("ntd_batch_apply", "ntd_batch_pcg_solve", "ntd_batch_apply_profile"):
+        getattr(L, name).restype = ctypes.c_int
+    L.ntd_batch_apply.argtypes = [P, P, P, P]
+    assert L.ntd_batch_apply(None, None, None, None) == 1

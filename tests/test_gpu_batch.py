@@ -1,0 +1,164 @@
+"""Parity of the batched solve (many systems, several right-hand sides each)
+with the FP64 oracle, entry by entry, through the C ABI.
+
+The batch packs every system with the elements per lane of its longest line,
+so the shorter systems below run with pass-through slots; their results are
+held to the same bars as the single-system path: apply 1e-9 (FP64, the GPU's
+own factors) and 1e-5 (MIXED) relative; PCG iterations within +-1 of the oracle
+in FP64, true relative residual <= tol.  Graph replay and eager launches must
+give bitwise identical results.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def G(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def C(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel2(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+# (nz, ny, nx), kind; nx 33 needs 1 element per lane, 70 needs 2: the first
+# and third systems run padded to 2
+SYSTEMS = [((12, 10, 33), "layers", 1), ((9, 7, 70), "rand", 2), ((5, 16, 20), "layers", 3)]
+
+
+def build(kind, shape, seed):
+    nz, ny, nx = shape
+    if kind == "layers":
+        return W.kappa_layers(nx, ny, nz, 4100 + seed), W.BC_ALL_DIRICHLET.copy()
+    rng = np.random.default_rng(seed)
+    return 10.0 ** rng.uniform(-2, 2, size=shape), np.array([0, 1, 1, 0, 1, 1], dtype=np.int32)
+
+
+@pytest.fixture(scope="module")
+def systems():
+    out = []
+    for shape, kind, seed in SYSTEMS:
+        kappa, bc = build(kind, shape, seed)
+        out.append(dict(shape=shape, kappa=kappa, bc=bc, bands=O.assemble(kappa, bc)))
+    return out
+
+
+def make_batch(systems, nrhs, prec, schur):
+    import paper_1909_09771_amd as P
+    return P.Batch([G(s["kappa"]) for s in systems], [s["bc"] for s in systems], nrhs=nrhs,
+                   prec=prec, schur=schur)
+
+
+def rhs_list(systems, nrhs, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.uniform(-1.0, 1.0, s["shape"]) for s in systems for _ in range(nrhs)]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("mixed", 1e-5)])
+@pytest.mark.parametrize("schur", ["diag", "newton"])
+def test_batch_apply_parity(systems, prec, tol, schur):
+    nrhs = 3
+    B = make_batch(systems, nrhs, prec, schur)
+    rs = rhs_list(systems, nrhs, 41)
+    zs = [C(z) for z in B.apply([G(r) for r in rs])]
+    for e, (r, z) in enumerate(zip(rs, zs)):
+        s = systems[e // nrhs]
+        want = O.apply(O.setup(s["bands"], mode=schur), r)
+        assert rel2(z, want) <= tol, "entry %d" % e
+    B.close()
+
+
+def test_batch_apply_matches_single_system_bitwise(systems):
+    """The unpadded system (its own elements per lane equal the batch's) gives
+    the single-system apply's output bit for bit."""
+    import paper_1909_09771_amd as P
+    nrhs = 2
+    B = make_batch(systems, nrhs, "mixed", "diag")
+    rs = rhs_list(systems, nrhs, 43)
+    zs = B.apply([G(r) for r in rs])
+    s = systems[1]
+    S = P.Solver(G(s["kappa"]), s["bc"], prec="mixed", schur="diag")
+    for q in range(nrhs):
+        e = 1 * nrhs + q
+        assert np.array_equal(C(zs[e]), C(S.apply(G(rs[e]))))
+    B.close()
+    S.close()
+
+
+def test_batch_apply_profile_matches_apply(systems):
+    B = make_batch(systems, 2, "mixed", "diag")
+    rs = [G(r) for r in rhs_list(systems, 2, 47)]
+    z1 = [C(z) for z in B.apply(rs)]
+    zs = B.empty_like_entries()
+    ms = B.apply_profile(rs, zs)
+    assert len(ms) == 4 and min(ms) >= 0.0 and ms[0] > 0.0
+    for a, b in zip(z1, zs):
+        assert np.array_equal(a, C(b))
+    B.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_pcg_parity(systems, prec):
+    nrhs = 2
+    tol = 1e-8
+    B = make_batch(systems, nrhs, prec, "diag")
+    bs = rhs_list(systems, nrhs, 53)
+    xs, its, rrs, sts = B.pcg([G(b) for b in bs], tol=tol, maxit=500)
+    for e, b in enumerate(bs):
+        s = systems[e // nrhs]
+        xo, ito, rro, sto = O.pcg(s["bands"], O.setup(s["bands"], mode="diag"), b, tol, 500)[:4]
+        print("batch PCG %s entry %d: %d iterations, oracle %d" % (prec, e, its[e], ito))
+        assert sts[e] == 0 and sto == 0 and rrs[e] <= tol
+        assert abs(its[e] - ito) <= (1 if prec == "fp64" else ito // 4 + 3)
+        res = b - O.spmv(s["bands"], C(xs[e]))
+        assert np.linalg.norm(res) <= 1.01 * tol * np.linalg.norm(b)
+    B.close()
+
+
+def test_batch_pcg_graph_equals_eager(systems):
+    """Replays of the captured chunk of iterations (with host checks and eager
+    true-residual launches between them) reproduce the eager launches bit for
+    bit, on a first and a repeated call."""
+    nrhs = 2
+    B = make_batch(systems, nrhs, "mixed", "newton")
+    bs = [G(b) for b in rhs_list(systems, nrhs, 59)]
+    xe, ie, re, se = B.pcg(bs, tol=1e-9, maxit=400, graph=False)
+    xe = [C(x) for x in xe]
+    for _ in range(2):
+        xg, ig, rg, sg = B.pcg(bs, tol=1e-9, maxit=400, graph=True)
+        assert ig == ie and se == sg and rg == re
+        for a, b in zip(xe, xg):
+            assert np.array_equal(a, C(b))
+    B.close()
+
+
+def test_batch_pcg_edge_cases(systems):
+    """A zero right-hand side stops at once with x = 0; an entry out of
+    iterations reports NTD_ENOCONV with iters = maxit, without holding back
+    the others."""
+    nrhs = 2
+    B = make_batch(systems, nrhs, "fp64", "diag")
+    bs = rhs_list(systems, nrhs, 61)
+    bs[0] = np.zeros_like(bs[0])
+    xs, its, rrs, sts = B.pcg([G(b) for b in bs], tol=1e-8, maxit=500)
+    assert its[0] == 0 and sts[0] == 0 and rrs[0] == 0.0
+    assert not np.any(C(xs[0]))
+    assert all(st == 0 for st in sts)
+    xs2, its2, rrs2, sts2 = B.pcg([G(b) for b in bs], tol=1e-14, maxit=3)
+    for e in range(1, len(bs)):
+        assert sts2[e] == 5 and its2[e] == 3  # NTD_ENOCONV
+    B.close()

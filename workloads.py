@@ -162,6 +162,24 @@ def workload(name: str) -> dict:
     raise KeyError(name)
 
 
+def batch_systems(count: int = 64, nrhs: int = 4, n_lo: int = 32, n_hi: int = 96,
+                  seed: int = 401, n_fixed: int | None = None) -> list:
+    """A batch of independent cubic systems: side n_s ~ U{n_lo..n_hi} from
+    PCG64(seed) (or n_fixed for every system), kappa constant on 8 z-slabs,
+    10**U(-4, 4) from PCG64(4100 + s), Dirichlet on every face, and nrhs
+    right-hand sides b ~ U[-1, 1] from PCG64(4200 + 4 s + r).  Returns one
+    dict(n, kappa, bc, bs) per system."""
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(n_lo, n_hi + 1, size=count)
+    out = []
+    for s in range(count):
+        n = int(n_fixed) if n_fixed is not None else int(sides[s])
+        out.append(dict(n=(n, n, n), kappa=kappa_layers(n, n, n, 4100 + s),
+                        bc=BC_ALL_DIRICHLET.copy(),
+                        bs=[rhs_uniform(n, n, n, 4200 + 4 * s + r) for r in range(nrhs)]))
+    return out
+
+
 def scaled_workload(name: str, n: int) -> dict:
     """The generator of a named workload at another cubic size n (same seeds)."""
     name = name.lower()
