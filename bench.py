@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 
 METRIC = "PCG time-to-1e-8 & precond-apply GB/s, 256³ jump κ: mixed/learned vs FP64"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_traffic_jump256.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_traffic.json")
 # Sources of the sweep kernels; the recorded byte counts hold only for them.
 SWEEP_SRCS = [os.path.join(ROOT, "paper_1909_09771_amd", "csrc", f)
               for f in ("ntd_sweep.h", "ntd_apply.h", "ntd_internal.h", "ntd_apply_f32.hip",
@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--batch-schur", default="diag", choices=["diag", "newton"])
     ap.add_argument("--batch-seq", action="store_true",
                     help="also solve the systems one at a time (one right-hand side each)")
+    ap.add_argument("--batch-apply-only", action="store_true",
+                    help="time the batched apply only (no PCG)")
     return ap.parse_args()
 
 
@@ -109,15 +111,16 @@ def sweep_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str, prec: str, smoother: str, n: int):
+def traffic_for(kernel: str, prec: str, smoother: str, size):
     """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by
-    the copy-kernel calibration) if recorded for the current kernel source."""
+    the copy-kernel calibration) if recorded for the current kernel source.
+    size: the cube side, or "<side>x<systems>x<rhs>" for a batch."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    key = "%s/%s/%s/%d" % (kernel, prec, smoother, n)
+    key = "%s/%s/%s/%s" % (kernel, prec, smoother, size)
     ent = rec.get("kernels", {}).get(key)
     if not ent or rec.get("sweep_sha") != sweep_hash():
         return None
@@ -241,13 +244,17 @@ def batch_suite(args):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         log("batch of %d systems x %d rhs: setup %.3f s" % (count, nrhs, t1 - t0))
-        B.pcg(bs, tol=args.tol, maxit=args.maxit, graph=True)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        xs, its, rrs, sts = B.pcg(bs, tol=args.tol, maxit=args.maxit, graph=True)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        log("batched PCG: %.3f s, iterations %d..%d" % (t3 - t2, min(its), max(its)))
+        if args.batch_apply_only:
+            t2 = t3 = t1
+            xs, its, rrs, sts = [], [0], [0.0], [0]
+        else:
+            B.pcg(bs, tol=args.tol, maxit=args.maxit, graph=True)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            xs, its, rrs, sts = B.pcg(bs, tol=args.tol, maxit=args.maxit, graph=True)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            log("batched PCG: %.3f s, iterations %d..%d" % (t3 - t2, min(its), max(its)))
         zs = B.empty_like_entries()
         B.apply_profile(bs, zs)
         prof = [B.apply_profile(bs, zs) for _ in range(5)]
@@ -255,7 +262,8 @@ def batch_suite(args):
         units = sum(n ** 3 - n ** 2 for n in sides)
         by = sum((n ** 3 - n ** 2) * (4 * e + 2 * e * nrhs) for n in sides)
         achieved = by / (lower_ms * 1e-3) / 1e9
-        line = {"suite": "batch", "systems": count, "nrhs": nrhs, "entries": count * nrhs,
+        line = {"suite": "batch" + ("-apply" if args.batch_apply_only else ""),
+                "systems": count, "nrhs": nrhs, "entries": count * nrhs,
                 "sides": [min(sides), max(sides)], "unknowns": sum(n ** 3 for n in sides),
                 "prec": prec, "schur": schur, "tol": args.tol,
                 "setup_s": round(t1 - t0, 4), "solve_s": round(t3 - t2, 4),
@@ -268,6 +276,9 @@ def batch_suite(args):
                 "roofline": {"kernel": "k_apply_lower_b", "bound": "hbm",
                              "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                             "traffic": traffic_for("k_apply_lower_b", prec, "none",
+                                                    "%sx%dx%d" % (args.batch_n, count, nrhs))
+                             if args.batch_n else None,
                              "unknowns_per_launch": units,
                              "bytes_per_unknown": "4e + 2e x nrhs, e = %d" % e},
                 "footprint_bytes": B.footprint_bytes}

@@ -539,9 +539,14 @@ __device__ void plane_solve(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty *
         if (nl <= 0) return;
         const int last = nl - 1;
         auto cl = [last](int q) { return q < last ? q : last; };
+        // The batches of the first steps are issued in step order: interleaved
+        // by the scheduler, the wait counts at the loop header (merged with the
+        // back edge) would assume the older batch was issued last.
         if (!pre) load(0, A);
         if constexpr (DEPTH == 2) {
+            __builtin_amdgcn_sched_barrier(0);
             load(cl(1), B);
+            __builtin_amdgcn_sched_barrier(0);
             int i = 0;
             for (; i + 2 < count; i += 3) {
                 load(cl(i + 2), C);
@@ -562,6 +567,7 @@ __device__ void plane_solve(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty *
                 else if (rest == 2) A = C;
             }
         } else {
+            __builtin_amdgcn_sched_barrier(0);
             int i = 0;
             for (; i + 1 < count; i += 2) {
                 load(cl(i + 1), B);
