@@ -731,18 +731,22 @@ __device__ void line_setup(const SetupArgs &a, long long pk, int m, int nnb, int
     wave_sync();
     const int j = G.ca - 1;
     if (G.hl == 0) {
+        // the previous pivot stays in a register: the chain's critical path is
+        // the division alone, not an LDS store and reload per element
         const int len = G.half ? G.cb : j;
-        for (int q = 0; q < len; ++q) {
-            const int i = G.half ? nx - 1 - q : q;
-            double Mi;
-            if (q == 0) {
-                Mi = sd[i];
-            } else {
-                const int ip = G.half ? i + 1 : i - 1;
+        if (len > 0) {
+            const int di = G.half ? -1 : 1;
+            int i = G.half ? nx - 1 : 0;
+            double Mp = sd[i];
+            sM[i] = Mp;
+#pragma unroll 4
+            for (int q = 1; q < len; ++q) {
+                i += di;
                 const double ec = G.half ? se[i] : se[i - 1];
-                Mi = sd[i] - ec * ec / sM[ip];
+                const double Mi = sd[i] - ec * ec / Mp;
+                sM[i] = Mi;
+                Mp = Mi;
             }
-            sM[i] = Mi;
         }
     }
     wave_sync();
