@@ -210,11 +210,10 @@ size_t handle_bytes(int nx, int ny, int nz, int prec, int smoother, int epl, boo
     return layout(&tmp, nullptr, nx, ny, nz, prec, smoother, epl, lean);
 }
 
-int setup_handle(int nx, int ny, int nz, const double *kappa, const int *bc, const double *t,
-                 int prec, int schur, int smoother, int epl, bool lean, void *workspace,
-                 size_t workspace_bytes, hipStream_t s, ntd_handle **out) {
-    if (out) *out = nullptr;
-    if (!out || !kappa || !bc || !workspace) return NTD_EINVAL;
+int handle_create(int nx, int ny, int nz, const int *bc, int prec, int schur, int smoother,
+                  int epl, bool lean, void *workspace, size_t workspace_bytes, ntd_handle **out) {
+    *out = nullptr;
+    if (!bc || !workspace) return NTD_EINVAL;
     if (!grid_ok(nx, ny, nz, epl)) return NTD_EINVAL;
     if (prec != NTD_PREC_FP64 && prec != NTD_PREC_MIXED) return NTD_EINVAL;
     if (schur != NTD_SCHUR_NEWTON && schur != NTD_SCHUR_DIAG) return NTD_EINVAL;
@@ -227,7 +226,6 @@ int setup_handle(int nx, int ny, int nz, const double *kappa, const int *bc, con
     if (ndir == 0) return NTD_EINVAL;  // pure Neumann: A is singular
     if (((uintptr_t)workspace) % kAlign) return NTD_EINVAL;
     if (workspace_bytes < handle_bytes(nx, ny, nz, prec, smoother, epl, lean)) return NTD_EINVAL;
-
     ntd_handle *h = (ntd_handle *)calloc(1, sizeof(ntd_handle));
     if (!h) return NTD_ENOMEM;
     h->nx = nx; h->ny = ny; h->nz = nz; h->prec = prec; h->schur = schur;
@@ -238,35 +236,71 @@ int setup_handle(int nx, int ny, int nz, const double *kappa, const int *bc, con
     h->npack = (long long)ny * nz * 64 * h->epl;
     h->used = layout(h, workspace, nx, ny, nz, prec, smoother, epl, lean);
     h->ilu = ntd::ilu_grid(nx, ny, nz, 2);
-    int st = NTD_OK;
-    int hflag = 0;
-    ntd::Grid g = grid_of(h);
+    *out = h;
+    return NTD_OK;
+}
+
+int handle_check(ntd_handle *h, const double *kappa, const double *t, hipStream_t s) {
+    CK(hipMemsetAsync(h->flag, 0, 4 * sizeof(int), s));
+    CK(hipMemsetAsync(h->sc, 0, sizeof(Scalars), s));
+    CK(ntd::launch_check_positive(kappa, t, h->N, h->flag, s));
+    return NTD_OK;
+}
+
+int handle_flag_async(const ntd_handle *h, int *flag, hipStream_t s) {
+    CK(hipMemcpyAsync(flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    return NTD_OK;
+}
+
+int handle_assemble(ntd_handle *h, const double *kappa, const int *bc, hipStream_t s) {
+    CK(ntd::launch_assemble(grid_of(h), kappa, bc, h->d, h->ax, h->ay, h->az, s));
+    return NTD_OK;
+}
+
+ntd::SetupArgs handle_setup_args(const ntd_handle *h, const double *t) {
     ntd::SetupArgs a;
-#define FAIL(code) do { st = (code); goto fail; } while (0)
-#define HK(expr) do { if ((expr) != hipSuccess) FAIL(NTD_EHIP); } while (0)
-    HK(hipMemsetAsync(h->flag, 0, 4 * sizeof(int), s));
-    HK(hipMemsetAsync(h->sc, 0, sizeof(Scalars), s));
-    HK(ntd::launch_check_positive(kappa, t, h->N, h->flag, s));
-    HK(hipMemcpyAsync(&hflag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    HK(hipStreamSynchronize(s));
-    if (hflag & ntd::kFlagBadInput) FAIL(NTD_EINVAL);
-    HK(ntd::launch_assemble(g, kappa, bc, h->d, h->ax, h->ay, h->az, s));
-    a.nx = nx; a.ny = ny; a.nz = nz; a.schur = schur;
+    a.nx = h->nx; a.ny = h->ny; a.nz = h->nz; a.schur = h->schur;
     a.d = h->d; a.ax = h->ax; a.ay = h->ay; a.az = h->az; a.t = t;
     a.dP = h->dP; a.xP = h->xP; a.f2 = h->f2; a.dT = h->dT; a.e1 = h->e1; a.mv = h->mv;
     a.scratch = (double *)h->scratch; a.flag = h->flag;
-    HK(ntd::launch_setup(a, h->epl, s));
-    if (smoother == NTD_SMOOTHER_ILU0)
-        HK(ntd::launch_ilu_factor(h->ilu, h->d, h->ax, h->ay, h->az, h->dt, h->dtinv, h->flag, s));
-    HK(hipMemcpyAsync(&hflag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    HK(hipStreamSynchronize(s));
-    if (hflag & ntd::kFlagNotSPD) FAIL(NTD_ENOTSPD);
-    if ((st = pack_factors(h, s)) != NTD_OK) goto fail;
+    return a;
+}
+
+int handle_finish(ntd_handle *h, hipStream_t s) {
+    int st = pack_factors(h, s);
+    if (st != NTD_OK) return st;
     // unused slots of the packed right-hand side are never written by the
     // packing of a right-hand side and must read as 0
     if (h->rp)
-        HK(ntd::launch_fill((double *)h->rp, 0.0,
-                            h->npack * (h->prec == NTD_PREC_FP64 ? 8 : 4) / 8, s));
+        CK(ntd::launch_fill((double *)h->rp, 0.0,
+                             h->npack * (h->prec == NTD_PREC_FP64 ? 8 : 4) / 8, s));
+    return NTD_OK;
+}
+
+int setup_handle(int nx, int ny, int nz, const double *kappa, const int *bc, const double *t,
+                 int prec, int schur, int smoother, int epl, bool lean, void *workspace,
+                 size_t workspace_bytes, hipStream_t s, ntd_handle **out) {
+    if (out) *out = nullptr;
+    if (!out || !kappa) return NTD_EINVAL;
+    ntd_handle *h = nullptr;
+    int st = handle_create(nx, ny, nz, bc, prec, schur, smoother, epl, lean, workspace,
+                           workspace_bytes, &h);
+    if (st != NTD_OK) return st;
+    int hflag = 0;
+#define FAIL(code) do { st = (code); goto fail; } while (0)
+#define HK(expr) do { if ((expr) != hipSuccess) FAIL(NTD_EHIP); } while (0)
+    if ((st = handle_check(h, kappa, t, s)) != NTD_OK) goto fail;
+    if ((st = handle_flag_async(h, &hflag, s)) != NTD_OK) goto fail;
+    HK(hipStreamSynchronize(s));
+    if (hflag & ntd::kFlagBadInput) FAIL(NTD_EINVAL);
+    if ((st = handle_assemble(h, kappa, bc, s)) != NTD_OK) goto fail;
+    HK(ntd::launch_setup(handle_setup_args(h, t), h->epl, s));
+    if (smoother == NTD_SMOOTHER_ILU0)
+        HK(ntd::launch_ilu_factor(h->ilu, h->d, h->ax, h->ay, h->az, h->dt, h->dtinv, h->flag, s));
+    if ((st = handle_flag_async(h, &hflag, s)) != NTD_OK) goto fail;
+    HK(hipStreamSynchronize(s));
+    if (hflag & ntd::kFlagNotSPD) FAIL(NTD_ENOTSPD);
+    if ((st = handle_finish(h, s)) != NTD_OK) goto fail;
     HK(hipStreamSynchronize(s));
     *out = h;
     return NTD_OK;

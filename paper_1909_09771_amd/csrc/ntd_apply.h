@@ -399,17 +399,6 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply_upper(ApplyArgs<T> a) {
 // right-hand side q of system s; entries whose active flag is 0 (when active
 // is given) do nothing.  The entry is read once per block into scalar
 // registers, so the sweeps see wave-uniform arguments as above.
-template <typename S>
-__device__ __forceinline__ S load_uniform(const S *p) {
-    static_assert(sizeof(S) % 4 == 0, "word-sized descriptor");
-    S out;
-    const unsigned *src = (const unsigned *)p;
-    unsigned *dst = (unsigned *)&out;
-#pragma unroll
-    for (unsigned i = 0; i < sizeof(S) / 4; ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
-    return out;
-}
-
 __device__ __forceinline__ bool entry_active(const int *active, int e) {
     return !active || __builtin_amdgcn_readfirstlane(active[e]) != 0;
 }

@@ -126,6 +126,7 @@ struct BatchWalk {
     ntd::BatchVec *tabV;
     ntd::BatchCtl *ctl;
     int *active;
+    ntd::SetupArgs *tabS;  // factorization arguments of the systems
 };
 
 size_t batch_walk(BatchWalk &w, void *ws, int count, const int *dims, int nrhs, int prec) {
@@ -169,6 +170,7 @@ size_t batch_walk(BatchWalk &w, void *ws, int count, const int *dims, int nrhs, 
     w.tabV = c.take<ntd::BatchVec>(D);
     w.ctl = c.take<ntd::BatchCtl>(D);
     w.active = c.take<int>(D);
+    w.tabS = c.take<ntd::SetupArgs>(count);
     return c.off;
 }
 
@@ -390,15 +392,45 @@ int ntd_batch_setup(int count, const int *dims, const double *const *kappa, cons
     b->hV.resize(b->D);
     b->hact.resize(b->D);
     b->hctl.resize(b->D);
+    // The setups of the systems, phase by phase over the whole batch: every
+    // factorization runs in one pair of launches.
     int st = NTD_OK;
     for (int sy = 0; sy < count && st == NTD_OK; ++sy) {
         ntd_handle *h = nullptr;
-        st = ntd_host::setup_handle(dims[3 * sy], dims[3 * sy + 1], dims[3 * sy + 2], kappa[sy],
-                                    bc + 6 * sy, nullptr, prec, schur, NTD_SMOOTHER_NONE, b->epl,
-                                    true, (char *)workspace + w->off_sys[sy], w->sys_bytes[sy], s,
-                                    &h);
+        st = ntd_host::handle_create(dims[3 * sy], dims[3 * sy + 1], dims[3 * sy + 2],
+                                     bc + 6 * sy, prec, schur, NTD_SMOOTHER_NONE, b->epl, true,
+                                     (char *)workspace + w->off_sys[sy], w->sys_bytes[sy], &h);
         if (st == NTD_OK) b->sys.push_back(h);
     }
+    std::vector<int> flags(count, 0);
+    auto read_flags = [&](int mask, int code) {
+        for (int sy = 0; sy < count && st == NTD_OK; ++sy)
+            st = ntd_host::handle_flag_async(b->sys[sy], &flags[sy], s);
+        if (st == NTD_OK && hipStreamSynchronize(s) != hipSuccess) st = NTD_EHIP;
+        for (int sy = 0; sy < count && st == NTD_OK; ++sy)
+            if (flags[sy] & mask) st = code;
+    };
+    for (int sy = 0; sy < count && st == NTD_OK; ++sy)
+        st = ntd_host::handle_check(b->sys[sy], kappa[sy], nullptr, s);
+    if (st == NTD_OK) read_flags(ntd::kFlagBadInput, NTD_EINVAL);
+    for (int sy = 0; sy < count && st == NTD_OK; ++sy)
+        st = ntd_host::handle_assemble(b->sys[sy], kappa[sy], bc + 6 * sy, s);
+    if (st == NTD_OK) {
+        std::vector<ntd::SetupArgs> args(count);
+        int max_nx = 1;
+        for (int sy = 0; sy < count; ++sy) {
+            args[sy] = ntd_host::handle_setup_args(b->sys[sy], nullptr);
+            if (dims[3 * sy] > max_nx) max_nx = dims[3 * sy];
+        }
+        if (hipMemcpyAsync(w->tabS, args.data(), count * sizeof(ntd::SetupArgs),
+                           hipMemcpyHostToDevice, s) != hipSuccess ||
+            ntd::launch_setup_batch(w->tabS, count, max_nx, b->epl, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = NTD_EHIP;
+    }
+    if (st == NTD_OK) read_flags(ntd::kFlagNotSPD, NTD_ENOTSPD);
+    for (int sy = 0; sy < count && st == NTD_OK; ++sy)
+        st = ntd_host::handle_finish(b->sys[sy], s);
     if (st == NTD_OK) {
         // unused slots of the packed right-hand sides must read as 0
         const size_t tsz = prec == NTD_PREC_MIXED ? sizeof(float) : sizeof(double);

@@ -51,6 +51,19 @@ struct Carver {
 size_t handle_bytes(int nx, int ny, int nz, int prec, int smoother, int epl, bool lean);
 bool grid_ok(int nx, int ny, int nz, int epl);
 
+// The phases of a setup, for callers that run them over many systems at once:
+// validation and layout (no GPU work; *out is a new handle), the check of kappa
+// and t (result in the handle's device flag), the asynchronous read of that
+// flag, the assembly of A, the factorization arguments, and the packing of the
+// factors (after the factorization).
+int handle_create(int nx, int ny, int nz, const int *bc, int prec, int schur, int smoother,
+                  int epl, bool lean, void *workspace, size_t workspace_bytes, ntd_handle **out);
+int handle_check(ntd_handle *h, const double *kappa, const double *t, hipStream_t s);
+int handle_flag_async(const ntd_handle *h, int *flag, hipStream_t s);
+int handle_assemble(ntd_handle *h, const double *kappa, const int *bc, hipStream_t s);
+ntd::SetupArgs handle_setup_args(const ntd_handle *h, const double *t);
+int handle_finish(ntd_handle *h, hipStream_t s);
+
 // Validation, assembly, factorization and packing of one system into a
 // workspace of handle_bytes(); on success *out is a new handle.
 int setup_handle(int nx, int ny, int nz, const double *kappa, const int *bc, const double *t,

@@ -164,6 +164,10 @@ hipError_t launch_pack_rhs_f32(const XferArgs<float> &x, int epl, hipStream_t s)
 hipError_t launch_unpack_f64(const XferArgs<double> &x, int epl, hipStream_t s, int *np);
 hipError_t launch_unpack_f32(const XferArgs<float> &x, int epl, hipStream_t s, int *np);
 hipError_t launch_setup(const SetupArgs &a, int epl, hipStream_t s);
+// the factorizations of `count` systems (a table of arguments in device
+// memory, all with the same elements per lane) in one pair of launches
+hipError_t launch_setup_batch(const SetupArgs *tab, int count, int max_nx, int epl,
+                              hipStream_t s);
 hipError_t launch_pack_f64(const PackArgs &p, int epl, hipStream_t s);
 hipError_t launch_pack_f32(const PackArgs &p, int epl, hipStream_t s);
 

@@ -23,4 +23,14 @@ hipError_t launch_setup(const SetupArgs &a, int epl, hipStream_t s) {
     }
 }
 
+hipError_t launch_setup_batch(const SetupArgs *tab, int count, int max_nx, int epl,
+                              hipStream_t s) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return setup_batch_impl<E>(tab, count, max_nx, s);
+        NTD_BATCH_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace ntd

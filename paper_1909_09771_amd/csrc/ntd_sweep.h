@@ -66,6 +66,19 @@ __device__ __forceinline__ void bstore(double v, rsrc_t r, unsigned vo, unsigned
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)vo, (int)so, 0);
 }
 
+// An argument struct read from device memory into scalar registers (one
+// entry of a batched launch's table; the whole wavefront reads the same one).
+template <typename S>
+__device__ __forceinline__ S load_uniform(const S *p) {
+    static_assert(sizeof(S) % 4 == 0, "word-sized descriptor");
+    S out;
+    const unsigned *src = (const unsigned *)p;
+    unsigned *dst = (unsigned *)&out;
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(S) / 4; ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return out;
+}
+
 // ---------------------------------------------------------------------------
 // Level 1: one line per wavefront.
 // ---------------------------------------------------------------------------
@@ -873,16 +886,14 @@ __device__ void plane_setup(const SetupArgs &a, int k, int nnb, int nb0, int nb1
     plane_lines_setup<EPL>(a, k, lds_lines);
 }
 
-// Setup of the two level-3 half chains (block 0: planes 0..j3-1 upward, each
-// with neighbour k-1; block 1: planes nz-1..j3+1 downward, neighbour k+1).
+// Setup of the two level-3 half chains (h = 0: planes 0..j3-1 upward, each
+// with neighbour k-1; h = 1: planes nz-1..j3+1 downward, neighbour k+1).
 template <int EPL>
-__global__ void __launch_bounds__(kSetupThreads) k_setup_halves(SetupArgs a) {
-    extern __shared__ double smem[];
+__device__ __forceinline__ void setup_halves(const SetupArgs &a, int h, double *smem) {
     double *lds_lines = smem;          // 2 waves x 5 lines
     double *lds_x = smem + 10 * a.nx;  // 2 x 64*EPL exchange lines
     const long long nxy = (long long)a.nx * a.ny;
     const int j3 = (a.nz - 1) / 2;
-    const int h = blockIdx.x;
     double *wbuf = a.scratch + (2 * h) * nxy, *zbuf = a.scratch + (2 * h + 1) * nxy;
     if (h == 0) {
         for (int k = 0; k < j3; ++k)
@@ -893,9 +904,9 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup_halves(SetupArgs a) {
     }
 }
 
+// The twist plane j3 (after both halves): both neighbours.
 template <int EPL>
-__global__ void __launch_bounds__(kSetupThreads) k_setup_twist(SetupArgs a) {
-    extern __shared__ double smem[];
+__device__ __forceinline__ void setup_twist(const SetupArgs &a, double *smem) {
     double *lds_lines = smem;
     double *lds_x = smem + 10 * a.nx;
     const long long nxy = (long long)a.nx * a.ny;
@@ -908,8 +919,39 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup_twist(SetupArgs a) {
 }
 
 template <int EPL>
+__global__ void __launch_bounds__(kSetupThreads) k_setup_halves(SetupArgs a) {
+    extern __shared__ double smem[];
+    setup_halves<EPL>(a, blockIdx.x, smem);
+}
+
+template <int EPL>
+__global__ void __launch_bounds__(kSetupThreads) k_setup_twist(SetupArgs a) {
+    extern __shared__ double smem[];
+    setup_twist<EPL>(a, smem);
+}
+
+// A batch of independent systems (blockIdx.y selects the system's arguments):
+// their level-3 chains run at the same time.
+template <int EPL>
+__global__ void __launch_bounds__(kSetupThreads) k_setup_halves_b(const SetupArgs *tab) {
+    extern __shared__ double smem[];
+    setup_halves<EPL>(load_uniform(tab + blockIdx.y), blockIdx.x, smem);
+}
+
+template <int EPL>
+__global__ void __launch_bounds__(kSetupThreads) k_setup_twist_b(const SetupArgs *tab) {
+    extern __shared__ double smem[];
+    setup_twist<EPL>(load_uniform(tab + blockIdx.y), smem);
+}
+
+template <int EPL>
+size_t setup_smem(int nx) {
+    return sizeof(double) * (10 * (size_t)nx + 2 * 64 * EPL);
+}
+
+template <int EPL>
 hipError_t setup_impl(const SetupArgs &a, hipStream_t s) {
-    size_t sh = sizeof(double) * (10 * (size_t)a.nx + 2 * 64 * EPL);
+    const size_t sh = setup_smem<EPL>(a.nx);
     if (sh > 65536) {
         (void)hipFuncSetAttribute((const void *)k_setup_halves<EPL>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
@@ -918,6 +960,20 @@ hipError_t setup_impl(const SetupArgs &a, hipStream_t s) {
     }
     hipLaunchKernelGGL((k_setup_halves<EPL>), dim3(2), dim3(kSetupThreads), sh, s, a);
     hipLaunchKernelGGL((k_setup_twist<EPL>), dim3(1), dim3(kSetupThreads), sh, s, a);
+    return hipGetLastError();
+}
+
+template <int EPL>
+hipError_t setup_batch_impl(const SetupArgs *tab, int count, int max_nx, hipStream_t s) {
+    const size_t sh = setup_smem<EPL>(max_nx);
+    if (sh > 65536) {
+        (void)hipFuncSetAttribute((const void *)k_setup_halves_b<EPL>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        (void)hipFuncSetAttribute((const void *)k_setup_twist_b<EPL>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    }
+    hipLaunchKernelGGL((k_setup_halves_b<EPL>), dim3(2, count), dim3(kSetupThreads), sh, s, tab);
+    hipLaunchKernelGGL((k_setup_twist_b<EPL>), dim3(1, count), dim3(kSetupThreads), sh, s, tab);
     return hipGetLastError();
 }
 
