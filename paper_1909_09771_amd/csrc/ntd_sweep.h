@@ -744,8 +744,9 @@ __device__ void line_setup(const SetupArgs &a, long long pk, int m, int nnb, int
     wave_sync();
     const int j = G.ca - 1;
     if (G.hl == 0) {
-        // the previous pivot stays in a register: the chain's critical path is
-        // the division alone, not an LDS store and reload per element
+        // M_i = d_i - e^2 / M_{i-1}: the previous pivot stays in a register, and
+        // 1/M_{i-1} is the hardware reciprocal refined by two Newton steps
+        // (r <- r + r(1 - M r)), a shorter dependent chain than an IEEE division
         const int len = G.half ? G.cb : j;
         if (len > 0) {
             const int di = G.half ? -1 : 1;
@@ -756,7 +757,10 @@ __device__ void line_setup(const SetupArgs &a, long long pk, int m, int nnb, int
             for (int q = 1; q < len; ++q) {
                 i += di;
                 const double ec = G.half ? se[i] : se[i - 1];
-                const double Mi = sd[i] - ec * ec / Mp;
+                double r = __builtin_amdgcn_rcp(Mp);
+                r = __builtin_fma(r, __builtin_fma(-Mp, r, 1.0), r);
+                r = __builtin_fma(r, __builtin_fma(-Mp, r, 1.0), r);
+                const double Mi = __builtin_fma(-ec * ec, r, sd[i]);
                 sM[i] = Mi;
                 Mp = Mi;
             }
