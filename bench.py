@@ -216,6 +216,27 @@ def paper_suite(args):
 P_BC_ALL = [0, 0, 0, 0, 0, 0]
 
 
+def copy_bandwidth(dev) -> float:
+    """Measured device-to-device copy bandwidth (GB/s, bytes read + written) of a
+    2 GiB copy, timed with events: the attainable HBM rate beside the published
+    8 TB/s peak."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbps = reps * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbps
+
+
 def batch_suite(args):
     """Many independent systems solved together: `count` cubes of side
     U{32..96} (or --batch-n), kappa constant on 8 z-slabs (10^U(-4,4)),
@@ -333,9 +354,14 @@ def main():
         kernels_only(args, make(args.prec), b, n)
         return
 
+    split = []  # (setup s, solve s) of each step; both calls synchronize
+
     def step(prec):
+        ta = time.perf_counter()
         S = make(prec)
+        tb = time.perf_counter()
         x, it, rr, st = S.pcg(b, tol=args.tol, maxit=args.maxit)
+        split.append((tb - ta, time.perf_counter() - tb))
         return S, x, it, rr, st
 
     for i in range(args.warmup):
@@ -354,6 +380,9 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    timed = split[-args.steps:]
+    setup_s = sum(v[0] for v in timed) / len(timed)
+    solve_s = sum(v[1] for v in timed) / len(timed)
     iters, relres, status = results[-1]
 
     # Preconditioner launches as PCG issues them, timed with HIP events on the
@@ -402,6 +431,7 @@ def main():
         del S2, x2
 
     precond_ms = sweeps_ms + rest_ms
+    copy_gbps = copy_bandwidth(dev)
     line = {
         "metric": METRIC,
         "value": round(ms_per_step / 1e3, 4),
@@ -420,6 +450,8 @@ def main():
                    "bc": "Dirichlet z=0, Neumann else", "tol": args.tol, "prec": args.prec,
                    "schur": args.schur, "smoother": args.smoother, "filter": "t=1"},
         "iters": iters,
+        "setup_s": round(setup_s, 4),
+        "solve_s": round(solve_s, 4),
         "relres": relres,
         "status": status,
         "precond_ms": round(precond_ms, 4),
@@ -428,6 +460,7 @@ def main():
         "launch_ms": {"lower": round(lower_ms, 4), "twist": round(twist_ms, 4),
                       "upper": round(upper_ms, 4), "rest": round(rest_ms, 4)},
         "spmv_ms": round(spmv_ms, 4),
+        "hbm_copy_GBps": round(copy_gbps, 1),
         "spmv_GBps": round(48 * N / (spmv_ms * 1e-3) / 1e9, 1),
         "footprint_bytes": footprint,
         "roofline": {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 2),

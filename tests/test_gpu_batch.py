@@ -162,3 +162,16 @@ def test_batch_pcg_edge_cases(systems):
     for e in range(1, len(bs)):
         assert sts2[e] == 5 and its2[e] == 3  # NTD_ENOCONV
     B.close()
+
+
+def test_batch_rejects_bad_kappa(systems):
+    """One system with a non-positive kappa fails the whole batch setup with
+    NTD_EINVAL (the input check runs over every system before any factorization)."""
+    import paper_1909_09771_amd as P
+    kappas = [G(s["kappa"]) for s in systems]
+    bad = systems[1]["kappa"].copy()
+    bad[0, 0, 0] = -1.0
+    kappas[1] = G(bad)
+    with pytest.raises(P.NTDError) as ei:
+        P.Batch(kappas, [s["bc"] for s in systems], nrhs=2, prec="mixed", schur="diag")
+    assert ei.value.status == P.EINVAL
