@@ -15,6 +15,11 @@ same solve in FP64.
 --kernels-only runs the preconditioner and the SpMV a few times plus a plain
 device copy of known size (the calibration of the HBM byte counters) and exits;
 it is the program the hardware-counter runs profile.
+
+--suite paper solves the test matrices of Sec. 3 (Types 1-3 at 100^3, 200^3,
+350^3, tolerances 1e-7 and 1e-10), one JSON line per case.  --suite batch solves
+many independent systems together (64 cubes of side 32..96, 4 right-hand sides
+each, by default) and reports the batched sweeps' throughput.
 """
 from __future__ import annotations
 
