@@ -529,6 +529,12 @@ int ntd_batch_pcg_solve(ntd_batch *b, const double *const *rhs, double *const *x
             if ((st = fin(b, ntd::kBOpTrue, 0.0, 0, s)) != NTD_OK) return st;
             if ((st = any_active(b, s, &any)) != NTD_OK) return st;
             if (!any) break;
+            // the recursive test stopped these entries right after their
+            // residual update; finish that iteration (z = B^{-1} r, beta,
+            // p = z + beta p) so that CG continues as the single-system solve does
+            if ((st = precond_b(b, s)) != NTD_OK) return st;
+            if ((st = fin(b, ntd::kOpBeta, 0.0, 0, s)) != NTD_OK) return st;
+            CK(ntd::launch_batch_xpay(b->tabV, b->active, b->D, b->gx, false, s));
         }
         if ((st = run_chunk(b, graph, s)) != NTD_OK) return st;
     }

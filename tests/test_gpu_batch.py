@@ -175,3 +175,25 @@ def test_batch_rejects_bad_kappa(systems):
     with pytest.raises(P.NTDError) as ei:
         P.Batch(kappas, [s["bc"] for s in systems], nrhs=2, prec="mixed", schur="diag")
     assert ei.value.status == P.EINVAL
+
+
+@pytest.mark.parametrize("tol", [1e-12, 1e-13, 1e-14])
+def test_batch_pcg_follows_the_single_solve_near_the_rounding_floor(systems, tol):
+    """Near the attainable accuracy the recursive residual can pass the
+    tolerance while the true one does not; the entry then continues its CG
+    iteration exactly as the single-system solve does (same iterations, same
+    status), instead of repeating its last step."""
+    import paper_1909_09771_amd as P
+    nrhs = 1
+    B = make_batch(systems, nrhs, "fp64", "diag")
+    bs = rhs_list(systems, nrhs, 67)
+    xs, its, rrs, sts = B.pcg([G(b) for b in bs], tol=tol, maxit=300)
+    for e, b in enumerate(bs):
+        s = systems[e]
+        S = P.Solver(G(s["kappa"]), s["bc"], prec="fp64", schur="diag")
+        x1, it1, rr1, st1 = S.pcg(G(b), tol=tol, maxit=300)
+        print("tol %.0e entry %d: batch %d its (status %d, relres %.2e), single %d (status %d, "
+              "relres %.2e)" % (tol, e, its[e], sts[e], rrs[e], it1, st1, rr1))
+        assert sts[e] == st1 and abs(its[e] - it1) <= 1
+        S.close()
+    B.close()
