@@ -19,7 +19,9 @@ it is the program the hardware-counter runs profile.
 --suite paper solves the test matrices of Sec. 3 (Types 1-3 at 100^3, 200^3,
 350^3, tolerances 1e-7 and 1e-10), one JSON line per case.  --suite batch solves
 many independent systems together (64 cubes of side 32..96, 4 right-hand sides
-each, by default) and reports the batched sweeps' throughput.
+each, by default) and reports the batched sweeps' throughput.  --suite learned
+trains the filter-vector network on mixture fields and compares PCG with t = 1,
+with the exact lowest-eigenvector target and with the network's t.
 """
 from __future__ import annotations
 
@@ -86,10 +88,11 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="run the preconditioner, the SpMV and a calibration copy, then exit")
     ap.add_argument("--reps", type=int, default=3, help="launches per kernel in --kernels-only")
-    ap.add_argument("--suite", default=None, choices=["paper", "batch"],
+    ap.add_argument("--suite", default=None, choices=["paper", "batch", "learned"],
                     help="paper: the test matrices of Sec. 3 (Types 1-3, 100^3/200^3/350^3, "
                          "tol 1e-7 and 1e-10), one JSON line per case; batch: many independent "
-                         "systems solved together, one JSON line per batch size")
+                         "systems solved together, one JSON line per batch size; learned: train the "
+                         "filter-vector network and compare PCG with t = 1 and with its t")
     ap.add_argument("--sizes", default="100,200,350", help="cube sides of --suite paper")
     ap.add_argument("--precs", default="mixed,fp64", help="precisions of --suite paper")
     ap.add_argument("--batch-counts", default="64", help="systems per batch (--suite batch)")
@@ -101,6 +104,12 @@ def parse():
                     help="also solve the systems one at a time (one right-hand side each)")
     ap.add_argument("--batch-apply-only", action="store_true",
                     help="time the batched apply only (no PCG)")
+    ap.add_argument("--learn-train", type=int, default=256, help="training fields (--suite learned)")
+    ap.add_argument("--learn-n", type=int, default=32, help="cube side of the training fields")
+    ap.add_argument("--learn-epochs", type=int, default=20)
+    ap.add_argument("--learn-lr", type=float, default=2e-3)
+    ap.add_argument("--learn-eval", type=int, default=8, help="held-out evaluation fields")
+    ap.add_argument("--learn-eval-n", type=int, default=128, help="cube side of the evaluation fields")
     return ap.parse_args()
 
 
@@ -328,6 +337,109 @@ def batch_suite(args):
         torch.cuda.empty_cache()
 
 
+# Multiply-adds of the filter network per voxel (2 flops each): 27 x 16 for
+# layer 1, 432 x 16 for layers 2 and 3, 432 for layer 4.
+CNN_FLOP_PER_VOXEL = 2 * (27 * 16 + 2 * 432 * 16 + 432)
+# Algorithmic HBM bytes of one prediction per voxel: kappa read twice (mean,
+# feature: 16), the feature written and read (4), three hidden maps of 16 bf16
+# written and read (192), y and t written (12).
+CNN_BYTES_PER_VOXEL = 16 + 4 + 192 + 12
+
+
+def learned_suite(args):
+    """The learned filter vector: targets (the lowest eigenvector of A by inverse
+    iteration with the library's batched FP64 PCG) on --learn-train mixture fields
+    of side --learn-n (seeds 10000+i), Adam training, then PCG to --tol with
+    t = 1, with the exact target and with the network's t on --learn-eval held-out
+    fields of side --learn-eval-n (seeds 20000+i, b ~ U[-1,1] seed 30000+i),
+    MIXED, for the Newton blocks + ILU(0) and for the diagonal blocks alone.
+    One JSON line for the training, one per evaluation configuration."""
+    import time
+    import numpy as np
+    import torch
+    import paper_1909_09771_amd as P
+    from paper_1909_09771_amd import learned as Lr
+    import workloads as W
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    bc = W.BC_ALL_DIRICHLET
+    n = args.learn_n
+    kap = [g(W.kappa_mixture(n, 10000 + i)) for i in range(args.learn_train)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tgt = []
+    for i in range(0, len(kap), 64):
+        tgt += Lr.eigen_targets(kap[i:i + 64], [bc] * len(kap[i:i + 64]))
+    torch.cuda.synchronize()
+    t_targets = time.perf_counter() - t0
+    log("targets: %d fields of %d^3 in %.2f s" % (len(kap), n, t_targets))
+    net = P.FilterNet(W.cnn_init_params(0))
+    t0 = time.perf_counter()
+    hist = Lr.train(net, kap, tgt, args.learn_epochs, args.learn_lr)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    for ep in range(0, len(hist), max(1, len(hist) // 10)):
+        log("epoch %d: loss %.4e" % (ep, hist[ep]))
+    log("training: %d steps in %.2f s, final loss %.4e" % (len(kap) * len(hist), t_train, hist[-1]))
+    net.release_workspaces()
+    del kap, tgt
+    torch.cuda.empty_cache()
+
+    ne = args.learn_eval_n
+    evk = [W.kappa_mixture(ne, 20000 + i) for i in range(args.learn_eval)]
+    # the network's forward pass at the evaluation size: event-timed median of 5
+    kd = g(evk[0])
+    tout = torch.empty_like(kd)
+    net.predict(kd, tout)
+    ms = []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        net.predict(kd, tout)
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    pred_ms = float(np.median(ms))
+    vox = ne ** 3
+    print(json.dumps({
+        "suite": "learned", "phase": "train", "train_fields": args.learn_train, "train_n": n,
+        "epochs": args.learn_epochs, "lr": args.learn_lr, "targets_s": round(t_targets, 3),
+        "train_s": round(t_train, 3), "ms_per_train_step": round(1e3 * t_train / (len(hist) * args.learn_train), 4),
+        "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+        "predict_ms": round(pred_ms, 4), "predict_n": ne,
+        "predict_TFLOPs": round(CNN_FLOP_PER_VOXEL * vox / (pred_ms * 1e-3) / 1e12, 2),
+        "predict_GBps": round(CNN_BYTES_PER_VOXEL * vox / (pred_ms * 1e-3) / 1e9, 1),
+        "peak_bf16_TFLOPs": 2500.0, "peak_hbm_GBps": 8000.0}), flush=True)
+    del kd, tout
+    evt = Lr.eigen_targets([g(k) for k in evk], [bc] * len(evk))
+    for schur, smoother in (("newton", "ilu0"), ("diag", "none")):
+        rows = []
+        for i, k in enumerate(evk):
+            kd = g(k)
+            b = g(W.rhs_uniform(ne, ne, ne, 30000 + i))
+            r = Lr.compare(net, kd, bc, b, tol=args.tol, maxit=args.maxit, prec="mixed",
+                           schur=schur, smoother=smoother)
+            r["target"] = Lr.solve_with(kd, bc, b, evt[i], args.tol, args.maxit, "mixed", schur,
+                                        smoother)
+            log("%s+%s field %d: iterations ones %d, target %d%s, learned %d%s" % (
+                schur, smoother, i, r["ones"]["iters"], r["target"]["iters"],
+                " (t=1 fallback)" if r["target"]["fallback"] else "", r["learned"]["iters"],
+                " (t=1 fallback)" if r["learned"]["fallback"] else ""))
+            rows.append(r)
+        summ = {}
+        for key in ("ones", "target", "learned"):
+            summ[key] = dict(
+                mean_iters=round(float(np.mean([r[key]["iters"] for r in rows])), 2),
+                total_s=round(float(np.sum([r[key]["seconds"] for r in rows])), 3),
+                fallbacks=int(np.sum([r[key]["fallback"] for r in rows])),
+                all_converged=bool(all(r[key]["status"] == 0 for r in rows)))
+        print(json.dumps({
+            "suite": "learned", "phase": "eval", "eval_fields": len(evk), "eval_n": ne,
+            "schur": schur, "smoother": smoother, "prec": "mixed", "tol": args.tol,
+            "iters": {k: [r[k]["iters"] for r in rows] for k in ("ones", "target", "learned")},
+            "summary": summ}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -339,6 +451,9 @@ def main():
         return
     if args.suite == "batch":
         batch_suite(args)
+        return
+    if args.suite == "learned":
+        learned_suite(args)
         return
     import torch
     import paper_1909_09771_amd as P

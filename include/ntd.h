@@ -223,6 +223,49 @@ size_t ntd_batch_footprint_bytes(const ntd_batch *b);
 /* Release the host-side state of the batch (not the caller's workspace). */
 int ntd_batch_destroy(ntd_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Learned filter vector (Sec. 1: B(t) t = A t, and a t close to A's lowest
+ * eigenvectors treats that end of the spectrum best; t = 1 is the rowsum
+ * choice).  A 3D convolutional network predicts t from kappa:
+ *   H0 = bf16((log10 kappa - mean(log10 kappa)) / 3)          1 channel
+ *   H_l = relu(conv_l(H_{l-1})), l = 1..3                      16 channels
+ *   y = conv_4(H3);  t = softplus(y) + 1e-3                    1 channel
+ * conv_l is a 3x3x3 cross-correlation with zero padding plus a bias, taken on
+ * bfloat16 operands with float32 accumulation (matrix cores).
+ *
+ * Parameters: NTD_CNN_NPARAMS floats (device), per layer W[cout][tap][cin]
+ * then b[cout], tap = 9 (dz+1) + 3 (dy+1) + (dx+1) for the neighbour
+ * (z+dz, y+dy, x+dx); layers (cin, cout) = (1,16), (16,16), (16,16), (16,1).
+ * Fields are [nz][ny][nx] as everywhere else; 1 <= nx*ny*nz <= 2^28.
+ * The workspace (device, caller-owned, 256-byte aligned) holds activations,
+ * gradient maps and packed weights: about 168 bytes per voxel + 15 MB.
+ * ------------------------------------------------------------------------ */
+#define NTD_CNN_NPARAMS 14737
+
+/* Bytes of workspace for one grid (0 if the grid is out of range). */
+size_t ntd_cnn_workspace_bytes(int nx, int ny, int nz);
+
+/* t = the network's filter vector for kappa (FP64 [N]); if y is not NULL it
+ * also receives the output before the softplus (float [N]).  Checks kappa
+ * (finite and > 0, else NTD_EINVAL) with one read-back, so it synchronises the
+ * stream once; the rest is stream-ordered. */
+int ntd_cnn_predict(int nx, int ny, int nz, const double *kappa, const float *params, double *t,
+                    float *y, void *workspace, size_t ws_bytes, void *stream);
+
+/* *loss (host) = mean over the grid of (t - target)^2 and grad (device, float
+ * [NTD_CNN_NPARAMS], same layout as params) = its gradient, with every
+ * back-propagated map rounded to bfloat16 as the forward activations are.
+ * Synchronises the stream (it returns the loss). */
+int ntd_cnn_loss_grad(int nx, int ny, int nz, const double *kappa, const double *target,
+                      const float *params, float *grad, double *loss, void *workspace,
+                      size_t ws_bytes, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; `step`
+ * counts from 1) on params with the moment vectors m and v (device, float
+ * [NTD_CNN_NPARAMS] each, zero before step 1).  Stream-ordered. */
+int ntd_cnn_adam(float *params, float *m, float *v, const float *grad, int step, float lr,
+                 void *stream);
+
 /* Static text for a status code. */
 const char *ntd_strerror(int status);
 

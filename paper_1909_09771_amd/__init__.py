@@ -87,6 +87,14 @@ def lib() -> ctypes.CDLL:
         L.ntd_batch_footprint_bytes.restype = Z
         L.ntd_batch_destroy.argtypes = [P]
         L.ntd_batch_destroy.restype = I
+        L.ntd_cnn_workspace_bytes.argtypes = [I, I, I]
+        L.ntd_cnn_workspace_bytes.restype = Z
+        L.ntd_cnn_predict.argtypes = [I, I, I, P, P, P, P, P, Z, P]
+        L.ntd_cnn_predict.restype = I
+        L.ntd_cnn_loss_grad.argtypes = [I, I, I, P, P, P, P, ctypes.POINTER(D), P, Z, P]
+        L.ntd_cnn_loss_grad.restype = I
+        L.ntd_cnn_adam.argtypes = [P, P, P, P, I, ctypes.c_float, P]
+        L.ntd_cnn_adam.restype = I
         _lib = L
     return _lib
 
@@ -375,3 +383,92 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+CNN_NPARAMS = 14737
+
+
+class FilterNet:
+    """The learned filter vector's network (ntd_cnn_* in include/ntd.h): kappa ->
+    t > 0, four 3x3x3 convolution layers 1-16-16-16-1 on the matrix cores.
+
+    params: float32 array-like of CNN_NPARAMS values (per layer W[cout][tap][cin]
+    then b[cout]).  The parameters and the Adam moments live on `device`; a
+    workspace is kept per grid shape.
+    """
+
+    def __init__(self, params, device="cuda:0"):
+        self.device = torch.device(device)
+        p = torch.as_tensor(params, dtype=torch.float32).reshape(-1)
+        if p.numel() != CNN_NPARAMS:
+            raise ValueError("expected %d parameters, got %d" % (CNN_NPARAMS, p.numel()))
+        self.params = p.to(self.device).contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.step = 0
+        self._ws = {}
+
+    def _workspace(self, shape):
+        nz, ny, nx = shape
+        ws = self._ws.get(shape)
+        if ws is None:
+            nbytes = int(lib().ntd_cnn_workspace_bytes(nx, ny, nz))
+            if nbytes == 0:
+                raise NTDError(EINVAL, "ntd_cnn_workspace_bytes")
+            ws = self._ws[shape] = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return ws
+
+    def release_workspaces(self):
+        self._ws = {}
+
+    def predict(self, kappa: torch.Tensor, t: torch.Tensor | None = None,
+                y: torch.Tensor | None = None) -> torch.Tensor:
+        """t (float64, shape of kappa) for one field; y optionally receives the
+        output before the softplus (float32)."""
+        if kappa.dim() != 3:
+            raise ValueError("kappa must have shape (nz, ny, nx)")
+        shape = tuple(kappa.shape)
+        _check_vec(kappa, shape, self.device, "kappa")
+        if t is None:
+            t = torch.empty_like(kappa)
+        _check_vec(t, shape, self.device, "t")
+        if y is not None and (y.dtype != torch.float32 or tuple(y.shape) != shape
+                              or not y.is_contiguous() or y.device != self.device):
+            raise ValueError("y must be a contiguous float32 tensor of shape %s" % (shape,))
+        ws = self._workspace(shape)
+        nz, ny, nx = shape
+        st = lib().ntd_cnn_predict(nx, ny, nz, _dptr(kappa), _dptr(self.params), _dptr(t),
+                                   _dptr(y) if y is not None else None, _dptr(ws), ws.numel(),
+                                   _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_cnn_predict")
+        return t
+
+    def loss_grad(self, kappa: torch.Tensor, target: torch.Tensor, grad: torch.Tensor | None = None):
+        """(loss, grad): mean (t - target)^2 and its gradient (float32 [CNN_NPARAMS])."""
+        shape = tuple(kappa.shape)
+        _check_vec(kappa, shape, self.device, "kappa")
+        _check_vec(target, shape, self.device, "target")
+        grad = self.grad if grad is None else grad
+        ws = self._workspace(shape)
+        nz, ny, nx = shape
+        loss = ctypes.c_double()
+        st = lib().ntd_cnn_loss_grad(nx, ny, nz, _dptr(kappa), _dptr(target), _dptr(self.params),
+                                     _dptr(grad), ctypes.byref(loss), _dptr(ws), ws.numel(),
+                                     _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_cnn_loss_grad")
+        return loss.value, grad
+
+    def adam_step(self, grad: torch.Tensor, lr: float):
+        self.step += 1
+        st = lib().ntd_cnn_adam(_dptr(self.params), _dptr(self.m), _dptr(self.v), _dptr(grad),
+                                self.step, float(lr), _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_cnn_adam")
+
+    def train_step(self, kappa: torch.Tensor, target: torch.Tensor, lr: float) -> float:
+        loss, g = self.loss_grad(kappa, target)
+        self.adam_step(g, lr)
+        return loss

@@ -138,3 +138,24 @@ def test_batch_setup_rejects_invalid_arguments_without_gpu(L):
         getattr(L, name).restype = ctypes.c_int
     L.ntd_batch_apply.argtypes = [P, P, P, P]
     assert L.ntd_batch_apply(None, None, None, None) == 1
+
+
+def test_cnn_validation_before_any_launch(L):
+    P, I, Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    L.ntd_cnn_workspace_bytes.restype = Z
+    L.ntd_cnn_workspace_bytes.argtypes = [I, I, I]
+    assert L.ntd_cnn_workspace_bytes(0, 4, 4) == 0
+    assert L.ntd_cnn_workspace_bytes(1024, 1024, 512) == 0         # beyond 2^28 voxels
+    n = 32 ** 3
+    assert L.ntd_cnn_workspace_bytes(32, 32, 32) >= 168 * n
+    L.ntd_cnn_predict.argtypes = [I, I, I, P, P, P, P, P, Z, P]
+    L.ntd_cnn_predict.restype = I
+    assert L.ntd_cnn_predict(4, 4, 4, None, None, None, None, None, 0, None) == 1
+    L.ntd_cnn_loss_grad.argtypes = [I, I, I, P, P, P, P, P, P, Z, P]
+    L.ntd_cnn_loss_grad.restype = I
+    assert L.ntd_cnn_loss_grad(0, 4, 4, None, None, None, None, None, None, 0, None) == 1
+    L.ntd_cnn_adam.argtypes = [P, P, P, P, I, ctypes.c_float, P]
+    L.ntd_cnn_adam.restype = I
+    buf = ctypes.create_string_buffer(16)
+    assert L.ntd_cnn_adam(buf, buf, buf, buf, 0, 0.01, None) == 1     # step counts from 1
+    assert L.ntd_cnn_adam(buf, buf, buf, buf, 1, -1.0, None) == 1     # lr > 0

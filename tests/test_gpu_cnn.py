@@ -1,0 +1,162 @@
+"""Parity of the learned-filter network's kernels (ntd_cnn_* through the C ABI)
+with the oracle in oracle/cnn.py, which rounds to bfloat16 at the same points.
+
+Tolerances.  Both sides round the same values to bfloat16; they differ only
+where the float32 matrix-core sums and the float64 oracle sums fall on
+opposite sides of a bfloat16 rounding boundary (relative spacing 2^-8), which
+changes that one activation by one unit in its last place.  Such flips are
+rare (one in ~10^4 values) and a flip moves the output through one weight of a
+432-term sum, so the prediction t agrees to 1e-3 (absolute, t is O(1))
+element-wise and 1e-5 in mean.  The gradient goes through four more bfloat16
+maps and sums over the whole grid; per layer it agrees to 1e-3 in relative
+2-norm.  Adam runs in
+float32 against float64: 1e-5 relative plus, per step, one float32 spacing of
+the largest parameter.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import oracle.cnn as C
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def G(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(DEV)
+
+
+def H(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def trained_like_params(seed):
+    """Initial parameters with every bias moved off zero (so that no layer is
+    dead on a constant region)."""
+    p = W.cnn_init_params(seed).astype(np.float64)
+    p += np.random.default_rng(seed + 1).normal(0, 0.05, p.size)
+    return p.astype(np.float32)
+
+
+# (nz, ny, nx): ragged x tiles (16-voxel tiles with a tail), a single voxel,
+# a single row, one plane, several tiles
+SHAPES = [(9, 7, 19), (1, 1, 1), (1, 1, 40), (1, 12, 33), (16, 16, 48)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_cnn_forward_parity(shape):
+    import paper_1909_09771_amd as P
+    nz, ny, nx = shape
+    kappa = W.kappa_subcubes(nx, ny, nz, 61, cubes=3, log10_lo=-3, log10_hi=3)
+    p = trained_like_params(62)
+    net = P.FilterNet(p)
+    y = torch.empty(shape, dtype=torch.float32, device=DEV)
+    t = H(net.predict(G(kappa), y=y))
+    ref = C.forward(p, kappa)
+    err = np.abs(t - ref["t"])
+    print("forward %s: max |dt| %.2e mean %.2e" % (shape, err.max(), err.mean()))
+    assert err.max() <= 1e-3 and err.mean() <= 1e-5
+    assert np.abs(H(y) - ref["y"]).max() <= 2e-3
+    assert np.all(t > 0)
+
+
+def test_cnn_constant_kappa_gives_one():
+    import paper_1909_09771_amd as P
+    net = P.FilterNet(W.cnn_init_params(5))
+    t = H(net.predict(G(W.kappa_const(20, 6, 5, 3.0))))
+    np.testing.assert_allclose(t, 1.0, rtol=1e-6)
+
+
+@pytest.mark.parametrize("shape", [(9, 7, 19), (12, 12, 32)])
+def test_cnn_loss_grad_parity(shape):
+    import paper_1909_09771_amd as P
+    nz, ny, nx = shape
+    kappa = W.kappa_layers(nx, ny, nz, 71, layers=4, log10_lo=-2, log10_hi=2)
+    target = np.random.default_rng(72).uniform(0.05, 1.0, shape)
+    p = trained_like_params(73)
+    net = P.FilterNet(p)
+    loss, g = net.loss_grad(G(kappa), G(target))
+    g = H(g)
+    loss_o, g_o = C.loss_grad(p, kappa, target)
+    assert abs(loss - loss_o) <= 1e-4 * loss_o
+    offs = np.cumsum([0] + [co * 27 * ci + co for ci, co in C.LAYERS])
+    for l in range(4):
+        a, b = g[offs[l]:offs[l + 1]], g_o[offs[l]:offs[l + 1]]
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        print("grad %s layer %d: rel 2-norm error %.2e" % (shape, l, rel))
+        assert rel <= 1e-3, (l, rel)
+
+
+def test_cnn_adam_parity():
+    import paper_1909_09771_amd as P
+    rng = np.random.default_rng(81)
+    p0 = rng.normal(0, 0.1, C.param_count()).astype(np.float32)
+    net = P.FilterNet(p0)
+    po, m, v = p0.astype(np.float64), np.zeros(p0.size), np.zeros(p0.size)
+    for step in range(1, 4):
+        g = rng.normal(0, 1e-3, p0.size).astype(np.float32)
+        net.adam_step(G(g, torch.float32), 1e-3)
+        po, m, v = C.adam(po, g.astype(np.float64), m, v, step, 1e-3)
+    # float32 parameters: each of the 3 steps rounds to half a unit in the last
+    # place of |p| <= max|p|, plus float32 rounding inside the update
+    atol = 3 * float(np.spacing(np.float32(np.abs(po).max())))
+    np.testing.assert_allclose(H(net.params), po, rtol=1e-5, atol=atol)
+
+
+def test_cnn_training_lowers_the_loss():
+    import paper_1909_09771_amd as P
+    kappa = G(W.kappa_mixture(16, 91))
+    target = G(C.eigen_target(O.assemble(H(kappa), W.BC_ALL_DIRICHLET)))
+    net = P.FilterNet(W.cnn_init_params(92))
+    first = net.train_step(kappa, target, 3e-3)
+    for _ in range(60):
+        last = net.train_step(kappa, target, 3e-3)
+    print("training loss %.3e -> %.3e" % (first, last))
+    assert last < 0.5 * first
+
+
+def test_cnn_rejects_bad_kappa():
+    import paper_1909_09771_amd as P
+    net = P.FilterNet(W.cnn_init_params(1))
+    k = W.kappa_const(8, 8, 8)
+    k[3, 2, 1] = 0.0
+    with pytest.raises(P.NTDError) as ei:
+        net.predict(G(k))
+    assert ei.value.status == P.EINVAL
+
+
+def test_gpu_targets_match_oracle():
+    """Inverse iteration through the library's batched PCG against the oracle's
+    sparse direct solves, on two fields of different sizes."""
+    from paper_1909_09771_amd import learned
+    fields = [W.kappa_mixture(12, 101), W.kappa_mixture(16, 102)]
+    bcs = [W.BC_ALL_DIRICHLET.copy()] * 2
+    ts = learned.eigen_targets([G(k) for k in fields], bcs, tol=1e-10)
+    for k, bc, t in zip(fields, bcs, ts):
+        want = C.eigen_target(O.assemble(k, bc))
+        assert np.abs(H(t) - want).max() <= 1e-7
+
+
+@pytest.mark.parametrize("schur", ["newton", "diag"])
+def test_predicted_t_keeps_the_filter_property(schur):
+    """B(t) t = A t holds for the network's t: applying B^{-1} to A t gives t
+    back (FP64 factors and sweeps), and PCG with it converges."""
+    import paper_1909_09771_amd as P
+    kappa = G(W.kappa_mixture(20, 111))
+    net = P.FilterNet(trained_like_params(112))
+    t = net.predict(kappa)
+    S = P.Solver(kappa, W.BC_ALL_DIRICHLET, t=t, prec="fp64", schur=schur)
+    back = H(S.apply(S.spmv(t)))
+    tt = H(t)
+    assert np.linalg.norm(back - tt) <= 1e-9 * np.linalg.norm(tt)
+    b = G(W.rhs_uniform(20, 20, 20, 113))
+    x, it, rr, st = S.pcg(b, tol=1e-8, maxit=2000)
+    assert st == P.OK and rr <= 1e-8
+    S.close()

@@ -198,3 +198,40 @@ def scaled_workload(name: str, n: int) -> dict:
         return dict(n=(n, n, n), kappa=kappa, bc=BC_ALL_DIRICHLET.copy(),
                     b=rhs_uniform(n, n, n, 701), t=None)
     raise KeyError(name)
+
+
+def kappa_mixture(n: int, seed: int) -> np.ndarray:
+    """A field of the learned-filter sets: from PCG64(seed) draw the kind
+    (subcubes / z-layers / spheres, equally likely), the contrast exponent
+    c ~ U(2, 6) and a sub-seed; subcubes (4 or 8 per side) and layers (8) take
+    kappa = 10**U(0, c), spheres (20..100, radii U(0.02, 0.08)) kappa = 10**c
+    inside and 1 outside."""
+    rng = np.random.default_rng(seed)
+    kind = int(rng.integers(3))
+    c = float(rng.uniform(2.0, 6.0))
+    sub = int(rng.integers(1 << 30))
+    if kind == 0:
+        return kappa_subcubes(n, n, n, sub, cubes=int(rng.choice([4, 8])), log10_lo=0.0,
+                              log10_hi=c)
+    if kind == 1:
+        return kappa_layers(n, n, n, sub, layers=8, log10_lo=0.0, log10_hi=c)
+    return kappa_spheres(n, n, n, sub, count=int(rng.integers(20, 101)), inside=10.0 ** c,
+                         outside=1.0)
+
+
+CNN_LAYERS = [(1, 16), (16, 16), (16, 16), (16, 1)]   # (cin, cout) of the filter network
+
+
+def cnn_init_params(seed: int) -> np.ndarray:
+    """Initial parameters of the filter network (float32, per layer W[cout][27][cin]
+    then b[cout]): He-normal weights (std sqrt(2 / (27 cin))) from PCG64(seed),
+    zero biases except the last, log(e^(1 - 1e-3) - 1), which makes the output
+    softplus(b) + 1e-3 equal 1 where the features vanish."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in CNN_LAYERS:
+        parts.append(rng.normal(0.0, np.sqrt(2.0 / (27 * ci)), size=co * 27 * ci))
+        parts.append(np.zeros(co))
+    p = np.concatenate(parts)
+    p[-1] = np.log(np.expm1(1.0 - 1.0e-3))
+    return p.astype(np.float32)
