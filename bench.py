@@ -110,6 +110,7 @@ def parse():
     ap.add_argument("--learn-lr", type=float, default=2e-3)
     ap.add_argument("--learn-eval", type=int, default=8, help="held-out evaluation fields")
     ap.add_argument("--learn-eval-n", type=int, default=128, help="cube side of the evaluation fields")
+    ap.add_argument("--learn-maxit", type=int, default=2000, help="PCG iteration cap of the evaluation")
     return ap.parse_args()
 
 
@@ -417,16 +418,25 @@ def learned_suite(args):
         for i, k in enumerate(evk):
             kd = g(k)
             b = g(W.rhs_uniform(ne, ne, ne, 30000 + i))
-            r = Lr.compare(net, kd, bc, b, tol=args.tol, maxit=args.maxit, prec="mixed",
+            r = Lr.compare(net, kd, bc, b, tol=args.tol, maxit=args.learn_maxit, prec="mixed",
                            schur=schur, smoother=smoother)
-            r["target"] = Lr.solve_with(kd, bc, b, evt[i], args.tol, args.maxit, "mixed", schur,
-                                        smoother)
+            r["target"] = Lr.solve_with(kd, bc, b, evt[i], args.tol, args.learn_maxit, "mixed",
+                                        schur, smoother)
             log("%s+%s field %d: iterations ones %d, target %d%s, learned %d%s" % (
                 schur, smoother, i, r["ones"]["iters"], r["target"]["iters"],
                 " (t=1 fallback)" if r["target"]["fallback"] else "", r["learned"]["iters"],
                 " (t=1 fallback)" if r["learned"]["fallback"] else ""))
             rows.append(r)
         summ = {}
+        conv = [r for r in rows if all(r[k]["status"] == 0 for k in ("ones", "target", "learned"))]
+        for key in ("target", "learned"):   # against t = 1, on fields every candidate solved
+            d = [r[key]["iters"] - r["ones"]["iters"] for r in conv]
+            summ[key + "_vs_ones"] = dict(fewer=int(sum(x < 0 for x in d)),
+                                          same=int(sum(x == 0 for x in d)),
+                                          more=int(sum(x > 0 for x in d)),
+                                          mean_change_pct=round(float(np.mean(
+                                              [100.0 * (r[key]["iters"] / r["ones"]["iters"] - 1)
+                                               for r in conv])) if conv else 0.0, 2))
         for key in ("ones", "target", "learned"):
             summ[key] = dict(
                 mean_iters=round(float(np.mean([r[key]["iters"] for r in rows])), 2),

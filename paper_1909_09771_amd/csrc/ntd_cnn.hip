@@ -36,7 +36,7 @@ constexpr int kTaps = 27;
 constexpr int kHid = 16;
 constexpr float kEpsT = 1.0e-3f;
 constexpr double kFeatureScale = 3.0;
-constexpr int kWgMaxBlocks = 512;   // weight-gradient partial blocks
+constexpr int kWgMaxBlocks = 256;   // weight-gradient partial blocks
 constexpr int kRedBlocks = 1024;    // reduction partial blocks
 constexpr size_t kAlign = 256;
 constexpr long long kMaxVoxels = 1LL << 28;
@@ -109,6 +109,102 @@ struct ConvArgs {
     int nx, ny, nz;
 };
 
+// A-operand fragments of the 16-voxel tile whose lane row is voxel (x, y, z):
+// k = 32 kb + 8 g + j.  Every load is issued (at voxel 0 where the neighbour
+// is outside the grid or the tile) and masked afterwards, so that the wait
+// counts stay exact when the next tile's loads are in flight.
+template <int CIN>
+__device__ __forceinline__ void conv_frag(const ConvArgs &a, int x, int y, int z, int g,
+                                          bf16x8 (&av)[pack_kb(CIN)]) {
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    if constexpr (CIN == kHid) {
+#pragma unroll
+        for (int kb = 0; kb < pack_kb(CIN); ++kb) {
+            // tap 2 kb + g/2, channels 8 (g%2) .. +7
+            const int tap = 2 * kb + (g >> 1);
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int xx = x + dx, yy = y + dy, zz = z + dz;
+            const bool ok = tap < kTaps && x < nx && xx >= 0 && xx < nx && yy >= 0 && yy < ny &&
+                            zz >= 0 && zz < nz;
+            const size_t vox = ok ? ((size_t)zz * ny + yy) * nx + xx : 0;
+            const bf16x8 v = *reinterpret_cast<const bf16x8 *>(a.in + vox * kHid +
+                                                                (size_t)((g & 1) << 3));
+            const bf16x8 zero = {};
+            av[kb] = ok ? v : zero;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {  // one input channel: k = tap = 8 g + j
+            const int tap = 8 * g + j;
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int xx = x + dx, yy = y + dy, zz = z + dz;
+            const bool ok = tap < kTaps && x < nx && xx >= 0 && xx < nx && yy >= 0 && yy < ny &&
+                            zz >= 0 && zz < nz;
+            const size_t vox = ok ? ((size_t)zz * ny + yy) * nx + xx : 0;
+            const bf16_t h = a.in[vox];
+            av[0][j] = __builtin_bit_cast(__bf16, ok ? h : (bf16_t)0);
+        }
+    }
+}
+
+// Values the epilogue of the tile at x0 reads besides the accumulators: the
+// ReLU mask of its outputs (kEpiMask), loaded before the next tile's fragments
+// are issued so that waiting for them leaves those in flight.
+struct ConvPre {
+    bf16_t mask[4];
+};
+
+template <int EPI>
+__device__ __forceinline__ ConvPre conv_pre(const ConvArgs &a, int x0, int y, int z, int lane) {
+    ConvPre p{};
+    if constexpr (EPI == kEpiMask) {
+        const int g = lane >> 4, n = lane & 15;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int xo = x0 + 4 * g + i;
+            const size_t v = ((size_t)z * a.ny + y) * a.nx + (xo < a.nx ? xo : a.nx - 1);
+            p.mask[i] = a.mask[v * kHid + n];
+        }
+    }
+    return p;
+}
+
+// D[4 g + i][n] of the tile at x0 sits in lane 16 g + n, element i; bias is
+// this lane's output-channel bias (kEpiRelu: channel n, kEpiFinal: channel 0).
+template <int EPI>
+__device__ __forceinline__ void conv_out(const ConvArgs &a, int x0, int y, int z, int lane,
+                                         float bias, const ConvPre &pre, const f32x4 &acc) {
+    const int g = lane >> 4, n = lane & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int xo = x0 + 4 * g + i;
+        if (xo >= a.nx) continue;
+        const size_t v = ((size_t)z * a.ny + y) * a.nx + xo;
+        if constexpr (EPI == kEpiRelu) {
+            a.out[v * kHid + n] = f2bf(fmaxf(acc[i] + bias, 0.0f));
+        } else if constexpr (EPI == kEpiMask) {
+            a.out[v * kHid + n] = pre.mask[i] != 0 ? f2bf(acc[i]) : (bf16_t)0;
+        } else {
+            if (n == 0) {
+                const float yv = acc[i] + bias;
+                a.y[v] = yv;
+                if (a.t) a.t[v] = (double)(softplusf(yv) + kEpsT);
+            }
+        }
+    }
+}
+
+template <int NKB>
+__device__ __forceinline__ f32x4 conv_mma(const bf16x8 (&av)[NKB], const bf16x8 (&wb)[NKB]) {
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[kb], wb[kb], acc, 0, 0, 0);
+    return acc;
+}
+
+// One wavefront per grid row (y, z), tiles of 16 voxels along x; the
+// fragments of the next tile load while the current tile's MFMAs run.
 template <int CIN, int EPI>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     constexpr int NKB = pack_kb(CIN);
@@ -116,60 +212,31 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= (long long)a.ny * a.nz) return;  // whole wavefront
     const int y = (int)(row % a.ny), z = (int)(row / a.ny);
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nx = a.nx;
     const bf16x8 *wp = reinterpret_cast<const bf16x8 *>(a.wp);
     bf16x8 wb[NKB];
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) wb[kb] = wp[kb * 64 + lane];
     const int m = lane & 15, g = lane >> 4;
-    for (int x0 = 0; x0 < nx; x0 += 16) {
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const int x = x0 + m;  // this lane's row of the A operand
-#pragma unroll
-        for (int kb = 0; kb < NKB; ++kb) {
-            bf16x8 av = {};
-            if constexpr (CIN == kHid) {
-                // k = 32 kb + 8 g + j: tap 2 kb + g/2, channels 8 (g%2) .. +7
-                const int tap = 2 * kb + (g >> 1);
-                const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-                const int xx = x + dx, yy = y + dy, zz = z + dz;
-                if (tap < kTaps && x < nx && xx >= 0 && xx < nx && yy >= 0 && yy < ny && zz >= 0 &&
-                    zz < nz)
-                    av = *reinterpret_cast<const bf16x8 *>(
-                        a.in + (((size_t)zz * ny + yy) * nx + xx) * kHid + (size_t)((g & 1) << 3));
-            } else {
-                // one input channel: k = tap = 8 g + j
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int tap = 8 * g + j;
-                    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-                    const int xx = x + dx, yy = y + dy, zz = z + dz;
-                    if (tap < kTaps && x < nx && xx >= 0 && xx < nx && yy >= 0 && yy < ny &&
-                        zz >= 0 && zz < nz)
-                        av[j] = __builtin_bit_cast(__bf16, a.in[((size_t)zz * ny + yy) * nx + xx]);
-                }
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, wb[kb], acc, 0, 0, 0);
-        }
-        // D[4 g + i][n] sits in lane 16 g + n, element i
-        const int n = lane & 15;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int xo = x0 + 4 * g + i;
-            if (xo >= nx) continue;
-            const size_t v = ((size_t)z * ny + y) * nx + xo;
-            if constexpr (EPI == kEpiRelu) {
-                a.out[v * kHid + n] = f2bf(fmaxf(acc[i] + a.bias[n], 0.0f));
-            } else if constexpr (EPI == kEpiMask) {
-                a.out[v * kHid + n] = a.mask[v * kHid + n] != 0 ? f2bf(acc[i]) : (bf16_t)0;
-            } else {
-                if (n == 0) {
-                    const float yv = acc[i] + a.bias[0];
-                    a.y[v] = yv;
-                    if (a.t) a.t[v] = (double)(softplusf(yv) + kEpsT);
-                }
-            }
-        }
+    float bias = 0.0f;
+    if constexpr (EPI == kEpiRelu) bias = a.bias[m];
+    if constexpr (EPI == kEpiFinal) bias = a.bias[0];
+    bf16x8 fa[NKB], fb[NKB];
+    conv_frag<CIN>(a, m, y, z, g, fa);
+    for (int x0 = 0;;) {
+        // past the last tile the "next" loads repeat the current tile
+        ConvPre pre = conv_pre<EPI>(a, x0, y, z, lane);
+        const int xa = x0 + 16 < nx ? x0 + 16 : x0;
+        conv_frag<CIN>(a, xa + m, y, z, g, fb);
+        conv_out<EPI>(a, x0, y, z, lane, bias, pre, conv_mma<NKB>(fa, wb));
+        if (x0 + 16 >= nx) break;
+        x0 += 16;
+        pre = conv_pre<EPI>(a, x0, y, z, lane);
+        const int xb = x0 + 16 < nx ? x0 + 16 : x0;
+        conv_frag<CIN>(a, xb + m, y, z, g, fa);
+        conv_out<EPI>(a, x0, y, z, lane, bias, pre, conv_mma<NKB>(fb, wb));
+        if (x0 + 16 >= nx) break;
+        x0 += 16;
     }
 }
 
@@ -236,13 +303,21 @@ __global__ __launch_bounds__(448) void k_wgrad(WgArgs a) {
     }
 }
 
+// grad[p] = sum over the blocks of partial[b][p]: 64 outputs per workgroup,
+// its four wavefronts summing every fourth block, combined in a fixed order.
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ partial, int blocks,
                                                       int stride, float *__restrict__ grad) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= stride) return;
+    __shared__ double sh[4][64];
+    const int seg = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int p = blockIdx.x * 64 + l;
     double s = 0.0;
-    for (int b = 0; b < blocks; ++b) s += partial[(size_t)b * stride + p];
-    grad[p] = (float)s;
+    if (p < stride) {
+#pragma unroll 8
+        for (int b = seg; b < blocks; b += 4) s += partial[(size_t)b * stride + p];
+    }
+    sh[seg][l] = s;
+    __syncthreads();
+    if (seg == 0 && p < stride) grad[p] = (float)(((sh[0][l] + sh[1][l]) + sh[2][l]) + sh[3][l]);
 }
 
 // Fixed-order block sum of 256 values in LDS; the result is valid in thread 0.
@@ -440,7 +515,7 @@ hipError_t wgrad(int nx, int ny, int nz, const bf16_t *h, const bf16_t *g, float
     hipLaunchKernelGGL((k_wgrad<CIN, COUT>), dim3(blocks), dim3(threads), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((stride + 255) / 256), dim3(256), 0, s, part, blocks,
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((stride + 63) / 64), dim3(256), 0, s, part, blocks,
                        stride, grad);
     return hipGetLastError();
 }
