@@ -63,11 +63,15 @@ def apply_bytes(prec: str, smoother: str):
 # three couplings, the inverted diagonal and their input and write their output
 # (FP64).  The pack reads r (and, with the smoother, zi and the four bands for
 # r - A zi) and writes the packed right-hand side; the unpack reads the packed
-# result and r (and zi), and writes z.
+# result and r (and zi), and writes z.  The symmetric smoother adds a third
+# stage: the SpMV into tv (48), tv = r - tv (24), both ILU(0) sweeps (96) and
+# z += zi with the r.z partials (32).
 def rest_bytes(prec: str, smoother: str):
     e = FACTOR_BYTES[prec]
     if smoother == "ilu0":
         return 2 * (5 * 8 + 8) + (6 * 8 + e) + (e + 3 * 8)
+    if smoother == "ilu0sym":
+        return 2 * (5 * 8 + 8) + (6 * 8 + e) + (e + 3 * 8) + 48 + 24 + 2 * (5 * 8 + 8) + 32
     return (8 + e) + (e + 2 * 8)
 
 
@@ -79,7 +83,7 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="cubic grid side")
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--schur", default="newton", choices=["diag", "newton"])
-    ap.add_argument("--smoother", default="ilu0", choices=["none", "ilu0"])
+    ap.add_argument("--smoother", default="ilu0", choices=["none", "ilu0", "ilu0sym"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
@@ -88,11 +92,13 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="run the preconditioner, the SpMV and a calibration copy, then exit")
     ap.add_argument("--reps", type=int, default=3, help="launches per kernel in --kernels-only")
-    ap.add_argument("--suite", default=None, choices=["paper", "batch", "learned"],
+    ap.add_argument("--suite", default=None, choices=["paper", "batch", "learned", "spheres"],
                     help="paper: the test matrices of Sec. 3 (Types 1-3, 100^3/200^3/350^3, "
                          "tol 1e-7 and 1e-10), one JSON line per case; batch: many independent "
                          "systems solved together, one JSON line per batch size; learned: train the "
-                         "filter-vector network and compare PCG with t = 1 and with its t")
+                         "filter-vector network and compare PCG with t = 1 and with its t; spheres: "
+                         "one solve of the 350^3 high-contrast inclusion field (b = 1) with its "
+                         "memory footprint")
     ap.add_argument("--sizes", default="100,200,350", help="cube sides of --suite paper")
     ap.add_argument("--precs", default="mixed,fp64", help="precisions of --suite paper")
     ap.add_argument("--batch-counts", default="64", help="systems per batch (--suite batch)")
@@ -347,6 +353,48 @@ CNN_FLOP_PER_VOXEL = 2 * (27 * 16 + 2 * 432 * 16 + 432)
 CNN_BYTES_PER_VOXEL = 16 + 4 + 192 + 12
 
 
+def spheres_suite(args):
+    """The high-contrast inclusion workload: --n^3 (default 350^3, 42.9 M unknowns),
+    200 spheres of radius U(0.02, 0.08) with kappa = 1e6 inside and 1 outside
+    (seed 301), Dirichlet faces, b = 1, t = 1; one setup and one PCG solve to --tol
+    per --precs entry with --schur/--smoother.  Reports setup and solve times,
+    iterations, the true relative residual, ntd_footprint_bytes and the drop of
+    free device memory from before the setup to after it (hipMemGetInfo)."""
+    import time
+    import numpy as np
+    import torch
+    import paper_1909_09771_amd as P
+    import workloads as W
+    dev = torch.device("cuda:0")
+    n = args.n if args.n != 256 else 350
+    w = W.workload("spheres350") if n == 350 else W.scaled_workload("spheres", n)
+    kappa = torch.from_numpy(w["kappa"]).to(dev)
+    b = torch.from_numpy(np.ascontiguousarray(w["b"])).to(dev)
+    log("spheres %d^3: kappa in [%g, %g], inside fraction %.4f" % (
+        n, w["kappa"].min(), w["kappa"].max(), float((w["kappa"] > 1).mean())))
+    for prec in args.precs.split(","):
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        free0 = torch.cuda.mem_get_info(dev)[0]
+        t0 = time.perf_counter()
+        S = P.Solver(kappa, w["bc"], prec=prec, schur=args.schur, smoother=args.smoother)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        free1 = torch.cuda.mem_get_info(dev)[0]
+        x, it, rr, st = S.pcg(b, tol=args.tol, maxit=args.maxit)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        line = {"suite": "spheres", "n": n, "prec": prec, "schur": args.schur,
+                "smoother": args.smoother, "tol": args.tol, "iters": it, "relres": rr,
+                "status": st, "setup_s": round(t1 - t0, 4), "solve_s": round(t2 - t1, 4),
+                "overall_s": round(t2 - t0, 4), "footprint_bytes": S.footprint_bytes,
+                "mem_get_info_delta_bytes": int(free0 - free1)}
+        print(json.dumps(line), flush=True)
+        S.close()
+        del S, x
+        torch.cuda.empty_cache()
+
+
 def learned_suite(args):
     """The learned filter vector: targets (the lowest eigenvector of A by inverse
     iteration with the library's batched FP64 PCG) on --learn-train mixture fields
@@ -464,6 +512,9 @@ def main():
         return
     if args.suite == "learned":
         learned_suite(args)
+        return
+    if args.suite == "spheres":
+        spheres_suite(args)
         return
     import torch
     import paper_1909_09771_amd as P

@@ -66,6 +66,12 @@ typedef struct ntd_handle ntd_handle;
  * (the preconditioner of the paper's experiments, Table 1). */
 #define NTD_SMOOTHER_NONE 0
 #define NTD_SMOOTHER_ILU0 1
+/* Symmetric combination (an addition to the paper): z1 = B_ILU^{-1} r,
+ * z2 = z1 + B^{-1}(r - A z1), z = z2 + B_ILU^{-1}(r - A z2).  B and B_ILU are
+ * symmetric, so this preconditioner is symmetric, which CG assumes; the
+ * combination of eq. com is not, and CG with it diverges on high-contrast
+ * inclusions.  Costs one more ILU(0) solve and one more SpMV per application. */
+#define NTD_SMOOTHER_ILU0_SYM 2
 
 /* Largest supported line length nx (one wavefront solves one line).  The
  * grid must also satisfy 8*nx*ny*nz < 2^31 (32-bit byte offsets). */
@@ -94,7 +100,8 @@ int ntd_setup(int nx, int ny, int nz, const double *kappa, const int *bc, const 
               void *stream, ntd_handle **out);
 
 /* z = (the handle's preconditioner)^{-1} r: B^{-1} r, or with the ILU(0)
- * smoother the combination of eq. com.  r and z are [N] device FP64 and must
+ * smoother the combination of eq. com, or the symmetric combination
+ * (NTD_SMOOTHER_ILU0_SYM).  r and z are [N] device FP64 and must
  * not overlap.  Stream-ordered, asynchronous. */
 int ntd_apply_precond(ntd_handle *h, const double *r, double *z, void *stream);
 
@@ -114,7 +121,8 @@ int ntd_apply_ilu0(ntd_handle *h, const double *r, double *z, void *stream);
  * upper level-3 sweep), ms[3] the rest of the application: the ILU(0) sweeps
  * when the handle has the smoother, the packing of the right-hand side into
  * the sweep layout (with r - A zi fused in when there is a smoother) and the
- * unpacking of the result to FP64 (with the r.z partials).  For
+ * unpacking of the result to FP64 (with the r.z partials), and with the
+ * symmetric smoother its third stage (SpMV, ILU(0) sweeps, update).  For
  * benchmarking. */
 int ntd_apply_profile(ntd_handle *h, const double *r, double *z, float *ms, void *stream);
 

@@ -203,6 +203,50 @@ def combo_apply(bands, F, dt, r, nblocks=2):
     return z
 
 
+def sym_combo_apply(bands, F, dt, r, nblocks=2):
+    """The symmetric combination: z1 = B_ILU^{-1} r, z2 = z1 + B^{-1}(r - A z1),
+    z = z2 + B_ILU^{-1}(r - A z2) -- the three steps in order, each one an oracle
+    routine (not from the paper: eq. com's combination is not symmetric)."""
+    r = _f64(r)
+    z1 = ilu0_apply(bands, dt, r, nblocks)
+    z2 = z1 + apply(F, r - spmv(bands, z1))
+    return z2 + ilu0_apply(bands, dt, r - spmv(bands, z2), nblocks)
+
+
+def pcg_with(bands, precond, b, tol=1e-8, maxit=200):
+    """Preconditioned CG (x0 = 0) with any preconditioner function z = precond(r),
+    stopping on the recursive residual and confirming with the true one (the
+    rules of pcg below); returns (x, iters, true relres, status)."""
+    b = _f64(b)
+    bn = np.sqrt(dot(b, b))
+    x = np.zeros_like(b)
+    if bn == 0.0:
+        return x, 0, 0.0, OK
+    r = b.copy()
+    z = precond(r)
+    p = z.copy()
+    rho = dot(r, z)
+    for it in range(1, maxit + 1):
+        q = spmv(bands, p)
+        pq = dot(p, q)
+        if not (pq > 0.0) or not np.isfinite(pq):
+            return x, it - 1, np.sqrt(dot(b - spmv(bands, x), b - spmv(bands, x))) / bn, EBREAKDOWN
+        alpha = rho / pq
+        x += alpha * p
+        r -= alpha * q
+        if np.sqrt(dot(r, r)) / bn <= tol:
+            res = b - spmv(bands, x)
+            tr = np.sqrt(dot(res, res)) / bn
+            if tr <= tol:
+                return x, it, tr, OK
+        z = precond(r)
+        rho_new = dot(r, z)
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    res = b - spmv(bands, x)
+    return x, maxit, np.sqrt(dot(res, res)) / bn, ENOCONV
+
+
 def pcg(bands, F, b, tol=1e-8, maxit=200, dt=None, nblocks=2):
     """PCG with B (dt None) or with the combination of B and ILU(0) (dt given);
     returns (x, iters, true relres, status, residual history)."""

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libntd.so")
 OK, EINVAL, ENOMEM, ENOTSPD, EBREAKDOWN, ENOCONV, EHIP = range(7)
 PREC = {"fp64": 0, "mixed": 1}
 SCHUR = {"newton": 0, "diag": 1}
-SMOOTHER = {"none": 0, "ilu0": 1}
+SMOOTHER = {"none": 0, "ilu0": 1, "ilu0sym": 2}
 EXPORTS = {"d": 0, "ax": 1, "ay": 2, "az": 3, "e1": 4, "minv": 5, "f2": 6, "dT": 7, "dP": 8,
            "xP": 9, "dt": 10}
 MAX_NX = 1024

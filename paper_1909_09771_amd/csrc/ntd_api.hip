@@ -54,7 +54,7 @@ size_t layout(ntd_handle *h, void *ws, int nx, int ny, int nz, int prec, int smo
         h->rp = (void *)c.take<char>(npack * tsz);
     }
     h->dt = h->dtinv = h->zi = h->tv = nullptr;
-    if (smoother == NTD_SMOOTHER_ILU0) {
+    if (smoother != NTD_SMOOTHER_NONE) {
         double **ilu[] = {&h->dt, &h->dtinv, &h->zi, &h->tv};
         for (double **a : ilu) *a = c.take<double>(N);
     }
@@ -141,12 +141,15 @@ int ilu_internal(ntd_handle *h, const double *r, double *z, hipStream_t s) {
     return NTD_OK;
 }
 
-// The handle's preconditioner: B^{-1} r, or with the smoother the combination
-// of eq. com evaluated as z = B_ILU^{-1} r + B^{-1}(r - A B_ILU^{-1} r).
-// ev: as for ntd_solve, with ev[0] recorded before the ILU(0) sweeps.
+// The handle's preconditioner: B^{-1} r; with the ILU(0) smoother the
+// combination of eq. com evaluated as z = B_ILU^{-1} r + B^{-1}(r - A B_ILU^{-1} r);
+// with the symmetric smoother that z followed by z += B_ILU^{-1}(r - A z).
+// ev: as for ntd_solve, with ev[0] recorded before the ILU(0) sweeps and ev[5]
+// after the last stage.
 int precond_internal(ntd_handle *h, const double *r, double *z, double *partials, int *np,
                      hipStream_t s, hipEvent_t *ev = nullptr) {
-    if (h->smoother != NTD_SMOOTHER_ILU0) return ntd_solve_any(h, r, nullptr, z, partials, np, s, ev);
+    if (h->smoother == NTD_SMOOTHER_NONE)
+        return ntd_solve_any(h, r, nullptr, z, partials, np, s, ev);
     if (ev) CK(hipEventRecord(ev[0], s));
     int st = ilu_internal(h, r, h->zi, s);
     if (st != NTD_OK) return st;
@@ -155,7 +158,17 @@ int precond_internal(ntd_handle *h, const double *r, double *z, double *partials
         for (int i = 1; i < 6; ++i) ev2[i] = ev[i];
         ev2[0] = ev[6];  // a spare event: the pack start inside the smoother region
     }
-    return ntd_solve_any(h, r, h->zi, z, partials, np, s, ev ? ev2 : nullptr);
+    const bool sym = h->smoother == NTD_SMOOTHER_ILU0_SYM;
+    st = ntd_solve_any(h, r, h->zi, z, sym ? nullptr : partials, sym ? nullptr : np, s,
+                       ev ? ev2 : nullptr);
+    if (st != NTD_OK || !sym) return st;
+    // third stage: tv = r - A z, zi = B_ILU^{-1} tv, z += zi with the r.z partials
+    CK(ntd::launch_spmv(grid_of(h), h->d, h->ax, h->ay, h->az, z, h->tv, nullptr, nullptr, s));
+    CK(ntd::launch_residual(h->tv, r, h->tv, h->N, s));
+    if ((st = ilu_internal(h, h->tv, h->zi, s)) != NTD_OK) return st;
+    CK(ntd::launch_add_dot(z, h->zi, r, h->N, partials, np, s));
+    if (ev) CK(hipEventRecord(ev[5], s));
+    return NTD_OK;
 }
 
 // Pack the FP64 natural-layout factors into the line records of the apply.
@@ -205,7 +218,9 @@ namespace ntd_host {
 
 size_t handle_bytes(int nx, int ny, int nz, int prec, int smoother, int epl, bool lean) {
     if (!grid_ok(nx, ny, nz, epl) || (prec != NTD_PREC_FP64 && prec != NTD_PREC_MIXED)) return 0;
-    if (smoother != NTD_SMOOTHER_NONE && smoother != NTD_SMOOTHER_ILU0) return 0;
+    if (smoother != NTD_SMOOTHER_NONE && smoother != NTD_SMOOTHER_ILU0 &&
+        smoother != NTD_SMOOTHER_ILU0_SYM)
+        return 0;
     ntd_handle tmp;
     return layout(&tmp, nullptr, nx, ny, nz, prec, smoother, epl, lean);
 }
@@ -217,7 +232,9 @@ int handle_create(int nx, int ny, int nz, const int *bc, int prec, int schur, in
     if (!grid_ok(nx, ny, nz, epl)) return NTD_EINVAL;
     if (prec != NTD_PREC_FP64 && prec != NTD_PREC_MIXED) return NTD_EINVAL;
     if (schur != NTD_SCHUR_NEWTON && schur != NTD_SCHUR_DIAG) return NTD_EINVAL;
-    if (smoother != NTD_SMOOTHER_NONE && smoother != NTD_SMOOTHER_ILU0) return NTD_EINVAL;
+    if (smoother != NTD_SMOOTHER_NONE && smoother != NTD_SMOOTHER_ILU0 &&
+        smoother != NTD_SMOOTHER_ILU0_SYM)
+        return NTD_EINVAL;
     int ndir = 0;
     for (int f = 0; f < 6; ++f) {
         if (bc[f] != NTD_BC_DIRICHLET && bc[f] != NTD_BC_NEUMANN) return NTD_EINVAL;
@@ -295,7 +312,7 @@ int setup_handle(int nx, int ny, int nz, const double *kappa, const int *bc, con
     if (hflag & ntd::kFlagBadInput) FAIL(NTD_EINVAL);
     if ((st = handle_assemble(h, kappa, bc, s)) != NTD_OK) goto fail;
     HK(ntd::launch_setup(handle_setup_args(h, t), h->epl, s));
-    if (smoother == NTD_SMOOTHER_ILU0)
+    if (smoother != NTD_SMOOTHER_NONE)
         HK(ntd::launch_ilu_factor(h->ilu, h->d, h->ax, h->ay, h->az, h->dt, h->dtinv, h->flag, s));
     if ((st = handle_flag_async(h, &hflag, s)) != NTD_OK) goto fail;
     HK(hipStreamSynchronize(s));
@@ -341,7 +358,7 @@ int ntd_apply_ntd(ntd_handle *h, const double *r, double *z, void *stream) {
 }
 
 int ntd_apply_ilu0(ntd_handle *h, const double *r, double *z, void *stream) {
-    if (!h || !r || !z || r == z || h->smoother != NTD_SMOOTHER_ILU0) return NTD_EINVAL;
+    if (!h || !r || !z || r == z || h->smoother == NTD_SMOOTHER_NONE) return NTD_EINVAL;
     return ilu_internal(h, r, z, S(stream));
 }
 

@@ -224,6 +224,8 @@ hipError_t launch_axpy2_norm(double *x, double *r, const double *p, const double
                              const Scalars *sc, long long N, double *partials, int *nparts,
                              hipStream_t s);
 hipError_t launch_xpay(double *p, const double *z, const Scalars *sc, long long N, hipStream_t s);
+hipError_t launch_add_dot(double *z, const double *w, const double *r, long long N,
+                          double *partials, int *nparts, hipStream_t s);
 hipError_t launch_residual(double *out, const double *b, const double *Ax, long long N,
                            hipStream_t s);
 hipError_t launch_fill(double *x, double v, long long N, hipStream_t s);

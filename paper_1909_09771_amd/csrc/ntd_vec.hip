@@ -186,6 +186,22 @@ __global__ void __launch_bounds__(kBlock) k_residual(double *__restrict__ out,
         out[i] = b[i] - Ax[i];
 }
 
+// z += w; partials of r.z (the last stage of the symmetric combination).
+__global__ void __launch_bounds__(kBlock) k_add_dot(double *__restrict__ z,
+                                                    const double *__restrict__ w,
+                                                    const double *__restrict__ r, long long N,
+                                                    double *__restrict__ partials) {
+    double acc = 0.0;
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < N;
+         i += (long long)gridDim.x * kBlock) {
+        const double zv = z[i] + w[i];
+        z[i] = zv;
+        acc += r[i] * zv;
+    }
+    const double t = block_sum(acc);
+    if (partials && threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
 __global__ void __launch_bounds__(kBlock) k_fill(double *__restrict__ x, double v, long long N) {
     for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < N;
          i += (long long)gridDim.x * kBlock)
@@ -270,6 +286,14 @@ hipError_t launch_xpay(double *p, const double *z, const Scalars *sc, long long 
 hipError_t launch_residual(double *out, const double *b, const double *Ax, long long N,
                            hipStream_t s) {
     hipLaunchKernelGGL(k_residual, dim3(blocks_for(N)), dim3(kBlock), 0, s, out, b, Ax, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_dot(double *z, const double *w, const double *r, long long N,
+                          double *partials, int *nparts, hipStream_t s) {
+    const int nb = blocks_for(N);
+    if (nparts) *nparts = nb;
+    hipLaunchKernelGGL(k_add_dot, dim3(nb), dim3(kBlock), 0, s, z, w, r, N, partials);
     return hipGetLastError();
 }
 

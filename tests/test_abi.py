@@ -159,3 +159,12 @@ def test_cnn_validation_before_any_launch(L):
     buf = ctypes.create_string_buffer(16)
     assert L.ntd_cnn_adam(buf, buf, buf, buf, 0, 0.01, None) == 1     # step counts from 1
     assert L.ntd_cnn_adam(buf, buf, buf, buf, 1, -1.0, None) == 1     # lr > 0
+
+
+def test_symmetric_smoother_workspace(L):
+    n = 16
+    none_ = L.ntd_workspace_bytes(n, n, n, 1, 0)
+    ilu = L.ntd_workspace_bytes(n, n, n, 1, 1)
+    sym = L.ntd_workspace_bytes(n, n, n, 1, 2)
+    assert sym == ilu > none_                 # same ILU(0) arrays, tv used as the third stage's residual
+    assert L.ntd_workspace_bytes(n, n, n, 1, 3) == 0
