@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the solve with the filter network's t (trained first)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=3, help="oracle PCG iterations sampled")
     ap.add_argument("--kernels-only", action="store_true",
@@ -611,6 +613,42 @@ def main():
         log("comparison solve (%s): %.2f s, %d iterations" % (other, c1 - c0, it2))
         del S2, x2
 
+    if not args.no_learned:
+        # The filter network (--suite learned's defaults: 256 mixture fields of
+        # 32^3, all faces Dirichlet, 20 epochs), then the same solve with its t.
+        import numpy as np
+        from paper_1909_09771_amd import learned as Lr
+        torch.cuda.synchronize()
+        l0 = time.perf_counter()
+        kap = [torch.from_numpy(W.kappa_mixture(32, 10000 + i)).to(dev) for i in range(256)]
+        tgt = []
+        for i in range(0, 256, 64):
+            tgt += Lr.eigen_targets(kap[i:i + 64], [W.BC_ALL_DIRICHLET] * 64)
+        net = P.FilterNet(W.cnn_init_params(0))
+        hist = Lr.train(net, kap, tgt, 20, 2e-3)
+        net.release_workspaces()
+        del kap, tgt
+        torch.cuda.synchronize()
+        l1 = time.perf_counter()
+        tl = net.predict(kappa)
+        torch.cuda.synchronize()
+        l2 = time.perf_counter()
+        SL = P.Solver(kappa, bc, t=tl, prec=args.prec, schur=args.schur, smoother=args.smoother)
+        xl, itl, rrl, stl = SL.pcg(b, tol=args.tol, maxit=args.maxit)
+        torch.cuda.synchronize()
+        l3 = time.perf_counter()
+        spread = (tl.max() / tl.min()).item()
+        extra["compare_learned"] = {
+            "prec": args.prec, "s_to_solution": round(l3 - l1, 4),
+            "predict_s": round(l2 - l1, 4), "train_s": round(l1 - l0, 3), "iters": itl,
+            "relres": rrl, "status": stl, "t_max_over_min": round(spread, 4),
+            "net": "4 conv layers 3x3x3, trained on 256 mixture fields of 32^3 with all faces "
+                   "Dirichlet (this workload has Dirichlet at z=0 only), final loss %.4f" % hist[-1]}
+        log("learned-t solve: %.2f s (predict %.3f s), %d iterations; t max/min %.3f"
+            % (l3 - l1, l2 - l1, itl, spread))
+        del SL, xl, tl, net
+        torch.cuda.empty_cache()
+
     precond_ms = sweeps_ms + rest_ms
     copy_gbps = copy_bandwidth(dev)
     line = {
@@ -629,7 +667,8 @@ def main():
         "config": {"workload": "jump%d" % n, "grid": [n, n, n],
                    "kappa": "8^3 subcubes, 10^U(-3,3), seed %d" % (601 if n == 256 else 201),
                    "bc": "Dirichlet z=0, Neumann else", "tol": args.tol, "prec": args.prec,
-                   "schur": args.schur, "smoother": args.smoother, "filter": "t=1"},
+                   "schur": args.schur, "smoother": args.smoother, "filter": "t=1",
+                   "learned": "compare_learned: the same solve with the filter network's t"},
         "iters": iters,
         "setup_s": round(setup_s, 4),
         "solve_s": round(solve_s, 4),
