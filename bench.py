@@ -110,6 +110,9 @@ def parse():
     ap.add_argument("--batch-schur", default="diag", choices=["diag", "newton"])
     ap.add_argument("--batch-seq", action="store_true",
                     help="also solve the systems one at a time (one right-hand side each)")
+    ap.add_argument("--batch-tune", action="store_true",
+                    help="also autotune the bandwidth kernels' launch shape (ntd_batch_tune) "
+                         "and time the solve again")
     ap.add_argument("--batch-apply-only", action="store_true",
                     help="time the batched apply only (no PCG)")
     ap.add_argument("--learn-train", type=int, default=256, help="training fields (--suite learned)")
@@ -326,6 +329,23 @@ def batch_suite(args):
                              "unknowns_per_launch": units,
                              "bytes_per_unknown": "4e + 2e x nrhs, e = %d" % e},
                 "footprint_bytes": B.footprint_bytes}
+        if args.batch_tune and not args.batch_apply_only:
+            tt0 = time.perf_counter()
+            g = B.tune()
+            tt1 = time.perf_counter()
+            B.pcg(bs, tol=args.tol, maxit=args.maxit, graph=True)   # recaptures the graph
+            torch.cuda.synchronize()
+            tt2 = time.perf_counter()
+            xs, its2, rrs2, sts2 = B.pcg(bs, tol=args.tol, maxit=args.maxit, graph=True)
+            torch.cuda.synchronize()
+            tt3 = time.perf_counter()
+            gmax = min(512, (max(n ** 3 for n in sides) + 1023) // 1024)
+            line["tuned"] = {"gx_default": gmax, "gx": g, "tune_s": round(tt1 - tt0, 4),
+                             "solve_s": round(tt3 - tt2, 4),
+                             "iters_mean": round(sum(its2) / len(its2), 2),
+                             "all_ok": all(st == 0 for st in sts2)}
+            log("tuned launch shape: %d workgroups per entry (default %d); PCG %.3f s"
+                % (g, gmax, tt3 - tt2))
         del xs, zs
         B.close()
         del B

@@ -228,6 +228,17 @@ int ntd_batch_pcg_solve(ntd_batch *b, const double *const *rhs, double *const *x
 /* Device bytes the batch keeps in use inside its workspace. */
 size_t ntd_batch_footprint_bytes(const ntd_batch *b);
 
+/* Autotune the launch shape of the batch's bandwidth kernels (SpMV, vector
+ * updates, packing of the right-hand sides and unpacking of the results): time
+ * one round of them, on zero-filled vectors, for 1, 1/2, 1/4 and 1/8 of the
+ * workgroups per entry that the setup sized (one per 1024 points of the
+ * largest system, at most 512), and keep the fastest; *gx (HOST) receives
+ * it.  Until it is called the sized maximum is used, so results are bitwise
+ * repeatable run to run; a tuned batch is repeatable with the same choice (the
+ * reductions are fixed-order for a given count).  Discards a captured
+ * iteration graph.  Synchronises `stream`; must not overlap a solve. */
+int ntd_batch_tune(ntd_batch *b, int *gx, void *stream);
+
 /* Release the host-side state of the batch (not the caller's workspace). */
 int ntd_batch_destroy(ntd_batch *b);
 

@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
         L.ntd_batch_pcg_solve.argtypes = [P, PP, PP, D, I, I, ctypes.POINTER(I), ctypes.POINTER(D),
                                           ctypes.POINTER(I), P]
         L.ntd_batch_pcg_solve.restype = I
+        L.ntd_batch_tune.argtypes = [P, ctypes.POINTER(I), P]
+        L.ntd_batch_tune.restype = I
         L.ntd_batch_footprint_bytes.argtypes = [P]
         L.ntd_batch_footprint_bytes.restype = Z
         L.ntd_batch_destroy.argtypes = [P]
@@ -368,6 +370,15 @@ class Batch:
         if st != OK:
             raise NTDError(st, "ntd_batch_pcg_solve")
         return xs, list(it), list(rr), list(stv)
+
+    def tune(self) -> int:
+        """Autotune the workgroups per entry of the bandwidth kernels (ntd_batch_tune);
+        returns the choice."""
+        gx = ctypes.c_int(0)
+        st = lib().ntd_batch_tune(self._h, ctypes.byref(gx), _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_batch_tune")
+        return gx.value
 
     @property
     def footprint_bytes(self) -> int:

@@ -39,7 +39,7 @@ using ntd_host::Carver;
 }  // namespace
 
 struct ntd_batch {
-    int count = 0, nrhs = 0, prec = 0, epl = 0, gx = 0, D = 0;
+    int count = 0, nrhs = 0, prec = 0, epl = 0, gx = 0, gx_max = 0, D = 0;
     size_t used = 0;
     std::vector<ntd_handle *> sys;
     // device tables
@@ -381,6 +381,7 @@ int ntd_batch_setup(int count, const int *dims, const double *const *kappa, cons
     b->prec = prec;
     b->epl = batch_epl(count, dims);
     b->gx = gx_for(count, dims);
+    b->gx_max = b->gx;  // the entries' partials hold this many blocks
     b->D = count * nrhs;
     b->used = need;
     b->tabA = w->tabA;
@@ -547,6 +548,61 @@ int ntd_batch_pcg_solve(ntd_batch *b, const double *const *rhs, double *const *x
         relres[e] = b->hctl[e].relres;
         status[e] = b->hctl[e].status;
     }
+    return NTD_OK;
+}
+
+int ntd_batch_tune(ntd_batch *b, int *gx_out, void *stream) {
+    if (!b || !gx_out) return NTD_EINVAL;
+    hipStream_t s = S(stream);
+    // clean inputs for the timed kernels (every CG vector is rewritten by a solve)
+    for (int e = 0; e < b->D; ++e) {
+        const long long N = (long long)b->hV[e].nx * b->hV[e].ny * b->hV[e].nz;
+        for (double *v : {b->hV[e].r, b->hV[e].z, b->hV[e].p, b->hV[e].q})
+            CK(ntd::launch_fill(v, 0.0, N, s));
+    }
+    hipEvent_t ev[2];
+    int made = 0, st = NTD_OK;
+    for (; made < 2; ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess) { st = NTD_EHIP; break; }
+    // one round: the bandwidth kernels of an iteration that touch only the
+    // entries' own arrays (q = A p, p = z, pack of r, unpack into z)
+    auto round = [&](void) -> hipError_t {
+        hipError_t e;
+        if ((e = ntd::launch_batch_spmv(b->tabV, nullptr, b->D, b->gx, 0, s))) return e;
+        if ((e = ntd::launch_batch_xpay(b->tabV, nullptr, b->D, b->gx, true, s))) return e;
+        if ((e = pack_b(b, b->tabXp, nullptr, s))) return e;
+        return unpack_b(b, b->tabXp, nullptr, s);
+    };
+    int best = b->gx_max;
+    float best_ms = 0.0f;
+    for (int k = 0, last = 0; k < 4 && st == NTD_OK; ++k) {
+        const int g = (b->gx_max + (1 << k) - 1) >> k;
+        if (g < 1 || g == last) break;
+        last = g;
+        b->gx = g;
+        float ms = 0.0f;
+        if (round() != hipSuccess || hipEventRecord(ev[0], s) != hipSuccess) { st = NTD_EHIP; break; }
+        for (int r = 0; r < 3 && st == NTD_OK; ++r)
+            if (round() != hipSuccess) st = NTD_EHIP;
+        if (st != NTD_OK || hipEventRecord(ev[1], s) != hipSuccess ||
+            hipEventSynchronize(ev[1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) {
+            st = NTD_EHIP;
+            break;
+        }
+        if (k == 0 || ms < best_ms) {
+            best = g;
+            best_ms = ms;
+        }
+    }
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    b->gx = best;
+    if (b->gexec) {  // captured with the old grid
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    if (st != NTD_OK) return st;
+    *gx_out = best;
     return NTD_OK;
 }
 

@@ -197,3 +197,27 @@ def test_batch_pcg_follows_the_single_solve_near_the_rounding_floor(systems, tol
         assert sts[e] == st1 and abs(its[e] - it1) <= 1
         S.close()
     B.close()
+
+
+def test_batch_tune_keeps_parity(systems):
+    """The autotuned launch shape is one of the candidates (the sized maximum
+    and its halvings), and the batch still solves to the oracle's bar, with
+    graph replay equal to eager launches."""
+    nrhs = 2
+    B = make_batch(systems, nrhs, "mixed", "diag")
+    bs = rhs_list(systems, nrhs, 71)
+    B.pcg([G(b) for b in bs], tol=1e-8, maxit=500)     # captures a graph first
+    gmax = max((s["shape"][0] * s["shape"][1] * s["shape"][2] + 1023) // 1024 for s in systems)
+    g = B.tune()
+    assert g in {(gmax + (1 << k) - 1) >> k for k in range(4)}
+    assert B.tune() in {(gmax + (1 << k) - 1) >> k for k in range(4)}
+    xg, ig, rg, sg = B.pcg([G(b) for b in bs], tol=1e-8, maxit=500, graph=True)
+    xe, ie, re, se = B.pcg([G(b) for b in bs], tol=1e-8, maxit=500, graph=False)
+    assert ig == ie and sg == se
+    for a, b in zip(xg, xe):
+        assert np.array_equal(C(a), C(b))
+    for e, b in enumerate(bs):
+        s = systems[e // nrhs]
+        ito = O.pcg(s["bands"], O.setup(s["bands"], mode="diag"), b, 1e-8, 500)[1]
+        assert sg[e] == 0 and rg[e] <= 1e-8 and abs(ig[e] - ito) <= ito // 4 + 3
+    B.close()
