@@ -17,7 +17,8 @@ device copy of known size (the calibration of the HBM byte counters) and exits;
 it is the program the hardware-counter runs profile.
 
 --suite paper solves the test matrices of Sec. 3 (Types 1-3 at 100^3, 200^3,
-350^3, tolerances 1e-7 and 1e-10), one JSON line per case.  --suite batch solves
+350^3, tolerances 1e-7 and 1e-10), one JSON line per case (the paper's own
+preconditioner is --smoother ilu0).  --suite batch solves
 many independent systems together (64 cubes of side 32..96, 4 right-hand sides
 each, by default) and reports the batched sweeps' throughput.  --suite learned
 trains the filter-vector network on mixture fields and compares PCG with t = 1,
@@ -83,7 +84,9 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="cubic grid side")
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--schur", default="newton", choices=["diag", "newton"])
-    ap.add_argument("--smoother", default="ilu0", choices=["none", "ilu0", "ilu0sym"])
+    ap.add_argument("--smoother", default="ilu0sym", choices=["none", "ilu0", "ilu0sym"],
+                    help="ilu0sym (default): the symmetric ILU(0)-B-ILU(0) combination; ilu0: "
+                         "the combination of eq. com (Sec. 3); none: B alone")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
@@ -163,21 +166,34 @@ def cpu_baseline(w, args, gpu_iters: int):
     t0 = time.perf_counter()
     bands = O.assemble(w["kappa"], w["bc"])
     F = O.setup(bands, mode=args.schur)
-    dt = O.ilu0(bands, 2)[0] if args.smoother == "ilu0" else None
+    dt = O.ilu0(bands, 2)[0] if args.smoother != "none" else None
     t1 = time.perf_counter()
-    O.pcg(bands, F, w["b"], 1e-30, n_iters, dt=dt)
+    if args.smoother == "ilu0sym":
+        O.pcg_with(bands, lambda r: O.sym_combo_apply(bands, F, dt, r), w["b"], 1e-30, n_iters)
+    else:
+        O.pcg(bands, F, w["b"], 1e-30, n_iters, dt=dt)
     t2 = time.perf_counter()
     per_iter = (t2 - t1) / n_iters
     est = (t1 - t0) + gpu_iters * per_iter
     del bands, F, dt
     n = w["n"][0]
-    combo = " + ILU(0) combination" if args.smoother == "ilu0" else ""
+    combo = {"ilu0": " + ILU(0) combination", "ilu0sym": " + symmetric ILU(0) combination",
+             "none": ""}[args.smoother]
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(est, 3), "unit": "s", "cores": 1, "kind": "oracle",
             "sample": "FP64 oracle, %s Schur blocks%s: assembly+setup on the full %d^3 grid "
                       "(%.2f s) and %d PCG iterations (%.3f s/iter), extrapolated to the GPU's "
-                      "%d iterations; 1 thread of %d host cores"
+                      "%d iterations; 1 thread of %d host cores (%s)"
                       % (args.schur, combo, n, t1 - t0, n_iters, per_iter, gpu_iters,
-                         os.cpu_count() or 0)}
+                         os.cpu_count() or 0, model or "model unknown")}
 
 
 def kernels_only(args, S, b, n):

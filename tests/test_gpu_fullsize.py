@@ -2,7 +2,8 @@
 
 Workload jump256: 256^3 grid, kappa on 8^3 subcubes 10^U(-3,3) (seed 601),
 Dirichlet at z = 0 and Neumann on the other faces, b ~ U[-1,1] (seed 602),
-t = 1, Newton Schur blocks with the ILU(0) combination of eq. com (Sec. 3).
+t = 1, Newton Schur blocks with the ILU(0) combination of eq. com (Sec. 3) and
+with the symmetric ILU(0)-B-ILU(0) combination (the benchmark's default).
 The FP64 oracle computes the assembly, the SpMV, the three-level setup, the
 ILU(0) factorization and one application of each preconditioner at this size
 in seconds, so those are compared element by element.  PCG to 1e-8 is checked
@@ -52,6 +53,9 @@ def full():
     kappa = G(w["kappa"])
     solvers = {prec: P.Solver(kappa, w["bc"], prec=prec, schur="newton", smoother="ilu0")
                for prec in ("mixed", "fp64")}
+    for prec in ("mixed", "fp64"):
+        solvers[prec + "-sym"] = P.Solver(kappa, w["bc"], prec=prec, schur="newton",
+                                          smoother="ilu0sym")
     print("jump256: GPU setups done", flush=True)
     yield dict(w=w, bands=bands, F=F, dt=dt, S=solvers)
     for S in solvers.values():
@@ -99,6 +103,25 @@ def test_full_pcg_true_residual(full, prec):
     b = full["w"]["b"]
     x, it, rr, st = S.pcg(G(b), tol=1e-8, maxit=2000)
     print("jump256 PCG %s: %d iterations, relres %.3e" % (prec, it, rr), flush=True)
+    assert st == 0 and rr <= 1e-8
+    res = b - O.spmv(full["bands"], C(x))
+    assert np.linalg.norm(res) <= 1.01e-8 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-5), ("fp64", 1e-9)])
+def test_full_apply_symmetric(full, prec, tol):
+    S = full["S"][prec + "-sym"]
+    r = np.random.default_rng(812).uniform(-1.0, 1.0, full["w"]["b"].shape)
+    want = O.sym_combo_apply(full["bands"], full["F"], full["dt"], r, 2)
+    assert rel2(C(S.apply(G(r))), want) <= tol
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_full_pcg_symmetric_true_residual(full, prec):
+    S = full["S"][prec + "-sym"]
+    b = full["w"]["b"]
+    x, it, rr, st = S.pcg(G(b), tol=1e-8, maxit=2000)
+    print("jump256 PCG symmetric %s: %d iterations, relres %.3e" % (prec, it, rr), flush=True)
     assert st == 0 and rr <= 1e-8
     res = b - O.spmv(full["bands"], C(x))
     assert np.linalg.norm(res) <= 1.01e-8 * np.linalg.norm(b)
