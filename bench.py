@@ -722,7 +722,9 @@ def main():
         "roofline": {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": traffic_for(kname, args.prec, args.smoother, n)},
+                     "traffic": traffic_for(kname, args.prec, args.smoother, n),
+                     "measured_copy_GBps": round(copy_gbps, 1),
+                     "frac_of_measured_copy": round(achieved / copy_gbps, 5)},
     }
     line["rest_GBps"] = round(rest_bytes(args.prec, args.smoother) * N / (rest_ms * 1e-3) / 1e9, 1)
     line.update(extra)
