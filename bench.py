@@ -724,7 +724,12 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": traffic_for(kname, args.prec, args.smoother, n),
                      "measured_copy_GBps": round(copy_gbps, 1),
-                     "frac_of_measured_copy": round(achieved / copy_gbps, 5)},
+                     "frac_of_measured_copy": round(achieved / copy_gbps, 5),
+                     # the launch is a chain of dependent line solves: the longer
+                     # level-3 half walks n-1-floor((n-1)/2) planes, each plane a lower
+                     # and an upper level-2 pass over about n lines in all
+                     "chain_line_steps": (n - 1 - (n - 1) // 2) * n,
+                     "us_per_line_step": round(k_ms * 1e3 / ((n - 1 - (n - 1) // 2) * n), 4)},
     }
     line["rest_GBps"] = round(rest_bytes(args.prec, args.smoother) * N / (rest_ms * 1e-3) / 1e9, 1)
     line.update(extra)
