@@ -232,10 +232,17 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, 
     const int nx = g.nx;
     const unsigned nx8 = 8u * nx, nxy8 = 8u * (unsigned)g.nxy;
     const IluLanes<E, false> Ln(nx);
+    // Every load is issued, at line 0 for a line outside the grid and at the
+    // line itself for an absent neighbour: a skipped load would leave the
+    // waits before the next solve unable to count, and they would drain the
+    // loads in flight.  Values of absent neighbours, and neighbours that solve
+    // takes from LDS instead, are never used.
     auto load = [&](int ll, IluLine<E> &d) {
         int j, k;
-        if (!tile_line(g, b, ty, tz, w, ll, j, k)) return;
-        const unsigned so = 8u * (unsigned)(((long long)k * g.ny + j) * nx);
+        const bool ok = tile_line(g, b, ty, tz, w, ll, j, k);
+        const unsigned so = ok ? 8u * (unsigned)(((long long)k * g.ny + j) * nx) : 0u;
+        const unsigned sy = ok && j > 0 ? so - nx8 : so;
+        const unsigned sz = ok && k > 0 ? so - nxy8 : so;
         ld<E, false, VEC>(B.r, so, Ln, d.rv);
         ld<E, false, VEC>(B.di, so, Ln, d.di);
         // ax of element i-1 (0 at i = 0 and past the line)
@@ -244,14 +251,10 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, 
             const unsigned o = (Ln.eo[s] != kOOB && Ln.elem(s) > 0) ? Ln.eo[s] - 8u : kOOB;
             d.cx[s] = bload((double *)nullptr, B.ax, o, so);
         }
-        if (j > 0) {
-            ld<E, false, VEC>(B.ay, so - nx8, Ln, d.cy);
-            if (w == 0) ld<E, false, VEC>(B.y, so - nx8, Ln, d.vy);  // tile ty-1
-        }
-        if (k > 0) {
-            ld<E, false, VEC>(B.az, so - nxy8, Ln, d.cz);
-            if (ll - w == 0) ld<E, false, VEC>(B.y, so - nxy8, Ln, d.vz);  // tile tz-1
-        }
+        ld<E, false, VEC>(B.ay, sy, Ln, d.cy);
+        ld<E, false, VEC>(B.y, sy, Ln, d.vy);  // used at w = 0: tile ty-1
+        ld<E, false, VEC>(B.az, sz, Ln, d.cz);
+        ld<E, false, VEC>(B.y, sz, Ln, d.vz);  // used at ll - w = 0: tile tz-1
     };
     auto solve = [&](int ll, const IluLine<E> &d) {
         int j, k;
@@ -317,17 +320,20 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, 
 #pragma unroll
     for (int s = 0; s < E; ++s) A.cy[s] = A.cz[s] = A.vy[s] = A.vz[s] = Bq.cy[s] = Bq.cz[s] =
         Bq.vy[s] = Bq.vz[s] = 0.0;
+    // pairs of line diagonals with the next one's inputs in flight, then the
+    // last diagonal: no conditional half-steps, so the two input buffers keep
+    // their registers and no wait drains the prefetched loads
+    static_assert(NL % 2 == 1, "odd number of line diagonals");
     load(0, A);
-    for (int ll = 0; ll < NL; ll += 2) {
-        if (ll + 1 < NL) load(ll + 1, Bq);
+    for (int ll = 0; ll + 2 < NL; ll += 2) {
+        load(ll + 1, Bq);
         solve(ll, A);
         __syncthreads();
-        if (ll + 1 < NL) {
-            if (ll + 2 < NL) load(ll + 2, A);
-            solve(ll + 1, Bq);
-            __syncthreads();
-        }
+        load(ll + 2, A);
+        solve(ll + 1, Bq);
+        __syncthreads();
     }
+    solve(NL - 1, A);
 }
 
 // Backward sweep (I + Dt^{-1} U) z = y in place on the tiles of anti-diagonal L
@@ -347,21 +353,20 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_bwd_tile(IluGrid g, int L, 
     const int nx = g.nx;
     const unsigned nx8 = 8u * nx, nxy8 = 8u * (unsigned)g.nxy;
     const IluLanes<E, true> Ln(nx);
+    // every load issued, as in the forward sweep
     auto load = [&](int ll, IluLine<E> &d) {
         int j, k;
-        if (!tile_line(g, b, ty, tz, w, ll, j, k)) return;
-        const unsigned so = 8u * (unsigned)(((long long)k * g.ny + j) * nx);
+        const bool ok = tile_line(g, b, ty, tz, w, ll, j, k);
+        const unsigned so = ok ? 8u * (unsigned)(((long long)k * g.ny + j) * nx) : 0u;
+        const unsigned sy = ok && j < g.ny - 1 ? so + nx8 : so;
+        const unsigned sz = ok && k < g.nz - 1 ? so + nxy8 : so;
         ld<E, true, VEC>(B.y, so, Ln, d.rv);  // the forward result of this line
         ld<E, true, VEC>(B.di, so, Ln, d.di);
         ld<E, true, VEC>(B.ax, so, Ln, d.cx);
-        if (j < g.ny - 1) {
-            ld<E, true, VEC>(B.ay, so, Ln, d.cy);
-            if (w == kIluTile - 1) ld<E, true, VEC>(B.y, so + nx8, Ln, d.vy);  // tile ty+1
-        }
-        if (k < g.nz - 1) {
-            ld<E, true, VEC>(B.az, so, Ln, d.cz);
-            if (ll - w == kIluTile - 1) ld<E, true, VEC>(B.y, so + nxy8, Ln, d.vz);  // tile tz+1
-        }
+        ld<E, true, VEC>(B.ay, so, Ln, d.cy);
+        ld<E, true, VEC>(B.y, sy, Ln, d.vy);  // used at w = kIluTile-1: tile ty+1
+        ld<E, true, VEC>(B.az, so, Ln, d.cz);
+        ld<E, true, VEC>(B.y, sz, Ln, d.vz);  // used at ll - w = kIluTile-1: tile tz+1
     };
     auto solve = [&](int ll, const IluLine<E> &d) {
         int j, k;
@@ -427,17 +432,17 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_bwd_tile(IluGrid g, int L, 
 #pragma unroll
     for (int s = 0; s < E; ++s) A.cy[s] = A.cz[s] = A.vy[s] = A.vz[s] = Bq.cy[s] = Bq.cz[s] =
         Bq.vy[s] = Bq.vz[s] = 0.0;
+    static_assert(NL % 2 == 1, "odd number of line diagonals");
     load(NL - 1, A);
-    for (int ll = NL - 1; ll >= 0; ll -= 2) {
-        if (ll - 1 >= 0) load(ll - 1, Bq);
+    for (int ll = NL - 1; ll - 2 >= 0; ll -= 2) {
+        load(ll - 1, Bq);
         solve(ll, A);
         __syncthreads();
-        if (ll - 1 >= 0) {
-            if (ll - 2 >= 0) load(ll - 2, A);
-            solve(ll - 1, Bq);
-            __syncthreads();
-        }
+        load(ll - 2, A);
+        solve(ll - 1, Bq);
+        __syncthreads();
     }
+    solve(0, A);
 }
 
 inline int level_blocks(const IluGrid &g) {
