@@ -79,7 +79,7 @@ def rest_bytes(prec: str, smoother: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="cubic grid side")
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
@@ -605,11 +605,11 @@ def main():
     iters, relres, status = results[-1]
 
     # Preconditioner launches as PCG issues them, timed with HIP events on the
-    # solver's stream (median of 5).
+    # solver's stream (median of 21).
     z = torch.empty_like(b)
     S.apply_profile(b, z)
-    prof = [S.apply_profile(b, z) for _ in range(5)]
-    med = [sorted(p[i] for p in prof)[2] for i in range(4)]
+    prof = [S.apply_profile(b, z) for _ in range(21)]
+    med = [sorted(p[i] for p in prof)[10] for i in range(4)]
     lower_ms, twist_ms, upper_ms, rest_ms = med
     sweeps_ms = lower_ms + twist_ms + upper_ms
     N = n ** 3

@@ -425,11 +425,12 @@ struct Ws {
 
 size_t up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
+// Sizing when base is null (no pointer is formed then).
 Ws carve(char *base, long long N) {
     Ws w{};
     size_t o = 0;
     auto take = [&](size_t b) {
-        char *p = base + o;
+        char *p = base ? base + o : nullptr;
         o += up(b);
         return p;
     };
