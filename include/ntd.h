@@ -257,7 +257,7 @@ int ntd_batch_destroy(ntd_batch *b);
  * (z+dz, y+dy, x+dx); layers (cin, cout) = (1,16), (16,16), (16,16), (16,1).
  * Fields are [nz][ny][nx] as everywhere else; 1 <= nx*ny*nz <= 2^28.
  * The workspace (device, caller-owned, 256-byte aligned) holds activations,
- * gradient maps and packed weights: about 168 bytes per voxel + 15 MB.
+ * gradient maps and packed weights: about 168 bytes per voxel + 7 MB.
  * ------------------------------------------------------------------------ */
 #define NTD_CNN_NPARAMS 14737
 
