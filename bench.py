@@ -125,6 +125,8 @@ def parse():
     ap.add_argument("--learn-eval", type=int, default=8, help="held-out evaluation fields")
     ap.add_argument("--learn-eval-n", type=int, default=128, help="cube side of the evaluation fields")
     ap.add_argument("--learn-maxit", type=int, default=2000, help="PCG iteration cap of the evaluation")
+    ap.add_argument("--learn-configs", default="newton:ilu0sym,newton:ilu0,diag:none",
+                    help="schur:smoother pairs of the evaluation solves")
     return ap.parse_args()
 
 
@@ -439,7 +441,8 @@ def learned_suite(args):
     of side --learn-n (seeds 10000+i), Adam training, then PCG to --tol with
     t = 1, with the exact target and with the network's t on --learn-eval held-out
     fields of side --learn-eval-n (seeds 20000+i, b ~ U[-1,1] seed 30000+i),
-    MIXED, for the Newton blocks + ILU(0) and for the diagonal blocks alone.
+    MIXED, for each --learn-configs preconditioner (default: Newton blocks with the
+    symmetric and with the eq. com combination, and the diagonal blocks alone).
     One JSON line for the training, one per evaluation configuration."""
     import time
     import numpy as np
@@ -499,7 +502,7 @@ def learned_suite(args):
         "peak_bf16_TFLOPs": 2500.0, "peak_hbm_GBps": 8000.0}), flush=True)
     del kd, tout
     evt = Lr.eigen_targets([g(k) for k in evk], [bc] * len(evk))
-    for schur, smoother in (("newton", "ilu0"), ("diag", "none")):
+    for schur, smoother in (c.split(":") for c in args.learn_configs.split(",")):
         rows = []
         for i, k in enumerate(evk):
             kd = g(k)
