@@ -168,3 +168,18 @@ def test_symmetric_smoother_workspace(L):
     sym = L.ntd_workspace_bytes(n, n, n, 1, 2)
     assert sym == ilu > none_                 # same ILU(0) arrays, tv used as the third stage's residual
     assert L.ntd_workspace_bytes(n, n, n, 1, 3) == 0
+
+
+@pytest.mark.parametrize("prec,smoother", [(0, 0), (1, 0), (1, 1), (1, 2)])
+def test_storage_is_linear_in_the_unknowns(L, prec, smoother):
+    """The factorization and its workspace take O(N) storage (Sec. 2.3).  At a
+    fixed line length, doubling the number of planes doubles the bytes (fixed
+    tables aside).  Over cubes the bytes per unknown never grow: each line
+    record also holds a fixed per-lane part (scan multipliers, twist row), an
+    O(N / nx) term."""
+    a = L.ntd_workspace_bytes(128, 128, 64, prec, smoother)
+    b = L.ntd_workspace_bytes(128, 128, 128, prec, smoother)
+    c = L.ntd_workspace_bytes(128, 128, 256, prec, smoother)
+    assert abs(b / a - 2.0) <= 0.01 and abs(c / b - 2.0) <= 0.01
+    per = [L.ntd_workspace_bytes(n, n, n, prec, smoother) / n ** 3 for n in (32, 64, 128, 256)]
+    assert all(x >= y for x, y in zip(per, per[1:])) and per[-1] <= 260
