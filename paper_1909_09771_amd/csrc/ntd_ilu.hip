@@ -537,6 +537,9 @@ hipError_t launch_ilu_apply(const IluGrid &g, const double *ax, const double *ay
     if (e <= 1) return ilu_apply_v<1>(g, ax, ay, az, dtinv, r, z, s);
     if (e <= 2) return ilu_apply_v<2>(g, ax, ay, az, dtinv, r, z, s);
     if (e <= 4) return ilu_apply_v<4>(g, ax, ay, az, dtinv, r, z, s);
+    // 6 per lane (nx up to 384, e.g. 350) keeps the two input buffers in registers,
+    // where 8 per lane spills
+    if (e <= 6) return ilu_apply_v<6>(g, ax, ay, az, dtinv, r, z, s);
     if (e <= 8) return ilu_apply_v<8>(g, ax, ay, az, dtinv, r, z, s);
     return ilu_apply_v<16>(g, ax, ay, az, dtinv, r, z, s);
 }

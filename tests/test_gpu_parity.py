@@ -276,9 +276,14 @@ def test_deterministic_repeat():
 
 ILU_SHAPES = [((16, 12, 20), "jump"), ((7, 11, 37), "rand"), ((5, 4, 3), "rand"), ((1, 6, 9), "jump"),
               ((9, 1, 1), "rand"), ((2, 2, 2), "poisson"), ((41, 35, 24), "jump")]
+# lines longer than 256: 6 values per lane with whole-chunk loads (nx = 300) and
+# element loads (350), 8 per lane (500: the block split falls inside a line;
+# 512: whole chunks) and 16 per lane (600)
+ILU_WIDE_SHAPES = [((3, 4, 300), "rand"), ((2, 5, 350), "jump"), ((3, 3, 500), "rand"),
+                   ((2, 3, 512), "jump"), ((2, 2, 600), "rand")]
 
 
-@pytest.mark.parametrize("shape,kind", ILU_SHAPES)
+@pytest.mark.parametrize("shape,kind", ILU_SHAPES + ILU_WIDE_SHAPES)
 def test_ilu0_factor_and_apply_parity(shape, kind):
     kappa, bc = case(shape, kind)
     S = ntd().Solver(G(kappa), bc, prec="fp64", schur="newton", smoother="ilu0")
