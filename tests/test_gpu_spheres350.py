@@ -4,7 +4,8 @@ outside (seed 301), Dirichlet on every face, b = 1, MIXED, diagonal Schur blocks
 (the configuration that converges fastest on this field).
 
 The FP64 oracle assembles, sets up and applies B at this size in seconds, so
-those are compared element by element, with the bars of the small-size tests.
+those are compared element by element, with the bars of the small-size tests,
+and so are the ILU(0) factor and apply.
 A full PCG solve takes thousands of iterations here.  The FP64 attainable
 accuracy for b = 1 and this contrast is about 1e-6.  So PCG is run for a
 bounded number of iterations: its energy must fall, and its reported true
@@ -108,3 +109,26 @@ def test_sph350_pcg_bounded(sph):
               % (maxit, tr, rr, phi[-1]))
         assert abs(tr - rr) <= 1e-6 * tr
     assert phi[1] < phi[0] < 0.0
+
+
+def test_sph350_ilu0(sph):
+    """ILU(0) of the two-block diagonal of A (Sec. 3, eq. com) at full size: 350
+    points per line take 6 values per lane with element loads (350 is not a
+    multiple of 6).  The factor's diagonal and one application against the
+    oracle, element by element, with the bars of the small-size tests."""
+    import paper_1909_09771_amd as P
+    w = sph["w"]
+    dt, st = O.ilu0(sph["bands"], 2)
+    assert st == 0
+    S = P.Solver(G(w["kappa"]), w["bc"], prec="mixed", schur="diag", smoother="ilu0")
+    try:
+        np.testing.assert_allclose(C(S.export("dt")), dt, rtol=1e-13)
+        r = np.random.default_rng(353).uniform(-1.0, 1.0, w["kappa"].shape)
+        got = C(S.apply_ilu0(G(r)))
+        want = O.ilu0_apply(sph["bands"], dt, r, 2)
+        err = np.abs(got - want).max() / np.abs(want).max()
+        print("spheres350 ILU(0) apply: max rel err %.2e" % err)
+        assert err <= 1e-12
+    finally:
+        S.close()
+        torch.cuda.empty_cache()
