@@ -105,6 +105,10 @@ def parse():
                          "one solve of the 350^3 high-contrast inclusion field (b = 1) with its "
                          "memory footprint")
     ap.add_argument("--sizes", default="100,200,350", help="cube sides of --suite paper")
+    ap.add_argument("--types", default="1,2,3",
+                    help="test matrices of --suite paper: 1, 2 (as printed), 3, 2ring")
+    ap.add_argument("--paper-smoothers", default="ilu0",
+                    help="smoothers of --suite paper (ilu0 = the paper's eq. com)")
     ap.add_argument("--precs", default="mixed,fp64", help="precisions of --suite paper")
     ap.add_argument("--batch-counts", default="64", help="systems per batch (--suite batch)")
     ap.add_argument("--batch-rhs", type=int, default=4, help="right-hand sides per system")
@@ -219,42 +223,63 @@ def kernels_only(args, S, b, n):
                       "copy_bytes_each_way": src.numel() * 8}), flush=True)
 
 
+# Iteration counts of the paper's NTD+ILU(0) PCG (Sec. 3, Table 1), keyed by
+# (type, cube side, tolerance); context for --suite paper.
+TABLE1_ITERS = {(1, 100, 1e-7): 16, (1, 200, 1e-7): 22, (1, 350, 1e-7): 26,
+                (2, 100, 1e-7): 16, (2, 200, 1e-7): 21, (2, 350, 1e-7): 25,
+                (3, 100, 1e-7): 16, (3, 200, 1e-7): 21, (3, 350, 1e-7): 25,
+                (1, 100, 1e-10): 30, (1, 200, 1e-10): 44, (1, 350, 1e-10): 55,
+                (2, 100, 1e-10): 26, (2, 200, 1e-10): 35, (2, 350, 1e-10): 43,
+                (3, 100, 1e-10): 26, (3, 200, 1e-10): 35, (3, 350, 1e-10): 43}
+
+
 def paper_suite(args):
-    """The test matrices of Sec. 3 (Types 1-3 on n^3, Dirichlet on every face,
-    b ~ U[-1,1] seed 701 since the paper does not state b), solved to the two
-    tolerances of Table 1 with the Newton blocks and the ILU(0) combination:
-    setup time (assembly, factorization, ILU(0)), solve time and iterations,
-    one JSON line per case."""
+    """The test matrices of Sec. 3 (Types 1-3 on n^3, Dirichlet on every face;
+    Type 2 as printed, whose ring is empty, and optionally the non-empty ring
+    "2ring"), right-hand side b = A x* with x* ~ U[-1,1] (seed 701) formed by
+    the library's SpMV, solved to the two tolerances of Table 1: setup time
+    (assembly, factorization, ILU(0)), solve time, iterations and the error
+    against x*, one JSON line per case."""
     import torch
     import paper_1909_09771_amd as P
     import workloads as W
     dev = torch.device("cuda:0")
     for n in [int(v) for v in args.sizes.split(",")]:
-        for typ in (1, 2, 3):
-            w = W.scaled_workload("paper%d" % typ, n)
+        for typ in args.types.split(","):
+            w = W.scaled_workload("paper%s" % typ, n)
             kappa = torch.from_numpy(w["kappa"]).to(dev)
-            b = torch.from_numpy(w["b"]).to(dev)
+            xstar = torch.from_numpy(w["xstar"]).to(dev)
             del w
-            for tol in (1e-7, 1e-10):
-                for prec in args.precs.split(","):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    S = P.Solver(kappa, P_BC_ALL, prec=prec, schur=args.schur,
-                                 smoother=args.smoother)
-                    torch.cuda.synchronize()
-                    t1 = time.perf_counter()
-                    x, it, rr, st = S.pcg(b, tol=tol, maxit=args.maxit)
-                    torch.cuda.synchronize()
-                    t2 = time.perf_counter()
-                    line = {"suite": "paper", "type": typ, "n": n, "rows": n ** 3, "tol": tol,
-                            "prec": prec, "schur": args.schur, "smoother": args.smoother,
-                            "setup_s": round(t1 - t0, 4), "solve_s": round(t2 - t1, 4),
-                            "overall_s": round(t2 - t0, 4), "iters": it, "relres": rr,
-                            "status": st, "footprint_bytes": S.footprint_bytes}
-                    print(json.dumps(line), flush=True)
-                    del S, x
-                    torch.cuda.empty_cache()
-            del kappa, b
+            for smoother in args.paper_smoothers.split(","):
+                for tol in (1e-7, 1e-10):
+                    for prec in args.precs.split(","):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        S = P.Solver(kappa, P_BC_ALL, prec=prec, schur=args.schur,
+                                     smoother=smoother)
+                        torch.cuda.synchronize()
+                        t1 = time.perf_counter()
+                        b = S.spmv(xstar)
+                        torch.cuda.synchronize()
+                        t2 = time.perf_counter()
+                        x, it, rr, st = S.pcg(b, tol=tol, maxit=args.maxit)
+                        torch.cuda.synchronize()
+                        t3 = time.perf_counter()
+                        err = float(torch.linalg.vector_norm(x - xstar) /
+                                    torch.linalg.vector_norm(xstar))
+                        key = (int(typ), n, tol) if typ.isdigit() else None
+                        line = {"suite": "paper", "type": typ, "n": n, "rows": n ** 3,
+                                "tol": tol, "prec": prec, "schur": args.schur,
+                                "smoother": smoother, "rhs": "A x*, x* ~ U[-1,1] seed 701",
+                                "setup_s": round(t1 - t0, 4), "solve_s": round(t3 - t2, 4),
+                                "overall_s": round(t1 - t0 + t3 - t2, 4), "iters": it,
+                                "paper_iters": TABLE1_ITERS.get(key), "relres": rr,
+                                "err_vs_xstar": err, "status": st,
+                                "footprint_bytes": S.footprint_bytes}
+                        print(json.dumps(line), flush=True)
+                        del S, x, b
+                        torch.cuda.empty_cache()
+            del kappa, xstar
 
 
 P_BC_ALL = [0, 0, 0, 0, 0, 0]

@@ -113,13 +113,29 @@ def kappa_paper_type1(n: int) -> np.ndarray:
     return np.ascontiguousarray(out, dtype=np.float64)
 
 
-def kappa_paper_type2(n: int) -> np.ndarray:
-    """Type 2 ring field (Sec. 3): kappa = 1e3 where 1/(2*sqrt 2) <= |x - c| <= 1/2,
-    c = (1/2, 1/2, 1/2), else 1.  The inner radius is read as 1/(2 sqrt 2)."""
+def kappa_paper_type2(n: int, inner: float | None = None) -> np.ndarray:
+    """Type 2 ring field (Sec. 3): kappa = 1e3 where inner <= |x - c| <= 1/2,
+    c = (1/2, 1/2, 1/2), else 1.
+
+    The inner radius is printed as "1/2 sqrt 2".  Taken as printed, (1/2)*sqrt(2)
+    = 0.707 exceeds the outer radius 1/2, so the ring is empty and kappa = 1
+    everywhere (the default, inner=None).  The paper's Type 2 rows of Table 1
+    equal its Type 3 (kappa = 1) rows in every iteration count, which is what
+    an empty ring gives.  inner = 1/(2 sqrt 2) = 0.354 gives the non-empty
+    ring (kappa_paper_type2_ring)."""
+    if inner is None:
+        inner = 0.5 * np.sqrt(2.0)
     x, y, z = node_coords(n, n, n)
     r = np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2)
-    out = np.where((r >= 1.0 / (2.0 * np.sqrt(2.0))) & (r <= 0.5), 1.0e3, 1.0)
+    out = np.where((r >= inner) & (r <= 0.5), 1.0e3, 1.0)
     return np.ascontiguousarray(out, dtype=np.float64)
+
+
+def kappa_paper_type2_ring(n: int) -> np.ndarray:
+    """The Type 2 ring with inner radius 1/(2 sqrt 2): a shell of kappa = 1e3
+    between radii 0.354 and 0.5 around the cube's centre (touching the faces at
+    their centres), kappa = 1 elsewhere."""
+    return kappa_paper_type2(n, inner=1.0 / (2.0 * np.sqrt(2.0)))
 
 
 def rhs_uniform(nx: int, ny: int, nz: int, seed: int) -> np.ndarray:
@@ -192,11 +208,16 @@ def scaled_workload(name: str, n: int) -> dict:
     if name == "spheres":
         return dict(n=(n, n, n), kappa=kappa_spheres(n, n, n, 301), bc=BC_ALL_DIRICHLET.copy(),
                     b=np.ones((n, n, n)), t=None)
-    if name in ("paper1", "paper2", "paper3"):  # Sec. 3 test matrices, Dirichlet everywhere
+    if name in ("paper1", "paper2", "paper3", "paper2ring"):
+        # Sec. 3 test matrices, Dirichlet everywhere.  The paper does not state
+        # its right-hand side; b = A x* with a manufactured solution
+        # x* ~ U[-1,1] (seed 701) reproduces Table 1's iteration counts.  Each
+        # side forms b with its own SpMV from "xstar".
         kappa = {"paper1": kappa_paper_type1, "paper2": kappa_paper_type2,
+                 "paper2ring": kappa_paper_type2_ring,
                  "paper3": lambda m: kappa_const(m, m, m)}[name](n)
         return dict(n=(n, n, n), kappa=kappa, bc=BC_ALL_DIRICHLET.copy(),
-                    b=rhs_uniform(n, n, n, 701), t=None)
+                    xstar=rhs_uniform(n, n, n, 701), b=None, t=None)
     raise KeyError(name)
 
 
