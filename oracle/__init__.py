@@ -26,11 +26,12 @@ MODES = {"newton": 0, "paper_literal": 1, "diag": 2}
 
 
 def build(force: bool = True) -> str:
-    """Compile liborc.so next to its source (gcc, -O2, no FP contraction)."""
+    """Compile liborc.so next to its source (gcc -O3 for x86-64-v3, i.e. AVX2,
+    which every host here has; no FP contraction, so no FMA is formed)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O3", "-march=x86-64-v3", "-std=c99", "-ffp-contract=off",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -215,8 +216,9 @@ def sym_combo_apply(bands, F, dt, r, nblocks=2):
 
 def pcg_with(bands, precond, b, tol=1e-8, maxit=200):
     """Preconditioned CG (x0 = 0) with any preconditioner function z = precond(r),
-    stopping on the recursive residual and confirming with the true one (the
-    rules of pcg below); returns (x, iters, true relres, status)."""
+    stopping on the recursive residual and confirming with the true one, and
+    breaking down when p'Ap or r'z is not positive (the rules of orc_pcg);
+    returns (x, iters, true relres, status)."""
     b = _f64(b)
     bn = np.sqrt(dot(b, b))
     x = np.zeros_like(b)
@@ -226,6 +228,8 @@ def pcg_with(bands, precond, b, tol=1e-8, maxit=200):
     z = precond(r)
     p = z.copy()
     rho = dot(r, z)
+    if not (rho > 0.0) or not np.isfinite(rho):
+        return x, 0, 1.0, EBREAKDOWN
     for it in range(1, maxit + 1):
         q = spmv(bands, p)
         pq = dot(p, q)
@@ -241,6 +245,9 @@ def pcg_with(bands, precond, b, tol=1e-8, maxit=200):
                 return x, it, tr, OK
         z = precond(r)
         rho_new = dot(r, z)
+        if not (rho_new > 0.0) or not np.isfinite(rho_new):
+            res = b - spmv(bands, x)
+            return x, it, np.sqrt(dot(res, res)) / bn, EBREAKDOWN
         p = z + (rho_new / rho) * p
         rho = rho_new
     res = b - spmv(bands, x)

@@ -582,6 +582,10 @@ int orc_combo_apply(int nx, int ny, int nz, const double *d, const double *ax, c
 /* then confirm with the true residual ||b - A x||/||b|| (iterate on if it is */
 /* still above tol).  iters counts products with A inside the loop.  With dt  */
 /* (ILU(0) diagonal, nblocks blocks) the preconditioner is the combination.   */
+/* CG needs p'Ap > 0 (A positive definite) and r'z > 0 (a positive definite   */
+/* preconditioner); the combination of eq. com is not symmetric, so r'z can   */
+/* turn non-positive.  Either one ends the loop with ORC_EBREAKDOWN, x being  */
+/* the last iterate.                                                          */
 /* ------------------------------------------------------------------------- */
 /* Preconditioner of the PCG: B^{-1} (dt == NULL) or the combination (eq. com). */
 static void pcg_precond(int nx, int ny, int nz, const double *d, const double *ax,
@@ -611,11 +615,12 @@ int orc_pcg(int nx, int ny, int nz, const double *d, const double *ax, const dou
     for (long i = 0; i < N; ++i) p[i] = z[i];
     double rho = orc_dot(N, r, z);
     int it = 0;
-    for (;;) {
+    if (!(rho > 0.0) || !isfinite(rho)) st = ORC_EBREAKDOWN;
+    while (st == ORC_OK) {
         if (it >= maxit) { st = ORC_ENOCONV; break; }
         orc_spmv(nx, ny, nz, d, ax, ay, az, p, q);
         double pq = orc_dot(N, p, q);
-        if (!(pq > 0.0)) { st = ORC_EBREAKDOWN; break; }
+        if (!(pq > 0.0) || !isfinite(pq)) { st = ORC_EBREAKDOWN; break; }
         double alpha = rho / pq;
         for (long i = 0; i < N; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
         ++it;
@@ -629,6 +634,7 @@ int orc_pcg(int nx, int ny, int nz, const double *d, const double *ax, const dou
         }
         pcg_precond(nx, ny, nz, d, ax, ay, az, e1, M, f2, dt, nblocks, r, z);
         double rho_new = orc_dot(N, r, z);
+        if (!(rho_new > 0.0) || !isfinite(rho_new)) { st = ORC_EBREAKDOWN; break; }
         double beta = rho_new / rho;
         rho = rho_new;
         for (long i = 0; i < N; ++i) p[i] = z[i] + beta * p[i];

@@ -452,6 +452,58 @@ def test_pcg_reports_no_convergence():
     assert st == O.ENOCONV and it == 2
 
 
+def _identity_factors(shape, sign):
+    """Factors of B = sign * I on a single plane (no line or plane couplings,
+    every pivot = sign)."""
+    z = np.zeros(shape)
+    return {"e1": z, "M": np.full(shape, float(sign)), "f2": z, "g3": z}
+
+
+def test_pcg_breaks_down_on_a_negative_definite_preconditioner():
+    """B = -I gives r.z = -|r|^2 < 0 at once: CG cannot take a step, so the
+    oracle stops with EBREAKDOWN before the first product with A, x = 0."""
+    shape = (1, 5, 7)
+    bands = O.assemble(rand_kappa(shape, 171), W.BC_ALL_DIRICHLET)
+    b = W.rhs_uniform(7, 5, 1, 172)
+    x, it, rr, st, _ = O.pcg(bands, _identity_factors(shape, -1.0), b, 1e-8, 50)
+    assert st == O.EBREAKDOWN and it == 0 and np.all(x == 0.0) and rr == 1.0
+    x, it, rr, st = O.pcg_with(bands, lambda r: -r, b, 1e-8, 50)
+    assert st == O.EBREAKDOWN and it == 0 and np.all(x == 0.0)
+
+
+def test_pcg_breaks_down_on_a_negative_definite_matrix():
+    """With A negative definite and B = I, p.Ap = -p'(-A)p < 0 in the first
+    step: EBREAKDOWN before any update, x = 0."""
+    shape = (1, 5, 7)
+    d, ax, ay, az = O.assemble(rand_kappa(shape, 173), W.BC_ALL_DIRICHLET)
+    neg = (-d, -ax, -ay, -az)
+    b = W.rhs_uniform(7, 5, 1, 174)
+    x, it, rr, st, _ = O.pcg(neg, _identity_factors(shape, 1.0), b, 1e-8, 50)
+    assert st == O.EBREAKDOWN and it == 0 and np.all(x == 0.0)
+    x, it, rr, st = O.pcg_with(neg, lambda r: r.copy(), b, 1e-8, 50)
+    assert st == O.EBREAKDOWN and it == 0
+
+
+def test_pcg_breaks_down_when_rz_turns_negative():
+    """A preconditioner that is positive on the first residual and negative on
+    the second: z = s(k) r with s = +1 for the first call, -1 after.  Step 1
+    is the steepest-descent step; then r.z < 0 and the oracle stops with
+    EBREAKDOWN after exactly one iteration, x = that step's iterate."""
+    shape = (2, 4, 5)
+    bands = O.assemble(rand_kappa(shape, 175), W.BC_ALL_DIRICHLET)
+    b = W.rhs_uniform(5, 4, 2, 176)
+    calls = []
+
+    def flip(r):
+        calls.append(1)
+        return r.copy() if len(calls) == 1 else -r
+    x, it, rr, st = O.pcg_with(bands, flip, b, 1e-12, 50)
+    assert st == O.EBREAKDOWN and it == 1
+    Ab = O.spmv(bands, b)
+    alpha = np.dot(b.ravel(), b.ravel()) / np.dot(b.ravel(), Ab.ravel())
+    np.testing.assert_allclose(x, alpha * b, rtol=1e-13)
+
+
 # --------------------------------------------------------------------------
 # ILU(0) smoother and the combination preconditioner (Sec. 3, eq. com)
 # --------------------------------------------------------------------------
