@@ -36,7 +36,7 @@ typedef struct ntd_handle ntd_handle;
 #define NTD_EINVAL 1       /* bad argument: size, pointer, workspace, kappa or t not finite > 0, ... */
 #define NTD_ENOMEM 2       /* host-side allocation failed */
 #define NTD_ENOTSPD 3      /* a pivot of the factorization is not positive and finite */
-#define NTD_EBREAKDOWN 4   /* PCG: p'Ap <= 0 or not finite */
+#define NTD_EBREAKDOWN 4   /* PCG: p'Ap or r'z not positive, or not finite */
 #define NTD_ENOCONV 5      /* PCG: maxit reached before the tolerance */
 #define NTD_EHIP 6         /* a HIP runtime call failed */
 
@@ -138,8 +138,10 @@ int ntd_dot(ntd_handle *h, const double *x, const double *y, double *result, voi
  * iterate until ||r||/||b|| <= tol on the recursively updated residual and the
  * true residual ||b - A x||/||b|| confirms it.  b, x [N] device FP64.
  * *iters (HOST) = products with A taken in the loop; *relres (HOST) = final
- * true relative residual.  Returns NTD_ENOCONV after maxit iterations (x then
- * holds the last iterate) and NTD_EBREAKDOWN if p'Ap <= 0.  Synchronises. */
+ * true relative residual.  Returns NTD_ENOCONV after maxit iterations and
+ * NTD_EBREAKDOWN when p'Ap or r'z is not positive and finite (r'z can turn
+ * non-positive with the non-symmetric combination of eq. com); x then holds
+ * the last iterate.  Synchronises. */
 int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int maxit, int *iters,
                   double *relres, void *stream);
 

@@ -436,7 +436,10 @@ int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int max
         CK(ntd::launch_axpy2_norm(x, h->r, h->p, h->q, h->sc, N, h->partials, &np, s));
         CK(ntd::launch_finalize(h->partials, np, h->sc, ntd::kOpRR, s));
         if ((st = read_scalars(h, &hs, s)) != NTD_OK) return st;
-        if (hs.flag & 1) { status = NTD_EBREAKDOWN; break; }
+        if (hs.flag & (ntd::kFlagPqBreakdown | ntd::kFlagRhoBreakdown)) {
+            status = NTD_EBREAKDOWN;
+            break;
+        }
         ++it;
         if (sqrt(hs.rr) / bn <= tol) {
             double tr = 0.0;
@@ -484,7 +487,7 @@ const char *ntd_strerror(int status) {
     case NTD_EINVAL: return "invalid argument";
     case NTD_ENOMEM: return "host allocation failed";
     case NTD_ENOTSPD: return "factorization pivot not positive";
-    case NTD_EBREAKDOWN: return "PCG breakdown (p'Ap <= 0)";
+    case NTD_EBREAKDOWN: return "PCG breakdown (p'Ap or r'z not positive)";
     case NTD_ENOCONV: return "PCG did not converge within maxit";
     case NTD_EHIP: return "HIP runtime error";
     default: return "unknown status";

@@ -160,11 +160,18 @@ __global__ void __launch_bounds__(kBlock) k_batch_finalize(const BatchVec *tab, 
         *act = bn > 0.0 ? 1 : 0;
         break;
     }
-    case kOpRhoInit: sc->rho = s; break;
+    case kOpRhoInit:
+        sc->rho = s;
+        if (!(s > 0.0) || !isfinite(s)) {  // r.z of a preconditioner that is not SPD
+            sc->flag |= kFlagRhoBreakdown;
+            c.status = NTD_EBREAKDOWN;
+            *act = 0;
+        }
+        break;
     case kOpAlpha:
         sc->pq = s;
         if (!(s > 0.0) || !isfinite(s)) {
-            sc->flag |= 1;
+            sc->flag |= kFlagPqBreakdown;
             sc->alpha = 0.0;
             c.status = NTD_EBREAKDOWN;
             *act = 0;
@@ -184,8 +191,15 @@ __global__ void __launch_bounds__(kBlock) k_batch_finalize(const BatchVec *tab, 
         }
         break;
     case kOpBeta:
-        sc->beta = s / sc->rho;
-        sc->rho = s;
+        if (!(s > 0.0) || !isfinite(s)) {
+            sc->flag |= kFlagRhoBreakdown;
+            sc->beta = 0.0;
+            c.status = NTD_EBREAKDOWN;
+            *act = 0;
+        } else {
+            sc->beta = s / sc->rho;
+            sc->rho = s;
+        }
         break;
     case kBOpTrue:
         if (c.bn == 0.0) break;

@@ -16,7 +16,7 @@ struct Scalars {
     double beta;   // rho_new / rho
     double rr;     // r.r
     double result; // generic reduction result (ntd_dot, norms)
-    int flag;      // bit 0: breakdown (pq <= 0 or not finite)
+    int flag;      // kFlagPqBreakdown | kFlagRhoBreakdown
     int pad;
 };
 
@@ -29,9 +29,13 @@ enum FinalizeOp : int {
     kOpResult = 0,  // result = sum
     kOpAlpha = 1,   // pq = sum; alpha = rho / pq; flag on breakdown
     kOpRR = 2,      // rr = sum
-    kOpRhoInit = 3, // rho = sum
-    kOpBeta = 4,    // beta = sum / rho; rho = sum
+    kOpRhoInit = 3, // rho = sum; flag if not positive
+    kOpBeta = 4,    // beta = sum / rho; rho = sum; flag if sum not positive
 };
+
+// Breakdown bits of Scalars::flag.
+constexpr int kFlagPqBreakdown = 1;   // p.Ap not positive and finite
+constexpr int kFlagRhoBreakdown = 2;  // r.z not positive and finite
 
 // Device error flags (int, OR-ed by kernels).
 constexpr int kFlagBadInput = 1;   // kappa or t not finite and > 0

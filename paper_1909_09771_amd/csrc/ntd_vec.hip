@@ -133,15 +133,24 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double *__restrict__ 
     for (int q = threadIdx.x; q < nparts; q += kBlock) acc += partials[q];
     double s = block_sum(acc);
     if (threadIdx.x == 0) {
+        // CG needs p'Ap > 0 and r'z > 0; a failure sets a breakdown bit (1:
+        // p'Ap, 2: r'z) and zeroes the step, so x and r keep the last iterate.
         switch (op) {
         case kOpAlpha:
             sc->pq = s;
-            if (!(s > 0.0) || !isfinite(s)) { sc->flag |= 1; sc->alpha = 0.0; }
+            if (sc->flag & kFlagRhoBreakdown) sc->alpha = 0.0;
+            else if (!(s > 0.0) || !isfinite(s)) { sc->flag |= kFlagPqBreakdown; sc->alpha = 0.0; }
             else sc->alpha = sc->rho / s;
             break;
         case kOpRR: sc->rr = s; break;
-        case kOpRhoInit: sc->rho = s; break;
-        case kOpBeta: sc->beta = s / sc->rho; sc->rho = s; break;
+        case kOpRhoInit:
+            sc->rho = s;
+            if (!(s > 0.0) || !isfinite(s)) sc->flag |= kFlagRhoBreakdown;
+            break;
+        case kOpBeta:
+            if (!(s > 0.0) || !isfinite(s)) { sc->flag |= kFlagRhoBreakdown; sc->beta = 0.0; }
+            else { sc->beta = s / sc->rho; sc->rho = s; }
+            break;
         default: sc->result = s; break;
         }
     }
