@@ -4,7 +4,8 @@ with the FP64 oracle, entry by entry, through the C ABI.
 The batch packs every system with the elements per lane of its longest line,
 so the shorter systems below run with pass-through slots; their results are
 held to the same bars as the single-system path: apply 1e-9 (FP64, the GPU's
-own factors) and 1e-5 (MIXED) relative; PCG iterations within +-1 of the oracle
+own factors) and 1e-5 (MIXED) element by element relative to the largest
+entry of the oracle's result; PCG iterations within +-1 of the oracle
 in FP64, true relative residual <= tol.  Graph replay and eager launches must
 give bitwise identical results.
 """
@@ -31,8 +32,9 @@ def C(t):
     return t.detach().cpu().numpy()
 
 
-def rel2(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+def relelem(a, b):
+    """Largest element-wise error relative to the largest entry of b."""
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
 # (nz, ny, nx), kind; nx 33 needs 1 element per lane, 70 needs 2: the first
@@ -78,7 +80,7 @@ def test_batch_apply_parity(systems, prec, tol, schur):
     for e, (r, z) in enumerate(zip(rs, zs)):
         s = systems[e // nrhs]
         want = O.apply(O.setup(s["bands"], mode=schur), r)
-        assert rel2(z, want) <= tol, "entry %d" % e
+        assert relelem(z, want) <= tol, "entry %d" % e
     B.close()
 
 

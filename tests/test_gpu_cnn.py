@@ -8,8 +8,9 @@ changes that one activation by one unit in its last place.  Such flips are
 rare (one in ~10^4 values) and a flip moves the output through one weight of a
 432-term sum, so the prediction t agrees to 1e-3 (absolute, t is O(1))
 element-wise and 1e-5 in mean.  The gradient goes through four more bfloat16
-maps and sums over the whole grid; per layer it agrees to 1e-3 in relative
-2-norm.  Adam runs in
+maps and sums over the whole grid, so a flip moves a weight's gradient by one
+term of a sum over every voxel; per layer every element agrees to 1e-5 of the
+layer's largest gradient.  Adam runs in
 float32 against float64: 1e-5 relative plus, per step, one float32 spacing of
 the largest parameter.
 """
@@ -89,9 +90,9 @@ def test_cnn_loss_grad_parity(shape):
     offs = np.cumsum([0] + [co * 27 * ci + co for ci, co in C.LAYERS])
     for l in range(4):
         a, b = g[offs[l]:offs[l + 1]], g_o[offs[l]:offs[l + 1]]
-        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-        print("grad %s layer %d: rel 2-norm error %.2e" % (shape, l, rel))
-        assert rel <= 1e-3, (l, rel)
+        rel = np.abs(a - b).max() / np.abs(b).max()
+        print("grad %s layer %d: max element error / max |grad| %.2e" % (shape, l, rel))
+        assert rel <= 1e-5, (l, rel)
 
 
 def test_cnn_adam_parity():
