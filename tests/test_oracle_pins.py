@@ -247,6 +247,40 @@ def test_B_is_symmetric_positive_definite(shape, mode):
                 assert np.abs(E[k * nxy:(k + 1) * nxy, kk * nxy:(kk + 1) * nxy]).max() < 1e-9 * np.abs(A).max()
 
 
+def _contrast_fields(n, c, seed):
+    rng = np.random.default_rng(seed)
+    return {"subcubes": W.kappa_subcubes(n, n, n, seed, cubes=2, log10_lo=0.0, log10_hi=c),
+            "random": 10.0 ** rng.uniform(0.0, c, (n, n, n)),
+            "spheres": W.kappa_spheres(n, n, n, seed, count=6, r_lo=0.1, r_hi=0.25,
+                                       inside=10.0 ** c)}
+
+
+@pytest.mark.parametrize("mode", ["newton", "diag", "paper_literal"])
+@pytest.mark.parametrize("n", [6, 8])
+@pytest.mark.parametrize("contrast", [3, 6])
+def test_B_is_spd_at_high_contrast(contrast, n, mode):
+    """B stays symmetric positive definite on fields of contrast 1e3 and 1e6
+    (subcubes, random per-node kappa, spheres).  The spectrum of B^{-1}A is
+    one-sided as the Schur blocks imply: the diagonal block b lies above
+    P^{-1} (B <= A, lambda >= 1); the Newton block 2b - bPb lies below it
+    (B >= A, lambda <= 1) up to the level-3 filter compensation, which moves
+    the largest eigenvalue above 1 by at most about 1e-4 on these fields."""
+    for kind, kappa in _contrast_fields(n, contrast, 11).items():
+        bands = O.assemble(kappa, W.BC_ALL_DIRICHLET)
+        F = O.setup(bands, mode=mode)
+        Bi = dense_Binv(F, kappa.shape)
+        assert np.abs(Bi - Bi.T).max() <= 1e-12 * np.abs(Bi).max(), kind
+        Lc = sla.cholesky(0.5 * (Bi + Bi.T), lower=True)  # raises if not positive definite
+        if mode == "paper_literal":
+            continue
+        A = R.assemble_dense(kappa, W.BC_ALL_DIRICHLET)
+        lam = np.linalg.eigvalsh(Lc.T @ A @ Lc)   # the spectrum of B^{-1} A, symmetrically
+        if mode == "newton":
+            assert lam.min() > 0.0 and lam.max() <= 1.0 + 1e-3, (kind, lam.min(), lam.max())
+        else:
+            assert lam.min() >= 1.0 - 1e-9, (kind, lam.min(), lam.max())
+
+
 def _newton_identity(P, beta, X):
     """I - P X == (I - P beta)^2 for X = 2 beta - beta P beta (one Newton-Schulz
     step toward P^{-1} from the diagonal beta), written without X's formula."""
