@@ -62,6 +62,12 @@ def _L():
         lib.orc_line_pivots.restype = i
         lib.orc_pcg.argtypes = [i, i, i, P, P, P, P, P, P, P, P, i, P, P, d, i,
                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), P]
+        lib.orc_pcg_combo.argtypes = [i, i, i, P, P, P, P, P, P, P, P, i, i, P, P, d, i,
+                                      ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_double), P]
+        lib.orc_pcg_combo.restype = i
+        lib.orc_sym_combo_apply.argtypes = [i, i, i, P, P, P, P, P, P, P, P, i, P, P]
+        lib.orc_sym_combo_apply.restype = i
         lib.orc_ilu0.argtypes = [i, i, i, P, P, P, P, i, P]
         lib.orc_ilu0.restype = i
         lib.orc_ilu0_apply.argtypes = [i, i, i, P, P, P, P, i, P, P]
@@ -214,6 +220,20 @@ def sym_combo_apply(bands, F, dt, r, nblocks=2):
     return z2 + ilu0_apply(bands, dt, r - spmv(bands, z2), nblocks)
 
 
+def sym_combo_apply_c(bands, F, dt, r, nblocks=2):
+    """The symmetric combination's three steps in the C oracle (orc_sym_combo_apply)."""
+    d, ax, ay, az = [_f64(a) for a in bands]
+    nz, ny, nx = d.shape
+    r = _f64(r).reshape(d.shape)
+    z = np.empty_like(d)
+    st = _L().orc_sym_combo_apply(nx, ny, nz, _ptr(d), _ptr(ax), _ptr(ay), _ptr(az),
+                                  _ptr(F["e1"]), _ptr(F["M"]), _ptr(F["f2"]), _ptr(_f64(dt)),
+                                  int(nblocks), _ptr(r), _ptr(z))
+    if st != OK:
+        raise OracleError(st, "orc_sym_combo_apply")
+    return z
+
+
 def pcg_with(bands, precond, b, tol=1e-8, maxit=200):
     """Preconditioned CG (x0 = 0) with any preconditioner function z = precond(r),
     stopping on the recursive residual and confirming with the true one, and
@@ -254,9 +274,13 @@ def pcg_with(bands, precond, b, tol=1e-8, maxit=200):
     return x, maxit, np.sqrt(dot(res, res)) / bn, ENOCONV
 
 
-def pcg(bands, F, b, tol=1e-8, maxit=200, dt=None, nblocks=2):
-    """PCG with B (dt None) or with the combination of B and ILU(0) (dt given);
-    returns (x, iters, true relres, status, residual history)."""
+COMBOS = {"none": 0, "ilu0": 1, "ilu0sym": 2}
+
+
+def pcg(bands, F, b, tol=1e-8, maxit=200, dt=None, nblocks=2, smoother=None):
+    """PCG with B (dt None), with the combination of eq. com (dt given), or with
+    the symmetric combination (smoother="ilu0sym", dt given); returns (x, iters,
+    true relres, status, residual history)."""
     d, ax, ay, az = [_f64(a) for a in bands]
     nz, ny, nx = d.shape
     b = _f64(b).reshape(d.shape)
@@ -265,7 +289,9 @@ def pcg(bands, F, b, tol=1e-8, maxit=200, dt=None, nblocks=2):
     rr = ctypes.c_double(0.0)
     hist = np.zeros(maxit + 1)
     dtp = None if dt is None else _f64(dt)
-    st = _L().orc_pcg(nx, ny, nz, _ptr(d), _ptr(ax), _ptr(ay), _ptr(az), _ptr(F["e1"]),
-                      _ptr(F["M"]), _ptr(F["f2"]), _ptr(dtp), int(nblocks), _ptr(b), _ptr(x),
-                      float(tol), int(maxit), ctypes.byref(it), ctypes.byref(rr), _ptr(hist))
+    combo = COMBOS[smoother] if smoother is not None else (0 if dt is None else 1)
+    st = _L().orc_pcg_combo(nx, ny, nz, _ptr(d), _ptr(ax), _ptr(ay), _ptr(az), _ptr(F["e1"]),
+                            _ptr(F["M"]), _ptr(F["f2"]), _ptr(dtp), int(nblocks), int(combo),
+                            _ptr(b), _ptr(x), float(tol), int(maxit), ctypes.byref(it),
+                            ctypes.byref(rr), _ptr(hist))
     return x, it.value, rr.value, st, hist[: it.value]

@@ -587,21 +587,48 @@ int orc_combo_apply(int nx, int ny, int nz, const double *d, const double *ax, c
 /* turn non-positive.  Either one ends the loop with ORC_EBREAKDOWN, x being  */
 /* the last iterate.                                                          */
 /* ------------------------------------------------------------------------- */
-/* Preconditioner of the PCG: B^{-1} (dt == NULL) or the combination (eq. com). */
-static void pcg_precond(int nx, int ny, int nz, const double *d, const double *ax,
-                        const double *ay, const double *az, const double *e1, const double *M,
+/* The symmetric combination (an addition to the paper, whose eq. com is not
+ * symmetric), its three steps in order:
+ *   z1 = B_ILU^{-1} r,  z2 = z1 + B^{-1} (r - A z1),  z = z2 + B_ILU^{-1} (r - A z2). */
+int orc_sym_combo_apply(int nx, int ny, int nz, const double *d, const double *ax,
+                        const double *ay, const double *az, const double *e1, const double *M_,
                         const double *f2, const double *dt, int nblocks, const double *r,
                         double *z)
 {
-    if (dt) orc_combo_apply(nx, ny, nz, d, ax, ay, az, e1, M, f2, dt, nblocks, r, z);
+    const long N = (long)nx * ny * nz;
+    double *t = malloc(sizeof(double) * N), *u = malloc(sizeof(double) * N);
+    if (!t || !u) { free(t); free(u); return ORC_ENOMEM; }
+    orc_ilu0_apply(nx, ny, nz, ax, ay, az, dt, nblocks, r, z);      /* z = z1 */
+    orc_spmv(nx, ny, nz, d, ax, ay, az, z, t);
+    for (long p = 0; p < N; ++p) t[p] = r[p] - t[p];                 /* r - A z1 */
+    orc_apply(nx, ny, nz, e1, M_, f2, az, t, u);
+    for (long p = 0; p < N; ++p) z[p] += u[p];                       /* z = z2 */
+    orc_spmv(nx, ny, nz, d, ax, ay, az, z, t);
+    for (long p = 0; p < N; ++p) t[p] = r[p] - t[p];                 /* r - A z2 */
+    orc_ilu0_apply(nx, ny, nz, ax, ay, az, dt, nblocks, t, u);
+    for (long p = 0; p < N; ++p) z[p] += u[p];
+    free(t); free(u);
+    return ORC_OK;
+}
+
+/* Preconditioner of the PCG: B^{-1} (combo 0), the combination of eq. com
+ * (combo 1) or the symmetric combination (combo 2); dt is the ILU(0) diagonal. */
+static void pcg_precond(int nx, int ny, int nz, const double *d, const double *ax,
+                        const double *ay, const double *az, const double *e1, const double *M,
+                        const double *f2, const double *dt, int nblocks, int combo,
+                        const double *r, double *z)
+{
+    if (combo == 2) orc_sym_combo_apply(nx, ny, nz, d, ax, ay, az, e1, M, f2, dt, nblocks, r, z);
+    else if (combo == 1) orc_combo_apply(nx, ny, nz, d, ax, ay, az, e1, M, f2, dt, nblocks, r, z);
     else orc_apply(nx, ny, nz, e1, M, f2, az, r, z);
 }
 
-int orc_pcg(int nx, int ny, int nz, const double *d, const double *ax, const double *ay,
-            const double *az, const double *e1, const double *M, const double *f2,
-            const double *dt, int nblocks, const double *b, double *x, double tol, int maxit,
-            int *iters, double *relres, double *hist)
+int orc_pcg_combo(int nx, int ny, int nz, const double *d, const double *ax, const double *ay,
+                  const double *az, const double *e1, const double *M, const double *f2,
+                  const double *dt, int nblocks, int combo, const double *b, double *x,
+                  double tol, int maxit, int *iters, double *relres, double *hist)
 {
+    if (combo < 0 || combo > 2 || (combo > 0 && !dt)) return ORC_EINVAL;
     const long N = (long)nx * ny * nz;
     double *r = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N);
     double *p = malloc(sizeof(double) * N), *q = malloc(sizeof(double) * N);
@@ -611,7 +638,7 @@ int orc_pcg(int nx, int ny, int nz, const double *d, const double *ax, const dou
     for (long i = 0; i < N; ++i) { x[i] = 0.0; r[i] = b[i]; }
     *iters = 0;
     if (bn == 0.0) { *relres = 0.0; goto done; }
-    pcg_precond(nx, ny, nz, d, ax, ay, az, e1, M, f2, dt, nblocks, r, z);
+    pcg_precond(nx, ny, nz, d, ax, ay, az, e1, M, f2, dt, nblocks, combo, r, z);
     for (long i = 0; i < N; ++i) p[i] = z[i];
     double rho = orc_dot(N, r, z);
     int it = 0;
@@ -632,7 +659,7 @@ int orc_pcg(int nx, int ny, int nz, const double *d, const double *ax, const dou
             double tr = sqrt(orc_dot(N, q, q)) / bn;
             if (tr <= tol) break;
         }
-        pcg_precond(nx, ny, nz, d, ax, ay, az, e1, M, f2, dt, nblocks, r, z);
+        pcg_precond(nx, ny, nz, d, ax, ay, az, e1, M, f2, dt, nblocks, combo, r, z);
         double rho_new = orc_dot(N, r, z);
         if (!(rho_new > 0.0) || !isfinite(rho_new)) { st = ORC_EBREAKDOWN; break; }
         double beta = rho_new / rho;
@@ -646,4 +673,14 @@ int orc_pcg(int nx, int ny, int nz, const double *d, const double *ax, const dou
 done:
     free(r); free(z); free(p); free(q);
     return st;
+}
+
+/* PCG with B^{-1} (dt == NULL) or with the combination of eq. com (dt given). */
+int orc_pcg(int nx, int ny, int nz, const double *d, const double *ax, const double *ay,
+            const double *az, const double *e1, const double *M, const double *f2,
+            const double *dt, int nblocks, const double *b, double *x, double tol, int maxit,
+            int *iters, double *relres, double *hist)
+{
+    return orc_pcg_combo(nx, ny, nz, d, ax, ay, az, e1, M, f2, dt, nblocks, dt ? 1 : 0, b, x, tol,
+                         maxit, iters, relres, hist);
 }

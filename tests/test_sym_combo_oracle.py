@@ -60,3 +60,30 @@ def test_pcg_with_matches_a_dense_solve():
     x2, it2, rr2, st2 = O.pcg_with(bands, lambda r: O.apply(F, r), b, 1e-10, 200)
     x3, it3, rr3, st3, _ = O.pcg(bands, F, b, 1e-10, 200)
     assert st2 == st3 == O.OK and abs(it2 - it3) <= 1
+
+
+@pytest.mark.parametrize("mode", ["newton", "diag"])
+@pytest.mark.parametrize("name,kappa", FIELDS)
+def test_c_sym_combo_equals_the_dense_closed_form(name, kappa, mode):
+    """The C oracle's symmetric combination (orc_sym_combo_apply) against the
+    closed form built from dense B^{-1}, B_ILU^{-1} and A."""
+    bc = W.BC_ALL_DIRICHLET
+    bands, F, dt, A, Binv, C, _ = dense_ops(kappa, bc, mode)
+    I = np.eye(A.shape[0])
+    want = C @ (2 * np.linalg.inv(C) - A) @ C + (I - C @ A) @ Binv @ (I - A @ C)
+    E = np.eye(A.shape[0])
+    got = np.stack([O.sym_combo_apply_c(bands, F, dt, E[j].reshape(kappa.shape)).ravel()
+                    for j in range(A.shape[0])], axis=1)
+    assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
+
+
+def test_c_pcg_with_sym_combo_matches_dense_solve_and_python_loop():
+    kappa = FIELDS[1][1]
+    bands, F, dt, A, _, _, _ = dense_ops(kappa, W.BC_ALL_DIRICHLET, "newton")
+    b = W.rhs_uniform(*kappa.shape[::-1], 6)
+    x, it, rr, st, _ = O.pcg(bands, F, b, 1e-12, 200, dt=dt, smoother="ilu0sym")
+    assert st == O.OK and rr <= 1e-12
+    want = np.linalg.solve(A, b.ravel())
+    assert np.linalg.norm(x.ravel() - want) <= 1e-9 * np.linalg.norm(want) * np.linalg.cond(A)
+    x2, it2, rr2, st2 = O.pcg_with(bands, lambda r: O.sym_combo_apply(bands, F, dt, r), b, 1e-12, 200)
+    assert st2 == O.OK and abs(it - it2) <= 1
