@@ -134,6 +134,22 @@ int ntd_spmv(ntd_handle *h, const double *x, double *y, void *stream);
  * (bitwise reproducible run to run).  Synchronises `stream`. */
 int ntd_dot(ntd_handle *h, const double *x, const double *y, double *result, void *stream);
 
+/* ntd_dot without a handle and without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  *result (DEVICE, one double) =
+ * x . y over n entries (x, y [n] device FP64), in the same summation order as
+ * ntd_dot, so the two agree bitwise on the same vectors.  Stream-ordered and
+ * asynchronous (nothing synchronises), so it can be captured.
+ * Scratch: a fixed static device array per GPU (2048 block partial sums and
+ * one 64-byte scalar record, 16.4 KiB), held until the process ends; its use
+ * does not grow with n.  n must lie in [0, NTD_DOT_NOALLOC_MAX_N], else
+ * NTD_EINVAL.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams, or two host threads) race and must be
+ * ordered by the caller.  The current device must be the device of x, y,
+ * result and stream.  Allocates nothing; returns NTD_EHIP if a launch fails. */
+#define NTD_DOT_NOALLOC_MAX_N (1LL << 50)
+int ntd_dot_noalloc(const double *x, const double *y, long long n, double *result, void *stream);
+
 /* Preconditioned CG for A x = b (Sec. 1; stopping rule of Sec. 3): x0 = 0,
  * iterate until ||r||/||b|| <= tol on the recursively updated residual and the
  * true residual ||b - A x||/||b|| confirms it.  b, x [N] device FP64.

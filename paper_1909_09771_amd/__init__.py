@@ -58,6 +58,8 @@ def lib() -> ctypes.CDLL:
         L.ntd_spmv.restype = I
         L.ntd_dot.argtypes = [P, P, P, ctypes.POINTER(D), P]
         L.ntd_dot.restype = I
+        L.ntd_dot_noalloc.argtypes = [P, P, ctypes.c_longlong, P, P]
+        L.ntd_dot_noalloc.restype = I
         L.ntd_pcg_solve.argtypes = [P, P, P, D, I, ctypes.POINTER(I), ctypes.POINTER(D), P]
         L.ntd_pcg_solve.restype = I
         L.ntd_export.argtypes = [P, I, P, P]

@@ -183,3 +183,17 @@ def test_storage_is_linear_in_the_unknowns(L, prec, smoother):
     assert abs(b / a - 2.0) <= 0.01 and abs(c / b - 2.0) <= 0.01
     per = [L.ntd_workspace_bytes(n, n, n, prec, smoother) / n ** 3 for n in (32, 64, 128, 256)]
     assert all(x >= y for x, y in zip(per, per[1:])) and per[-1] <= 260
+
+
+def test_dot_noalloc_rejects_bad_arguments_on_the_host(L):
+    """Argument checks happen before any HIP call, so they run without a GPU."""
+    P = ctypes.c_void_p
+    L.ntd_dot_noalloc.argtypes = [P, P, ctypes.c_longlong, P, P]
+    L.ntd_dot_noalloc.restype = ctypes.c_int
+    buf = ctypes.create_string_buffer(64)
+    p = ctypes.cast(buf, P)
+    assert L.ntd_dot_noalloc(None, p, 4, p, None) == 1
+    assert L.ntd_dot_noalloc(p, None, 4, p, None) == 1
+    assert L.ntd_dot_noalloc(p, p, 4, None, None) == 1
+    assert L.ntd_dot_noalloc(p, p, -1, p, None) == 1
+    assert L.ntd_dot_noalloc(p, p, (1 << 50) + 1, p, None) == 1
