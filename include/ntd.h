@@ -161,6 +161,12 @@ int ntd_dot_noalloc(const double *x, const double *y, long long n, double *resul
 int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int maxit, int *iters,
                   double *relres, void *stream);
 
+/* ntd_pcg_solve that also records the recursively updated relative residual
+ * ||r||/||b|| after every iteration: hist (HOST, maxit doubles, may be NULL)
+ * receives entries 0..*iters-1. */
+int ntd_pcg_solve_history(ntd_handle *h, const double *b, double *x, double tol, int maxit,
+                          int *iters, double *relres, double *hist, void *stream);
+
 /* Copy an internal array of the handle into dst ([N] device FP64), for tests
  * and diagnostics.  which: 0..3 = bands d, ax, ay, az of A; 4 = e1 (x-band of
  * the line blocks T); 5 = 1/pivot of T; 6 = f2 (y-band of the plane blocks P);
@@ -243,6 +249,14 @@ int ntd_batch_pcg_solve(ntd_batch *b, const double *const *rhs, double *const *x
                         int maxit, int flags, int *iters, double *relres, int *status,
                         void *stream);
 
+/* Statistics of the batch's last ntd_batch_pcg_solve (HOST outputs): passes =
+ * runs of iterations between host checks of the entries' active flags;
+ * gap_ms = time the stream spent between the end of a run and the start of
+ * the next (the host's read of the flags and its decision), summed over the
+ * solve; solve_ms = the iterations' time from the first run to the end, both
+ * measured with HIP events on the solve's stream. */
+int ntd_batch_solve_stats(const ntd_batch *b, int *passes, double *gap_ms, double *solve_ms);
+
 /* Device bytes the batch keeps in use inside its workspace. */
 size_t ntd_batch_footprint_bytes(const ntd_batch *b);
 
@@ -256,6 +270,22 @@ size_t ntd_batch_footprint_bytes(const ntd_batch *b);
  * reductions are fixed-order for a given count).  Discards a captured
  * iteration graph.  Synchronises `stream`; must not overlap a solve. */
 int ntd_batch_tune(ntd_batch *b, int *gx, void *stream);
+
+/* Right-hand sides per wavefront pair in the batch's line sweeps.  nr = 1
+ * (the default): one wavefront pair per right-hand side, each reading its
+ * system's line records.  nr = 2 or 4: one pair runs nr right-hand sides of one
+ * system through the same chain and reads each line record once for all of
+ * them (nr must divide nrhs; nr = 2 for lines of up to 256 points in MIXED and
+ * 128 in FP64, nr = 4 for up to 128 in MIXED and 64 in FP64).  Results are the
+ * same operations as with nr = 1 (bitwise).  Returns NTD_EINVAL for an
+ * unsupported nr.  Discards a captured iteration graph if nr changes. */
+int ntd_batch_set_sweep_group(ntd_batch *b, int nr);
+
+/* Autotune the line-sweep shape: time one batched sweep (on zero right-hand
+ * sides) for every supported right-hand sides per wavefront pair (1, 2, 4) and
+ * keep the fastest; *nr (HOST) receives it.  Overwrites the batch's CG vectors
+ * and packed right-hand sides.  Synchronises `stream`; must not overlap a solve. */
+int ntd_batch_tune_sweeps(ntd_batch *b, int *nr, void *stream);
 
 /* Release the host-side state of the batch (not the caller's workspace). */
 int ntd_batch_destroy(ntd_batch *b);

@@ -62,6 +62,9 @@ def lib() -> ctypes.CDLL:
         L.ntd_dot_noalloc.restype = I
         L.ntd_pcg_solve.argtypes = [P, P, P, D, I, ctypes.POINTER(I), ctypes.POINTER(D), P]
         L.ntd_pcg_solve.restype = I
+        L.ntd_pcg_solve_history.argtypes = [P, P, P, D, I, ctypes.POINTER(I), ctypes.POINTER(D),
+                                            ctypes.POINTER(D), P]
+        L.ntd_pcg_solve_history.restype = I
         L.ntd_export.argtypes = [P, I, P, P]
         L.ntd_export.restype = I
         L.ntd_load_factors.argtypes = [P, P, P, P, P]
@@ -87,6 +90,13 @@ def lib() -> ctypes.CDLL:
         L.ntd_batch_pcg_solve.restype = I
         L.ntd_batch_tune.argtypes = [P, ctypes.POINTER(I), P]
         L.ntd_batch_tune.restype = I
+        L.ntd_batch_set_sweep_group.argtypes = [P, I]
+        L.ntd_batch_set_sweep_group.restype = I
+        L.ntd_batch_tune_sweeps.argtypes = [P, ctypes.POINTER(I), P]
+        L.ntd_batch_tune_sweeps.restype = I
+        L.ntd_batch_solve_stats.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(D),
+                                            ctypes.POINTER(D)]
+        L.ntd_batch_solve_stats.restype = I
         L.ntd_batch_footprint_bytes.argtypes = [P]
         L.ntd_batch_footprint_bytes.restype = Z
         L.ntd_batch_destroy.argtypes = [P]
@@ -231,6 +241,23 @@ class Solver:
         if st not in (OK, ENOCONV, EBREAKDOWN):
             raise NTDError(st, "ntd_pcg_solve")
         return x, it.value, rr.value, st
+
+    def pcg_history(self, b: torch.Tensor, tol: float = 1e-8, maxit: int = 200,
+                    x: torch.Tensor | None = None):
+        """As pcg, plus the recursive relative residual after every iteration:
+        returns (x, iterations, true relative residual, status, history)."""
+        _check_vec(b, self.shape, self.device, "b")
+        x = torch.empty_like(b) if x is None else x
+        _check_vec(x, self.shape, self.device, "x")
+        it = ctypes.c_int(0)
+        rr = ctypes.c_double(0.0)
+        hist = (ctypes.c_double * max(int(maxit), 1))()
+        st = lib().ntd_pcg_solve_history(self._h, _dptr(b), _dptr(x), float(tol), int(maxit),
+                                         ctypes.byref(it), ctypes.byref(rr), hist,
+                                         _stream_ptr(self.device))
+        if st not in (OK, ENOCONV, EBREAKDOWN):
+            raise NTDError(st, "ntd_pcg_solve_history")
+        return x, it.value, rr.value, st, list(hist[: it.value])
 
     # -- inspection ---------------------------------------------------------
     def export(self, which: str) -> torch.Tensor:
@@ -381,6 +408,32 @@ class Batch:
         if st != OK:
             raise NTDError(st, "ntd_batch_tune")
         return gx.value
+
+    def set_sweep_group(self, nr: int):
+        """Right-hand sides per wavefront pair in the line sweeps (1, 2 or 4;
+        ntd_batch_set_sweep_group)."""
+        st = lib().ntd_batch_set_sweep_group(self._h, int(nr))
+        if st != OK:
+            raise NTDError(st, "ntd_batch_set_sweep_group")
+
+    def solve_stats(self):
+        """(passes, gap_ms, solve_ms) of the last pcg: host checks, the stream's
+        idle time between runs of iterations, and the iterations' total time."""
+        n, g, t = ctypes.c_int(0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+        st = lib().ntd_batch_solve_stats(self._h, ctypes.byref(n), ctypes.byref(g),
+                                         ctypes.byref(t))
+        if st != OK:
+            raise NTDError(st, "ntd_batch_solve_stats")
+        return n.value, g.value, t.value
+
+    def tune_sweeps(self) -> int:
+        """Autotune the right-hand sides per wavefront pair of the line sweeps
+        (ntd_batch_tune_sweeps); returns the choice."""
+        nr = ctypes.c_int(0)
+        st = lib().ntd_batch_tune_sweeps(self._h, ctypes.byref(nr), _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_batch_tune_sweeps")
+        return nr.value
 
     @property
     def footprint_bytes(self) -> int:

@@ -406,6 +406,11 @@ int ntd_dot(ntd_handle *h, const double *x, const double *y, double *result, voi
 
 int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int maxit, int *iters,
                   double *relres, void *stream) {
+    return ntd_pcg_solve_history(h, b, x, tol, maxit, iters, relres, nullptr, stream);
+}
+
+int ntd_pcg_solve_history(ntd_handle *h, const double *b, double *x, double tol, int maxit,
+                          int *iters, double *relres, double *hist, void *stream) {
     if (!h || !b || !x || b == x || !iters || !relres) return NTD_EINVAL;
     if (!(tol > 0.0) || maxit < 1) return NTD_EINVAL;
     hipStream_t s = S(stream);
@@ -441,6 +446,7 @@ int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int max
             break;
         }
         ++it;
+        if (hist) hist[it - 1] = sqrt(hs.rr) / bn;
         if (sqrt(hs.rr) / bn <= tol) {
             double tr = 0.0;
             if ((st = true_relres(h, b, x, bn, &tr, s)) != NTD_OK) return st;

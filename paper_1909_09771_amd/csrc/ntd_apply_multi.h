@@ -1,0 +1,485 @@
+// ntd_apply_multi.h -- the batched sweeps with several right-hand sides of one
+// system per wavefront.
+//
+// In a batch every right-hand side of a system reads the same line records.
+// With one right-hand side per wavefront each of them fetches every record
+// again, and the batched sweeps become bound by that traffic.  Here one
+// wavefront pair runs NR right-hand sides of one system (and level-3 half)
+// through the same chain: each line step loads the line's record once and
+// runs NR independent twisted solves with it, interleaved, so the record is
+// read once per NR right-hand sides and the NR dependency chains fill each
+// other's latency.  The steps, the twists and the memory layouts are those of
+// ntd_apply.h.
+#pragma once
+
+#include "ntd_apply.h"
+
+namespace ntd {
+
+namespace {
+
+// Inputs of one line step for NR right-hand sides: the shared coefficients,
+// couplings and multipliers, and three per-right-hand-side lines (their use
+// depends on the sweep: see the policies below).
+template <typename T, int EPL, int NR>
+struct LineInM {
+    T c0[EPL], c1[EPL], c2[EPL];  // 1/M, a, u
+    T f[EPL];                     // y-coupling to the chain predecessor
+    T g[EPL], g2[EPL];            // z-couplings (level 3)
+    T mul[kRecMul];
+    double mvj, cpj, cnj;
+    T q0[NR][EPL], q1[NR][EPL], q2[NR][EPL];
+};
+
+template <typename T, int EPL, int NR>
+struct RecFmtM {
+    using Ty = T;
+    static constexpr int kEPL = EPL;
+    static constexpr int kNR = NR;
+    using R = RecFmt<T, EPL>;
+    rsrc_t rec;
+    rsrc_t W[NR];  // lower-sweep results of the plane, one buffer per right-hand side
+    unsigned vA, vM;
+    __device__ RecFmtM() {
+        const unsigned lane = threadIdx.x & 63;
+        vA = lane * EPL * (unsigned)sizeof(T);
+        vM = R::kMul + lane * kRecMul * (unsigned)sizeof(T);
+    }
+    __device__ void load_coef(int m, LineInM<T, EPL, NR> &in) const {
+        const unsigned so = (unsigned)m * R::kRec;
+        vload(rec, vA + kRecMv * R::kArr, so, in.c0);
+        vload(rec, vA + kRecA * R::kArr, so, in.c1);
+        vload(rec, vA + kRecU * R::kArr, so, in.c2);
+        vload(rec, vM, so, in.mul);
+        double tw[2];
+        vload(rec, R::kTw, so, tw);
+        in.mvj = tw[0];
+        in.cpj = tw[1];
+        in.cnj = bload((double *)nullptr, rec, R::kTw + 16u, so);
+    }
+    __device__ void load_fc(int m, bool up, T (&f)[EPL]) const {
+        vload(rec, vA + (up ? kRecFup : kRecFdn) * R::kArr, (unsigned)m * R::kRec, f);
+    }
+    __device__ void load_w(int m, T (&w)[NR][EPL]) const {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) vload(W[q], vA, (unsigned)m * R::kLine, w[q]);
+    }
+    __device__ void store_w(int m, int q, const T (&w)[EPL]) const {
+        vstore(W[q], vA, (unsigned)m * R::kLine, w);
+    }
+    __device__ void solve(const LineInM<T, EPL, NR> &in, const T (&y)[EPL], T (&x)[EPL]) const {
+        solve_rec(in.c1, in.c0, in.c2, in.mul, in.mvj, in.cpj, in.cnj, y, x);
+    }
+};
+
+// Lower level-3 step of plane k for NR right-hand sides: rhs_q = r_q - g z_q(kn).
+template <typename T, int EPL, int NR, bool HAS>
+struct PolLowerM {
+    rsrc_t rp[NR], Zn[NR], Zk[NR];
+    unsigned vA, vG;
+    __device__ void load_rhs(int m, const RecFmtM<T, EPL, NR> &F, LineInM<T, EPL, NR> &in) const {
+        constexpr unsigned kLine = RecFmt<T, EPL>::kLine;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) vload(rp[q], vA, (unsigned)m * kLine, in.q2[q]);
+        if constexpr (HAS) {
+            vload(F.rec, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.g);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) vload(Zn[q], vA, (unsigned)m * kLine, in.q1[q]);
+        }
+    }
+    __device__ T rhs(const LineInM<T, EPL, NR> &in, int q, int s) const {
+        if constexpr (HAS) return fmad(-in.g[s], in.q1[q][s], in.q2[q][s]);
+        else return in.q2[q][s];
+    }
+    __device__ void load_out(int, const RecFmtM<T, EPL, NR> &, LineInM<T, EPL, NR> &) const {}
+    __device__ void out(int m, int q, const T (&x)[EPL], const LineInM<T, EPL, NR> &) {
+        vstore(Zk[q], vA, (unsigned)m * RecFmt<T, EPL>::kLine, x);
+    }
+};
+
+// The twist plane for NR right-hand sides.
+template <typename T, int EPL, int NR>
+struct PolTwistM {
+    rsrc_t rp[NR], Zlo[NR], Zhi[NR], Zk[NR];
+    unsigned vA, vGdn, vGup;
+    bool lo_nb, hi_nb;
+    __device__ void load_rhs(int m, const RecFmtM<T, EPL, NR> &F, LineInM<T, EPL, NR> &in) const {
+        constexpr unsigned kLine = RecFmt<T, EPL>::kLine;
+        const unsigned so = (unsigned)m * RecFmt<T, EPL>::kRec;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) vload(rp[q], vA, (unsigned)m * kLine, in.q2[q]);
+        if (lo_nb) {
+            vload(F.rec, vGdn, so, in.g);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) vload(Zlo[q], vA, (unsigned)m * kLine, in.q1[q]);
+        } else {
+            zero_line(in.g);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) zero_line(in.q1[q]);
+        }
+        if (hi_nb) {
+            vload(F.rec, vGup, so, in.g2);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) vload(Zhi[q], vA, (unsigned)m * kLine, in.q0[q]);
+        } else {
+            zero_line(in.g2);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) zero_line(in.q0[q]);
+        }
+    }
+    __device__ T rhs(const LineInM<T, EPL, NR> &in, int q, int s) const {
+        return fmad(-in.g2[s], in.q0[q][s], fmad(-in.g[s], in.q1[q][s], in.q2[q][s]));
+    }
+    __device__ void load_out(int, const RecFmtM<T, EPL, NR> &, LineInM<T, EPL, NR> &) const {}
+    __device__ void out(int m, int q, const T (&x)[EPL], const LineInM<T, EPL, NR> &) {
+        vstore(Zk[q], vA, (unsigned)m * RecFmt<T, EPL>::kLine, x);
+    }
+};
+
+// Upper level-3 step of plane k for NR right-hand sides: c_q = Pt_k^{-1}(g x_q(kn)),
+// x_q(k) = z_q(k) - c_q over Z_q.  q0 carries the level-2 lower result (load_w).
+template <typename T, int EPL, int NR>
+struct PolUpperM {
+    rsrc_t Zn[NR], Zk[NR];
+    unsigned vA, vG;
+    __device__ void load_rhs(int m, const RecFmtM<T, EPL, NR> &F, LineInM<T, EPL, NR> &in) const {
+        vload(F.rec, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.g);
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+            vload(Zn[q], vA, (unsigned)m * RecFmt<T, EPL>::kLine, in.q1[q]);
+    }
+    __device__ T rhs(const LineInM<T, EPL, NR> &in, int q, int s) const {
+        return in.g[s] * in.q1[q][s];
+    }
+    __device__ void load_out(int m, const RecFmtM<T, EPL, NR> &, LineInM<T, EPL, NR> &in) const {
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+            vload(Zk[q], vA, (unsigned)m * RecFmt<T, EPL>::kLine, in.q2[q]);
+    }
+    __device__ void out(int m, int q, const T (&c)[EPL], const LineInM<T, EPL, NR> &in) {
+        T xv[EPL];
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) xv[s] = in.q2[q][s] - c[s];
+        vstore(Zk[q], vA, (unsigned)m * RecFmt<T, EPL>::kLine, xv);
+    }
+};
+
+// plane_solve (ntd_sweep.h) for NR right-hand sides: the same two half chains
+// and twist line, each step solving the NR lines of the step's line index with
+// one set of coefficients; q0 carries the level-2 lower results into the upper
+// steps.  lds holds 2 * 64 * EPL * NR values.
+template <int DEPTH, class Fmt, class Pol>
+__device__ void plane_solve_m(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty *lds) {
+    using T = typename Fmt::Ty;
+    constexpr int EPL = Fmt::kEPL;
+    constexpr int NR = Fmt::kNR;
+    using In = LineInM<T, EPL, NR>;
+    static_assert(DEPTH == 1 || DEPTH == 2, "prefetch depth");
+    const int wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int j2 = (ny - 1) / 2;
+    T y[NR][EPL], w[NR][EPL], prev[NR][EPL], fhi[EPL];
+    In A, B;
+    [[maybe_unused]] In C;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) zero_line(prev[q]);
+    auto L2 = [&](int q, int half, int s) -> T & {  // LDS slot of a half's line
+        return lds[((q * 2 + half) * 64 + lane) * EPL + s];
+    };
+
+    auto load_lower = [&](int m, bool up, In &in) {
+        pol.load_rhs(m, fmt, in);
+        fmt.load_fc(m, up, in.f);
+        fmt.load_coef(m, in);
+    };
+    auto load_upper = [&](int m, bool up, In &in) {
+        fmt.load_w(m, in.q0);
+        fmt.load_fc(m, up, in.f);
+        fmt.load_coef(m, in);
+        pol.load_out(m, fmt, in);
+    };
+    auto lower_step = [&](int m, const In &in) {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+            for (int s = 0; s < EPL; ++s) y[q][s] = pol.rhs(in, q, s) - in.f[s] * prev[q][s];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) fmt.solve(in, y[q], w[q]);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            fmt.store_w(m, q, w[q]);
+#pragma unroll
+            for (int s = 0; s < EPL; ++s) prev[q][s] = w[q][s];
+        }
+    };
+    auto upper_step = [&](int m, const In &in) {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+            for (int s = 0; s < EPL; ++s) y[q][s] = in.f[s] * prev[q][s];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) fmt.solve(in, y[q], w[q]);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+#pragma unroll
+            for (int s = 0; s < EPL; ++s) w[q][s] = in.q0[q][s] - w[q][s];
+            pol.out(m, q, w[q], in);
+#pragma unroll
+            for (int s = 0; s < EPL; ++s) prev[q][s] = w[q][s];
+        }
+    };
+    auto chain = [&](int count, bool tail, bool pre, auto &&load, auto &&step) {
+        const int nl = count + (tail ? 1 : 0);
+        if (nl <= 0) return;
+        const int last = nl - 1;
+        auto cl = [last](int i) { return i < last ? i : last; };
+        if (!pre) load(0, A);
+        if constexpr (DEPTH == 2) {
+            __builtin_amdgcn_sched_barrier(0);
+            load(cl(1), B);
+            __builtin_amdgcn_sched_barrier(0);
+            int i = 0;
+            for (; i + 2 < count; i += 3) {
+                load(cl(i + 2), C);
+                step(i, A);
+                load(cl(i + 3), A);
+                step(i + 1, B);
+                load(cl(i + 4), B);
+                step(i + 2, C);
+            }
+            const int rest = count - i;
+            if (rest >= 1) {
+                if (i + 2 < nl) load(i + 2, C);
+                step(i, A);
+            }
+            if (rest == 2) step(i + 1, B);
+            if (tail) {
+                if (rest == 1) A = B;
+                else if (rest == 2) A = C;
+            }
+        } else {
+            __builtin_amdgcn_sched_barrier(0);
+            int i = 0;
+            for (; i + 1 < count; i += 2) {
+                load(cl(i + 1), B);
+                step(i, A);
+                load(cl(i + 2), A);
+                step(i + 1, B);
+            }
+            if (i < count) {
+                if (i + 1 < nl) load(i + 1, B);
+                step(i, A);
+                if (tail) A = B;
+            }
+        }
+    };
+
+    if (wv == 0) {
+        chain(j2, true, false, [&](int i, In &in) { load_lower(i, false, in); },
+              [&](int i, const In &in) { lower_step(i, in); });
+        pol.load_out(j2, fmt, A);
+        fmt.load_fc(j2, true, fhi);
+    } else if (wv == 1) {
+        chain(ny - 1 - j2, false, false, [&](int i, In &in) { load_lower(ny - 1 - i, true, in); },
+              [&](int i, const In &in) { lower_step(ny - 1 - i, in); });
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+            for (int s = 0; s < EPL; ++s) L2(q, 1, s) = prev[q][s];
+        if (j2 + 1 < ny) load_upper(j2 + 1, false, A);
+    }
+    __syncthreads();
+    if (wv == 0) {  // the twist line takes both neighbours
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+            for (int s = 0; s < EPL; ++s)
+                y[q][s] = pol.rhs(A, q, s) - A.f[s] * prev[q][s] - fhi[s] * L2(q, 1, s);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) fmt.solve(A, y[q], w[q]);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            pol.out(j2, q, w[q], A);
+#pragma unroll
+            for (int s = 0; s < EPL; ++s) {
+                prev[q][s] = w[q][s];
+                L2(q, 0, s) = w[q][s];
+            }
+        }
+        if (j2 > 0) load_upper(j2 - 1, true, A);
+    }
+    __syncthreads();
+    if (wv == 1) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+            for (int s = 0; s < EPL; ++s) prev[q][s] = L2(q, 0, s);
+        chain(ny - 1 - j2, false, true, [&](int i, In &in) { load_upper(j2 + 1 + i, false, in); },
+              [&](int i, const In &in) { upper_step(j2 + 1 + i, in); });
+    } else if (wv == 0) {
+        chain(j2, false, true, [&](int i, In &in) { load_upper(j2 - 1 - i, true, in); },
+              [&](int i, const In &in) { upper_step(j2 - 1 - i, in); });
+    }
+}
+
+// Prefetch depth: two lines ahead while three input buffers stay small.
+template <typename T, int EPL, int NR>
+constexpr int kApplyDepthM = (sizeof(T) * EPL * NR <= 32) ? 2 : 1;
+
+template <typename T, int EPL, int NR>
+__device__ __forceinline__ RecFmtM<T, EPL, NR> rec_fmt_m(const ApplyArgs<T> (&a)[NR], int k) {
+    RecFmtM<T, EPL, NR> F;
+    F.rec = make_rsrc((const char *)a[0].rec + (size_t)k * a[0].ny * RecFmt<T, EPL>::kRec);
+    return F;
+}
+
+template <typename T, int EPL, int NR, bool HAS>
+__device__ __forceinline__ void lower_plane_m(const ApplyArgs<T> (&a)[NR], int k, int kn, T *lds) {
+    constexpr unsigned kArr = RecFmt<T, EPL>::kArr;
+    const int ny = a[0].ny;
+    PolLowerM<T, EPL, NR, HAS> pol;
+    RecFmtM<T, EPL, NR> F = rec_fmt_m<T, EPL, NR>(a, k);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        pol.rp[q] = plane_rsrc<T, EPL>(a[q].rp, k, ny);
+        pol.Zk[q] = plane_rsrc<T, EPL>(a[q].Z, k, ny);
+        pol.Zn[q] = plane_rsrc<T, EPL>(a[q].Z, HAS ? kn : k, ny);
+        F.W[q] = pol.Zk[q];
+    }
+    pol.vA = F.vA;
+    pol.vG = F.vA + (kn < k ? kRecGdn : kRecGup) * kArr;
+    plane_solve_m<kApplyDepthM<T, EPL, NR>>(ny, F, pol, lds);
+}
+
+template <typename T, int EPL, int NR>
+__device__ __forceinline__ void apply_lower_m(const ApplyArgs<T> (&a)[NR], int h, T *lds) {
+    const int nz = a[0].nz, j3 = (nz - 1) / 2;
+    const int dk = h == 0 ? 1 : -1;
+    const int k0 = h == 0 ? 0 : nz - 1;
+    if (h == 0 ? k0 >= j3 : k0 <= j3) return;
+    lower_plane_m<T, EPL, NR, false>(a, k0, k0, lds);
+    for (int k = k0 + dk; h == 0 ? k < j3 : k > j3; k += dk)
+        lower_plane_m<T, EPL, NR, true>(a, k, k - dk, lds);
+}
+
+template <typename T, int EPL, int NR>
+__device__ __forceinline__ void apply_twist_m(const ApplyArgs<T> (&a)[NR], T *lds) {
+    constexpr unsigned kArr = RecFmt<T, EPL>::kArr;
+    const int ny = a[0].ny, nz = a[0].nz, k = (nz - 1) / 2;
+    PolTwistM<T, EPL, NR> pol;
+    RecFmtM<T, EPL, NR> F = rec_fmt_m<T, EPL, NR>(a, k);
+    pol.lo_nb = k > 0;
+    pol.hi_nb = k < nz - 1;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        pol.rp[q] = plane_rsrc<T, EPL>(a[q].rp, k, ny);
+        pol.Zk[q] = plane_rsrc<T, EPL>(a[q].Z, k, ny);
+        pol.Zlo[q] = plane_rsrc<T, EPL>(a[q].Z, pol.lo_nb ? k - 1 : k, ny);
+        pol.Zhi[q] = plane_rsrc<T, EPL>(a[q].Z, pol.hi_nb ? k + 1 : k, ny);
+        F.W[q] = pol.Zk[q];
+    }
+    pol.vA = F.vA;
+    pol.vGdn = F.vA + kRecGdn * kArr;
+    pol.vGup = F.vA + kRecGup * kArr;
+    plane_solve_m<kApplyDepthM<T, EPL, NR>>(ny, F, pol, lds);
+}
+
+template <typename T, int EPL, int NR>
+__device__ __forceinline__ void apply_upper_m(const ApplyArgs<T> (&a)[NR], int h, T *lds) {
+    constexpr unsigned kArr = RecFmt<T, EPL>::kArr;
+    const int ny = a[0].ny, nz = a[0].nz, j3 = (nz - 1) / 2;
+    const int dk = h == 0 ? -1 : 1;
+    for (int k = j3 + dk; k >= 0 && k < nz; k += dk) {
+        const int kn = k - dk;
+        PolUpperM<T, EPL, NR> pol;
+        RecFmtM<T, EPL, NR> F = rec_fmt_m<T, EPL, NR>(a, k);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            pol.Zk[q] = plane_rsrc<T, EPL>(a[q].Z, k, ny);
+            pol.Zn[q] = plane_rsrc<T, EPL>(a[q].Z, kn, ny);
+            F.W[q] = make_rsrc(a[q].scratch + (size_t)h * ny * 64 * EPL);
+        }
+        pol.vA = F.vA;
+        pol.vG = F.vA + (kn < k ? kRecGdn : kRecGup) * kArr;
+        plane_solve_m<kApplyDepthM<T, EPL, NR>>(ny, F, pol, lds);
+    }
+}
+
+// Workgroup w runs right-hand sides q0..q0+NR-1 of system s, level-3 half h
+// (halves = 2), or the twist plane (halves = 1): group g = w / halves with
+// g = s * (nrhs / NR) + (q0 / NR).  The group's entries are s*nrhs + q0 + r.
+// The block returns when none of its entries is active; inactive entries of a
+// partly active group are swept too (their buffers are their own and their
+// results unused).
+template <typename T, int NR>
+__device__ __forceinline__ bool multi_slot(const ApplyArgs<T> *tab, const int *active, int count,
+                                           int nrhs, int halves, ApplyArgs<T> (&a)[NR], int &h) {
+    const int groups_per_sys = nrhs / NR;
+    const int g = blockIdx.x / halves;
+    h = blockIdx.x % halves;
+    if (g >= count * groups_per_sys) return false;
+    const int e0 = (g / groups_per_sys) * nrhs + (g % groups_per_sys) * NR;
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) any = any || entry_active(active, e0 + q);
+    if (!any) return false;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) a[q] = load_uniform(tab + e0 + q);
+    return true;
+}
+
+template <typename T, int EPL, int NR>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_lower_bm(const ApplyArgs<T> *tab,
+                                                                  const int *active, int count,
+                                                                  int nrhs) {
+    __shared__ T lds[2 * 64 * EPL * NR];
+    ApplyArgs<T> a[NR];
+    int h;
+    if (!multi_slot<T, NR>(tab, active, count, nrhs, 2, a, h)) return;
+    apply_lower_m<T, EPL, NR>(a, h, lds);
+}
+template <typename T, int EPL, int NR>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_twist_bm(const ApplyArgs<T> *tab,
+                                                                  const int *active, int count,
+                                                                  int nrhs) {
+    __shared__ T lds[2 * 64 * EPL * NR];
+    ApplyArgs<T> a[NR];
+    int h;
+    if (!multi_slot<T, NR>(tab, active, count, nrhs, 1, a, h)) return;
+    apply_twist_m<T, EPL, NR>(a, lds);
+}
+template <typename T, int EPL, int NR>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_upper_bm(const ApplyArgs<T> *tab,
+                                                                  const int *active, int count,
+                                                                  int nrhs) {
+    __shared__ T lds[2 * 64 * EPL * NR];
+    ApplyArgs<T> a[NR];
+    int h;
+    if (!multi_slot<T, NR>(tab, active, count, nrhs, 2, a, h)) return;
+    apply_upper_m<T, EPL, NR>(a, h, lds);
+}
+
+// The sweeps of a batch with NR right-hand sides per wavefront pair (nrhs a
+// multiple of NR), as three launches; ev (optional, 4 events) brackets them.
+template <typename T, int EPL, int NR>
+hipError_t apply_batch_multi_impl(const ApplyArgs<T> *tab, const int *active, int count, int nrhs,
+                                  hipStream_t s, hipEvent_t *ev) {
+    const unsigned groups = (unsigned)(count * (nrhs / NR));
+    if (ev) (void)hipEventRecord(ev[0], s);
+    hipLaunchKernelGGL((k_apply_lower_bm<T, EPL, NR>), dim3(2 * groups), dim3(kApplyThreads), 0, s,
+                       tab, active, count, nrhs);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    hipLaunchKernelGGL((k_apply_twist_bm<T, EPL, NR>), dim3(groups), dim3(kApplyThreads), 0, s,
+                       tab, active, count, nrhs);
+    if (ev) (void)hipEventRecord(ev[2], s);
+    hipLaunchKernelGGL((k_apply_upper_bm<T, EPL, NR>), dim3(2 * groups), dim3(kApplyThreads), 0, s,
+                       tab, active, count, nrhs);
+    if (ev) (void)hipEventRecord(ev[3], s);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+}  // namespace ntd

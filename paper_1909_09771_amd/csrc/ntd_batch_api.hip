@@ -40,6 +40,7 @@ using ntd_host::Carver;
 
 struct ntd_batch {
     int count = 0, nrhs = 0, prec = 0, epl = 0, gx = 0, gx_max = 0, D = 0;
+    int nr = 1;  // right-hand sides per wavefront pair in the line sweeps
     size_t used = 0;
     std::vector<ntd_handle *> sys;
     // device tables
@@ -60,6 +61,12 @@ struct ntd_batch {
     hipStream_t gs = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // statistics of the last solve: host checks of the active flags, and the
+    // time the GPU spent between the end of a run of iterations and the start
+    // of the next (the host's read and decision in between)
+    hipEvent_t ev_gap[4] = {nullptr, nullptr, nullptr, nullptr};  // gap start, end; solve start, end
+    int passes = 0;
+    double gap_ms = 0.0, solve_ms = 0.0;
 };
 
 namespace {
@@ -239,11 +246,32 @@ hipError_t pack_b(const ntd_batch *b, const void *tab, const int *act, hipStream
                                           b->epl, s);
 }
 hipError_t sweeps_b(const ntd_batch *b, const int *act, hipStream_t s, hipEvent_t *ev) {
-    if (b->prec == NTD_PREC_FP64)
-        return ntd::launch_apply_batch_f64((const ntd::ApplyArgs<double> *)b->tabA, act, b->count,
-                                           b->nrhs, b->epl, s, ev);
-    return ntd::launch_apply_batch_f32((const ntd::ApplyArgs<float> *)b->tabA, act, b->count,
-                                       b->nrhs, b->epl, s, ev);
+    if (b->prec == NTD_PREC_FP64) {
+        const auto *tab = (const ntd::ApplyArgs<double> *)b->tabA;
+        if (b->nr > 1)
+            return ntd::launch_apply_batch_multi_f64(tab, act, b->count, b->nrhs, b->epl, b->nr, s,
+                                                     ev);
+        return ntd::launch_apply_batch_f64(tab, act, b->count, b->nrhs, b->epl, s, ev);
+    }
+    const auto *tab = (const ntd::ApplyArgs<float> *)b->tabA;
+    if (b->nr > 1)
+        return ntd::launch_apply_batch_multi_f32(tab, act, b->count, b->nrhs, b->epl, b->nr, s, ev);
+    return ntd::launch_apply_batch_f32(tab, act, b->count, b->nrhs, b->epl, s, ev);
+}
+
+// Can the batch's sweeps run nr right-hand sides per wavefront pair?
+bool nr_ok(const ntd_batch *b, int nr) {
+    if (nr == 1) return true;
+    if (nr != 2 && nr != 4) return false;
+    if (b->nrhs % nr != 0) return false;
+    return ntd::batch_multi_ok(b->prec == NTD_PREC_FP64 ? 8 : 4, b->epl, nr);
+}
+
+void drop_graph(ntd_batch *b) {
+    if (b->gexec) {  // captured with the old launch shape
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
 }
 hipError_t unpack_b(const ntd_batch *b, const void *tab, const int *act, hipStream_t s) {
     if (b->prec == NTD_PREC_FP64)
@@ -332,6 +360,8 @@ int any_active(ntd_batch *b, hipStream_t s, bool *any) {
 
 void release(ntd_batch *b) {
     if (!b) return;
+    for (hipEvent_t e : b->ev_gap)
+        if (e) (void)hipEventDestroy(e);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -523,8 +553,16 @@ int ntd_batch_pcg_solve(ntd_batch *b, const double *const *rhs, double *const *x
     // passes maxit, so the loop ends; the bound guards against a logic error
     const long long max_pass = (long long)b->D * maxit + 2;
     bool any = true;
+    for (hipEvent_t &e : b->ev_gap)
+        if (!e) CK(hipEventCreate(&e));
+    b->passes = 0;
+    b->gap_ms = 0.0;
+    CK(hipEventRecord(b->ev_gap[2], s));  // start of the solve's iterations
     for (long long pass = 0; pass < max_pass; ++pass) {
+        // the end of the previous run of iterations, then the host's check
+        CK(hipEventRecord(b->ev_gap[0], s));
         if ((st = any_active(b, s, &any)) != NTD_OK) return st;
+        ++b->passes;
         if (!any) {
             CK(ntd::launch_batch_spmv(b->tabV, nullptr, b->D, b->gx, 1, s));
             if ((st = fin(b, ntd::kBOpTrue, 0.0, 0, s)) != NTD_OK) return st;
@@ -537,9 +575,22 @@ int ntd_batch_pcg_solve(ntd_batch *b, const double *const *rhs, double *const *x
             if ((st = fin(b, ntd::kOpBeta, 0.0, 0, s)) != NTD_OK) return st;
             CK(ntd::launch_batch_xpay(b->tabV, b->active, b->D, b->gx, false, s));
         }
+        // the next run starts here: the gap since ev_gap[0] is the check's cost
+        CK(hipEventRecord(b->ev_gap[1], s));
         if ((st = run_chunk(b, graph, s)) != NTD_OK) return st;
+        float g = 0.0f;
+        CK(hipEventSynchronize(b->ev_gap[1]));
+        CK(hipEventElapsedTime(&g, b->ev_gap[0], b->ev_gap[1]));
+        b->gap_ms += g;
     }
     if (any) return NTD_EHIP;
+    {
+        float ms = 0.0f;
+        CK(hipEventRecord(b->ev_gap[3], s));
+        CK(hipEventSynchronize(b->ev_gap[3]));
+        CK(hipEventElapsedTime(&ms, b->ev_gap[2], b->ev_gap[3]));
+        b->solve_ms = ms;
+    }
     CK(hipMemcpyAsync(b->hctl.data(), b->ctl, b->D * sizeof(ntd::BatchCtl),
                       hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
@@ -597,16 +648,72 @@ int ntd_batch_tune(ntd_batch *b, int *gx_out, void *stream) {
     }
     for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
     b->gx = best;
-    if (b->gexec) {  // captured with the old grid
-        (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
-    }
+    drop_graph(b);
     if (st != NTD_OK) return st;
     *gx_out = best;
     return NTD_OK;
 }
 
+int ntd_batch_set_sweep_group(ntd_batch *b, int nr) {
+    if (!b || !nr_ok(b, nr)) return NTD_EINVAL;
+    if (b->nr != nr) drop_graph(b);
+    b->nr = nr;
+    return NTD_OK;
+}
+
+int ntd_batch_tune_sweeps(ntd_batch *b, int *nr_out, void *stream) {
+    if (!b || !nr_out) return NTD_EINVAL;
+    hipStream_t s = S(stream);
+    // the sweeps read only the packed right-hand sides and write only the
+    // packed results and scratch planes: start from zero right-hand sides
+    for (int e = 0; e < b->D; ++e) {
+        const long long N = (long long)b->hV[e].nx * b->hV[e].ny * b->hV[e].nz;
+        CK(ntd::launch_fill(b->hV[e].r, 0.0, N, s));
+    }
+    if (pack_b(b, b->tabXp, nullptr, s) != hipSuccess) return NTD_EHIP;
+    hipEvent_t ev[2];
+    int made = 0, st = NTD_OK;
+    for (; made < 2; ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess) { st = NTD_EHIP; break; }
+    const int keep = b->nr;
+    int best = keep;
+    float best_ms = 0.0f;
+    bool first = true;
+    for (int nr : {1, 2, 4}) {
+        if (st != NTD_OK) break;
+        if (!nr_ok(b, nr)) continue;
+        b->nr = nr;
+        float ms = 0.0f;
+        if (sweeps_b(b, nullptr, s, nullptr) != hipSuccess ||     // warm-up
+            hipEventRecord(ev[0], s) != hipSuccess || sweeps_b(b, nullptr, s, nullptr) != hipSuccess ||
+            hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) {
+            st = NTD_EHIP;
+            break;
+        }
+        if (first || ms < best_ms) {
+            best = nr;
+            best_ms = ms;
+            first = false;
+        }
+    }
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    b->nr = st == NTD_OK ? best : keep;
+    if (b->nr != keep) drop_graph(b);
+    if (st != NTD_OK) return st;
+    *nr_out = best;
+    return NTD_OK;
+}
+
 size_t ntd_batch_footprint_bytes(const ntd_batch *b) { return b ? b->used : 0; }
+
+int ntd_batch_solve_stats(const ntd_batch *b, int *passes, double *gap_ms, double *solve_ms) {
+    if (!b || !passes || !gap_ms || !solve_ms) return NTD_EINVAL;
+    *passes = b->passes;
+    *gap_ms = b->gap_ms;
+    *solve_ms = b->solve_ms;
+    return NTD_OK;
+}
 
 int ntd_batch_destroy(ntd_batch *b) {
     release(b);

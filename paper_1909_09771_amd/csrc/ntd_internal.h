@@ -183,6 +183,15 @@ hipError_t launch_apply_batch_f32(const ApplyArgs<float> *tab, const int *active
                                   int nrhs, int epl, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_apply_batch_f64(const ApplyArgs<double> *tab, const int *active, int count,
                                   int nrhs, int epl, hipStream_t s, hipEvent_t *ev);
+// The same sweeps with nr right-hand sides of one system per wavefront pair
+// (nr = 2 or 4 dividing nrhs; batch_multi_ok tells which (precision, EPL, nr)
+// are built).
+bool batch_multi_ok(int elem_bytes, int epl, int nr);
+hipError_t launch_apply_batch_multi_f32(const ApplyArgs<float> *tab, const int *active, int count,
+                                        int nrhs, int epl, int nr, hipStream_t s, hipEvent_t *ev);
+hipError_t launch_apply_batch_multi_f64(const ApplyArgs<double> *tab, const int *active,
+                                        int count, int nrhs, int epl, int nr, hipStream_t s,
+                                        hipEvent_t *ev);
 hipError_t launch_pack_rhs_batch_f32(const XferArgs<float> *tab, const int *active, int count,
                                      int gx, int epl, hipStream_t s);
 hipError_t launch_pack_rhs_batch_f64(const XferArgs<double> *tab, const int *active, int count,

@@ -223,3 +223,58 @@ def test_batch_tune_keeps_parity(systems):
         ito = O.pcg(s["bands"], O.setup(s["bands"], mode="diag"), b, 1e-8, 500)[1]
         assert sg[e] == 0 and rg[e] <= 1e-8 and abs(ig[e] - ito) <= ito // 4 + 3
     B.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("nr", [2, 4])
+def test_batch_sweeps_with_several_rhs_per_wavefront(systems, prec, nr):
+    """Sweeping nr right-hand sides of a system per wavefront pair (one record
+    load for all of them) gives the one-per-pair results bitwise, and the
+    oracle's to the apply bars; PCG through the graph takes the same
+    iterations and gives the same solutions."""
+    import paper_1909_09771_amd as P
+    nrhs = 4
+    B = make_batch(systems, nrhs, prec, "newton")
+    rs = rhs_list(systems, nrhs, 43)
+    base = [C(z) for z in B.apply([G(r) for r in rs])]
+    try:
+        B.set_sweep_group(nr)
+    except P.NTDError as e:   # FP64 lines of 70 points take 2 values per lane: nr 4 is not built
+        assert prec == "fp64" and nr == 4 and e.status == P.EINVAL
+        B.close()
+        return
+    multi = [C(z) for z in B.apply([G(r) for r in rs])]
+    tol = 1e-9 if prec == "fp64" else 1e-5
+    for e, (r, z0, z1) in enumerate(zip(rs, base, multi)):
+        assert np.array_equal(z0, z1), "entry %d" % e
+        s = systems[e // nrhs]
+        want = O.apply(O.setup(s["bands"], mode="newton"), r)
+        assert relelem(z1, want) <= tol, "entry %d" % e
+    bs = rhs_list(systems, nrhs, 44)
+    B.set_sweep_group(1)
+    x1, i1, r1, s1 = B.pcg([G(b) for b in bs], tol=1e-8, maxit=500)
+    B.set_sweep_group(nr)
+    x2, i2, r2, s2 = B.pcg([G(b) for b in bs], tol=1e-8, maxit=500)
+    assert i1 == i2 and s1 == s2
+    for a, b in zip(x1, x2):
+        assert np.array_equal(C(a), C(b))
+    B.close()
+
+
+def test_batch_tune_sweeps_picks_a_supported_group(systems):
+    import paper_1909_09771_amd as P
+    nrhs = 4
+    B = make_batch(systems, nrhs, "mixed", "diag")
+    nr = B.tune_sweeps()
+    assert nr in (1, 2, 4)
+    bs = rhs_list(systems, nrhs, 45)
+    xs, its, rrs, sts = B.pcg([G(b) for b in bs], tol=1e-8, maxit=500)
+    for e, b in enumerate(bs):
+        assert sts[e] == P.OK and rrs[e] <= 1e-8
+    B.close()
+    with pytest.raises(P.NTDError):
+        B2 = make_batch(systems, 3, "mixed", "diag")
+        try:
+            B2.set_sweep_group(2)      # 2 does not divide 3 right-hand sides
+        finally:
+            B2.close()
