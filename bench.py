@@ -93,7 +93,10 @@ def parse():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the solve with the filter network's t (trained first)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=3, help="oracle PCG iterations sampled")
+    ap.add_argument("--cpu-iters", type=int, default=12, help="oracle PCG iterations sampled")
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-precond-legs", action="store_true",
+                    help="skip the one-off solves with eq. com and with the diagonal block alone")
     ap.add_argument("--kernels-only", action="store_true",
                     help="run the preconditioner, the SpMV and a calibration copy, then exit")
     ap.add_argument("--reps", type=int, default=3, help="launches per kernel in --kernels-only")
@@ -122,6 +125,10 @@ def parse():
                          "and time the solve again")
     ap.add_argument("--batch-apply-only", action="store_true",
                     help="time the batched apply only (no PCG)")
+    ap.add_argument("--batch-nr", type=int, default=1,
+                    help="right-hand sides per wavefront pair in the line sweeps (1, 2, 4)")
+    ap.add_argument("--batch-tune-sweeps", action="store_true",
+                    help="autotune the right-hand sides per wavefront pair (ntd_batch_tune_sweeps)")
     ap.add_argument("--learn-train", type=int, default=256, help="training fields (--suite learned)")
     ap.add_argument("--learn-n", type=int, default=32, help="cube side of the training fields")
     ap.add_argument("--learn-epochs", type=int, default=20)
@@ -162,44 +169,70 @@ def traffic_for(kernel: str, prec: str, smoother: str, size):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(w, args, gpu_iters: int):
-    """The FP64 oracle (single thread) on a bounded sample: assembly, setup (and
-    the ILU(0) factorization) on the full grid, then a few PCG iterations;
-    extrapolated to the GPU's iteration count as setup + iters x (time per
-    iteration, the initial preconditioner application included)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "model unknown"
+
+
+def cpu_baseline_child(args):
+    """The CPU baseline's own process (started by the benchmark before it
+    touches the GPU; it imports no torch): the FP64 oracle, single thread, on
+    the benchmark's workload -- assembly, setup and the ILU(0) factorization on
+    the full grid, then --cpu-iters PCG iterations with the same
+    preconditioner.  Prints one JSON object."""
     import oracle as O
-    n_iters = args.cpu_iters
+    import workloads as W
+    n = args.n
+    w = W.scaled_workload("jump", n) if n != 256 else W.workload("jump256")
     t0 = time.perf_counter()
     bands = O.assemble(w["kappa"], w["bc"])
     F = O.setup(bands, mode=args.schur)
     dt = O.ilu0(bands, 2)[0] if args.smoother != "none" else None
     t1 = time.perf_counter()
-    if args.smoother == "ilu0sym":
-        O.pcg_with(bands, lambda r: O.sym_combo_apply(bands, F, dt, r), w["b"], 1e-30, n_iters)
-    else:
-        O.pcg(bands, F, w["b"], 1e-30, n_iters, dt=dt)
+    x, it, rr, st, hist = O.pcg(bands, F, w["b"], 1e-30, args.cpu_iters, dt=dt,
+                                smoother=args.smoother)
     t2 = time.perf_counter()
-    per_iter = (t2 - t1) / n_iters
-    est = (t1 - t0) + gpu_iters * per_iter
-    del bands, F, dt
-    n = w["n"][0]
-    combo = {"ilu0": " + ILU(0) combination", "ilu0sym": " + symmetric ILU(0) combination",
-             "none": ""}[args.smoother]
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            for ln in f:
-                if ln.startswith("model name"):
-                    model = ln.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
+    print(json.dumps({"setup_s": t1 - t0, "iters": it, "solve_s": t2 - t1,
+                      "s_per_iter": (t2 - t1) / max(it, 1), "status": st,
+                      "recursive_relres_last": float(hist[-1]) if len(hist) else None,
+                      "model": cpu_model(), "host_cores": os.cpu_count() or 0}), flush=True)
+
+
+def cpu_baseline_start(args):
+    """Start cpu_baseline_child in its own process, before any GPU call, so the
+    oracle's CPU work runs beside the GPU steps."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--n", str(args.n),
+           "--schur", args.schur, "--smoother", args.smoother, "--cpu-iters",
+           str(args.cpu_iters)]
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+
+def cpu_baseline_finish(proc, args, gpu_iters: int):
+    """Wait for the child (it has usually finished by now), then extrapolate:
+    setup + the GPU's iteration count x the oracle's time per iteration."""
+    out, err = proc.communicate(timeout=900)
+    if proc.returncode != 0:
+        return {"error": "oracle process exited with %d: %s" % (proc.returncode, err[-400:])}
+    r = json.loads(out.strip().splitlines()[-1])
+    est = r["setup_s"] + gpu_iters * r["s_per_iter"]
+    combo = {"ilu0": " + ILU(0) combination (eq. com)",
+             "ilu0sym": " + symmetric ILU(0) combination", "none": ""}[args.smoother]
     return {"value": round(est, 3), "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": "FP64 oracle, %s Schur blocks%s: assembly+setup on the full %d^3 grid "
-                      "(%.2f s) and %d PCG iterations (%.3f s/iter), extrapolated to the GPU's "
-                      "%d iterations; 1 thread of %d host cores (%s)"
-                      % (args.schur, combo, n, t1 - t0, n_iters, per_iter, gpu_iters,
-                         os.cpu_count() or 0, model or "model unknown")}
+            "setup_s": round(r["setup_s"], 3), "s_per_iter": round(r["s_per_iter"], 4),
+            "iters_run": r["iters"],
+            "sample": "FP64 C oracle (gcc -O3, x86-64-v3, no FP contraction), %s Schur blocks%s, "
+                      "in its own process beside the GPU run: assembly + setup + ILU(0) on the "
+                      "full %d^3 grid (%.2f s) and %d PCG iterations (%.3f s each), extrapolated "
+                      "to the GPU's %d iterations; 1 thread of %d host cores (%s)"
+                      % (args.schur, combo, args.n, r["setup_s"], r["iters"], r["s_per_iter"],
+                         gpu_iters, r["host_cores"], r["model"])}
 
 
 def kernels_only(args, S, b, n):
@@ -334,6 +367,15 @@ def batch_suite(args):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         log("batch of %d systems x %d rhs: setup %.3f s" % (count, nrhs, t1 - t0))
+        sweep_group = {}
+        if args.batch_tune_sweeps:
+            ts0 = time.perf_counter()
+            sweep_group["tuned"] = B.tune_sweeps()
+            sweep_group["tune_s"] = round(time.perf_counter() - ts0, 4)
+            log("line sweeps: %d right-hand sides per wavefront pair (tuned)" % sweep_group["tuned"])
+        elif args.batch_nr != 1:
+            B.set_sweep_group(args.batch_nr)
+        sweep_group["nr"] = sweep_group.get("tuned", args.batch_nr)
         if args.batch_apply_only:
             t2 = t3 = t1
             xs, its, rrs, sts = [], [0], [0.0], [0]
@@ -344,7 +386,9 @@ def batch_suite(args):
             xs, its, rrs, sts = B.pcg(bs, tol=args.tol, maxit=args.maxit, graph=True)
             torch.cuda.synchronize()
             t3 = time.perf_counter()
-            log("batched PCG: %.3f s, iterations %d..%d" % (t3 - t2, min(its), max(its)))
+            passes, gap_ms, it_ms = B.solve_stats()
+            log("batched PCG: %.3f s, iterations %d..%d; %d host checks, stream idle %.3f ms"
+                % (t3 - t2, min(its), max(its), passes, gap_ms))
         zs = B.empty_like_entries()
         B.apply_profile(bs, zs)
         prof = [B.apply_profile(bs, zs) for _ in range(5)]
@@ -371,7 +415,12 @@ def batch_suite(args):
                              if args.batch_n else None,
                              "unknowns_per_launch": units,
                              "bytes_per_unknown": "4e + 2e x nrhs, e = %d" % e},
-                "footprint_bytes": B.footprint_bytes}
+                "footprint_bytes": B.footprint_bytes,
+                "sweep_rhs_per_wavefront_pair": sweep_group}
+        if not args.batch_apply_only:
+            line["host_checks"] = {"passes": passes, "stream_idle_ms": round(gap_ms, 4),
+                                   "iterations_ms": round(it_ms, 3),
+                                   "idle_frac": round(gap_ms / it_ms, 6) if it_ms > 0 else None}
         if args.batch_tune and not args.batch_apply_only:
             tt0 = time.perf_counter()
             g = B.tune()
@@ -446,14 +495,18 @@ def spheres_suite(args):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         free1 = torch.cuda.mem_get_info(dev)[0]
-        x, it, rr, st = S.pcg(b, tol=args.tol, maxit=args.maxit)
+        x, it, rr, st, hist = S.pcg_history(b, tol=args.tol, maxit=args.maxit)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        # the recursive residual every 10 % of the run, and its smallest value
+        marks = sorted(set([max(1, (it * q) // 10) for q in range(1, 11)])) if it else []
         line = {"suite": "spheres", "n": n, "prec": prec, "schur": args.schur,
                 "smoother": args.smoother, "tol": args.tol, "iters": it, "relres": rr,
                 "status": st, "setup_s": round(t1 - t0, 4), "solve_s": round(t2 - t1, 4),
                 "overall_s": round(t2 - t0, 4), "footprint_bytes": S.footprint_bytes,
-                "mem_get_info_delta_bytes": int(free0 - free1)}
+                "mem_get_info_delta_bytes": int(free0 - free1),
+                "residual_trend": {str(m): float("%.3e" % hist[m - 1]) for m in marks},
+                "min_recursive_relres": float("%.3e" % min(hist)) if hist else None}
         print(json.dumps(line), flush=True)
         S.close()
         del S, x
@@ -566,6 +619,9 @@ def learned_suite(args):
 
 def main():
     args = parse()
+    if args.cpu_baseline_child:
+        cpu_baseline_child(args)
+        return
     if args.gpus != 1:
         print("bench.py: runs on one GPU only (--gpus 1); the level-3 twist split "
               "across two GPUs is a design, not built", file=sys.stderr)
@@ -582,6 +638,9 @@ def main():
     if args.suite == "spheres":
         spheres_suite(args)
         return
+    cpu_proc = None
+    if not args.no_cpu and not args.kernels_only:
+        cpu_proc = cpu_baseline_start(args)   # before the first GPU call
     import torch
     import paper_1909_09771_amd as P
     import workloads as W
@@ -675,7 +734,26 @@ def main():
                             "relres": rr2, "status": st2,
                             "rel_diff_of_solutions": diff}
         log("comparison solve (%s): %.2f s, %d iterations" % (other, c1 - c0, it2))
+        x_other = x2.cpu().numpy()
         del S2, x2
+
+    if not args.no_precond_legs:
+        # the paper's own preconditioner (eq. com) and the diagonal block alone,
+        # one solve each in the benchmark's precision
+        legs = []
+        for schur, smoother in (("newton", "ilu0"), ("diag", "none")):
+            torch.cuda.synchronize()
+            p0 = time.perf_counter()
+            SP = P.Solver(kappa, bc, prec=args.prec, schur=schur, smoother=smoother)
+            xp, itp, rrp, stp = SP.pcg(b, tol=args.tol, maxit=args.maxit)
+            torch.cuda.synchronize()
+            p1 = time.perf_counter()
+            legs.append({"schur": schur, "smoother": smoother, "prec": args.prec,
+                         "s_to_solution": round(p1 - p0, 4), "iters": itp, "relres": rrp,
+                         "status": stp})
+            log("%s + %s solve: %.2f s, %d iterations" % (schur, smoother, p1 - p0, itp))
+            del SP, xp
+        extra["compare_preconditioners"] = legs
 
     if not args.no_learned:
         # The filter network (--suite learned's defaults: 256 mixture fields of
@@ -761,9 +839,20 @@ def main():
     }
     line["rest_GBps"] = round(rest_bytes(args.prec, args.smoother) * N / (rest_ms * 1e-3) / 1e9, 1)
     line.update(extra)
-    if not args.no_cpu:
-        log("timing the CPU oracle on a sample")
-        line["cpu_baseline"] = cpu_baseline(w, args, iters)
+    # Error of each result against the FP64 oracle: the oracle's own SpMV
+    # recomputes the true relative residual of the GPU's solutions.
+    import numpy as np
+    import oracle as O
+    bands = O.assemble(w["kappa"], w["bc"])
+    bn = np.linalg.norm(w["b"])
+    errs = {args.prec: float(np.linalg.norm(w["b"] - O.spmv(bands, x_main.cpu().numpy())) / bn)}
+    if not args.no_compare:
+        errs[other] = float(np.linalg.norm(w["b"] - O.spmv(bands, x_other)) / bn)
+    line["oracle_true_relres"] = errs
+    del bands
+    if cpu_proc is not None:
+        log("collecting the CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline_finish(cpu_proc, args, iters)
     print(json.dumps(line), flush=True)
 
 
