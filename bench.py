@@ -136,6 +136,8 @@ def parse():
     ap.add_argument("--learn-eval", type=int, default=8, help="held-out evaluation fields")
     ap.add_argument("--learn-eval-n", type=int, default=128, help="cube side of the evaluation fields")
     ap.add_argument("--learn-maxit", type=int, default=2000, help="PCG iteration cap of the evaluation")
+    ap.add_argument("--learn-target", default="binva", choices=["binva", "aeig"],
+                    help="targets: the smallest eigenvector of B^-1 A (binva) or of A (aeig)")
     ap.add_argument("--learn-configs", default="newton:ilu0sym,newton:ilu0,diag:none",
                     help="schur:smoother pairs of the evaluation solves")
     return ap.parse_args()
@@ -394,6 +396,7 @@ def batch_suite(args):
         prof = [B.apply_profile(bs, zs) for _ in range(5)]
         lower_ms, twist_ms, upper_ms, rest_ms = [sorted(p[i] for p in prof)[2] for i in range(4)]
         units = sum(n ** 3 - n ** 2 for n in sides)
+        kname_b = "k_apply_lower_b" if sweep_group["nr"] == 1 else "k_apply_lower_bm%d" % sweep_group["nr"]
         by = sum((n ** 3 - n ** 2) * (4 * e + 2 * e * nrhs) for n in sides)
         achieved = by / (lower_ms * 1e-3) / 1e9
         line = {"suite": "batch" + ("-apply" if args.batch_apply_only else ""),
@@ -407,10 +410,10 @@ def batch_suite(args):
                 "max_relres": max(rrs), "all_ok": all(st == 0 for st in sts),
                 "apply_ms": {"lower": round(lower_ms, 4), "twist": round(twist_ms, 4),
                              "upper": round(upper_ms, 4), "rest": round(rest_ms, 4)},
-                "roofline": {"kernel": "k_apply_lower_b", "bound": "hbm",
+                "roofline": {"kernel": kname_b, "bound": "hbm",
                              "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                             "traffic": traffic_for("k_apply_lower_b", prec, "none",
+                             "traffic": traffic_for(kname_b, prec, "none",
                                                     "%sx%dx%d" % (args.batch_n, count, nrhs))
                              if args.batch_n else None,
                              "unknowns_per_launch": units,
@@ -514,8 +517,10 @@ def spheres_suite(args):
 
 
 def learned_suite(args):
-    """The learned filter vector: targets (the lowest eigenvector of A by inverse
-    iteration with the library's batched FP64 PCG) on --learn-train mixture fields
+    """The learned filter vector: targets (--learn-target: the smallest-eigenvalue
+    eigenvector of B^-1 A by the library's inverse iteration, or the lowest
+    eigenvector of A by inverse iteration with the batched FP64 PCG) on
+    --learn-train mixture fields
     of side --learn-n (seeds 10000+i), Adam training, then PCG to --tol with
     t = 1, with the exact target and with the network's t on --learn-eval held-out
     fields of side --learn-eval-n (seeds 20000+i, b ~ U[-1,1] seed 30000+i),
@@ -536,11 +541,14 @@ def learned_suite(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tgt = []
-    for i in range(0, len(kap), 64):
-        tgt += Lr.eigen_targets(kap[i:i + 64], [bc] * len(kap[i:i + 64]))
+    if args.learn_target == "binva":
+        tgt, _ = Lr.binva_targets(kap, [bc] * len(kap), schur="newton")
+    else:
+        for i in range(0, len(kap), 64):
+            tgt += Lr.eigen_targets(kap[i:i + 64], [bc] * len(kap[i:i + 64]))
     torch.cuda.synchronize()
     t_targets = time.perf_counter() - t0
-    log("targets: %d fields of %d^3 in %.2f s" % (len(kap), n, t_targets))
+    log("targets (%s): %d fields of %d^3 in %.2f s" % (args.learn_target, len(kap), n, t_targets))
     net = P.FilterNet(W.cnn_init_params(0))
     t0 = time.perf_counter()
     hist = Lr.train(net, kap, tgt, args.learn_epochs, args.learn_lr)
@@ -579,8 +587,24 @@ def learned_suite(args):
         "predict_GBps": round(CNN_BYTES_PER_VOXEL * vox / (pred_ms * 1e-3) / 1e9, 1),
         "peak_bf16_TFLOPs": 2500.0, "peak_hbm_GBps": 8000.0}), flush=True)
     del kd, tout
-    evt = Lr.eigen_targets([g(k) for k in evk], [bc] * len(evk))
+    evt_cache, lam_cache = {}, {}
+
+    def eval_targets(schur):
+        if args.learn_target != "binva":
+            schur = "any"
+        if schur not in evt_cache:
+            te = time.perf_counter()
+            if args.learn_target == "binva":
+                evt_cache[schur], lam_cache[schur] = Lr.binva_targets(
+                    [g(k) for k in evk], [bc] * len(evk), schur=schur)
+            else:
+                evt_cache[schur] = Lr.eigen_targets([g(k) for k in evk], [bc] * len(evk))
+            log("evaluation targets (%s, %s blocks): %.1f s" % (args.learn_target, schur,
+                                                               time.perf_counter() - te))
+        return evt_cache[schur]
+
     for schur, smoother in (c.split(":") for c in args.learn_configs.split(",")):
+        evt = eval_targets(schur)
         rows = []
         for i, k in enumerate(evk):
             kd = g(k)
@@ -613,6 +637,9 @@ def learned_suite(args):
         print(json.dumps({
             "suite": "learned", "phase": "eval", "eval_fields": len(evk), "eval_n": ne,
             "schur": schur, "smoother": smoother, "prec": "mixed", "tol": args.tol,
+            "target": args.learn_target,
+            "target_lambda": lam_cache.get(schur),
+            "target_frac_at_floor": [round(float((t <= 1e-3).double().mean()), 4) for t in evt],
             "iters": {k: [r[k]["iters"] for r in rows] for k in ("ones", "target", "learned")},
             "summary": summ}), flush=True)
 
