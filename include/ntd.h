@@ -167,6 +167,48 @@ int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int max
 int ntd_pcg_solve_history(ntd_handle *h, const double *b, double *x, double tol, int maxit,
                           int *iters, double *relres, double *hist, void *stream);
 
+/* Progress callback of ntd_pcg_solve_progress: iteration count and recursive
+ * relative residual ||r||/||b|| after that iteration, and the caller's ctx. */
+typedef void (*ntd_progress_fn)(int iteration, double relres, void *ctx);
+
+/* ntd_pcg_solve_history that also calls progress(it, ||r||/||b||, ctx) on the
+ * calling host thread after every `every`-th iteration (every >= 1 when
+ * progress is not NULL; progress NULL: no calls).  The loop already reads its
+ * scalars back every iteration, so the calls change neither the iterates nor
+ * the number of synchronisations; they let a long solve report as it goes.
+ * The callback must not call into this handle. */
+int ntd_pcg_solve_progress(ntd_handle *h, const double *b, double *x, double tol, int maxit,
+                           int *iters, double *relres, double *hist, int every,
+                           ntd_progress_fn progress, void *ctx, void *stream);
+
+/* Filter-vector target from the handle's own preconditioner (Sec. 1: the
+ * error components that the filtered iteration (I - B^{-1}A)^n damps slowest
+ * are the eigenvectors of B^{-1}A of smallest eigenvalue).  Inverse iteration
+ * on M = B^{-1}A (B as set up, without smoother): `outer` times,
+ * y = M^{-1} v by conjugate gradients in the A-inner product (M is self-adjoint
+ * and positive definite there; one B^{-1} application and one product with A
+ * per step) to ||v - M y||_A <= inner_tol ||v||_A, then v = y / (the entry of
+ * y of largest magnitude); each solve starts at y = 0.  On return
+ * v = max(v, floor).
+ * v: [N] device FP64, the start vector in, the target out.  The start must
+ * carry components along the eigenvector sought: t = 1 (the handle's own filter
+ * vector when set up with t = NULL) is itself an eigenvector of B^{-1}A with
+ * eigenvalue 1 (B t = A t), and the iteration would stay there.  work: [7 N] device FP64 scratch owned by the caller.  *inner_iters
+ * (HOST): CG steps over all outer iterations; *lambda (HOST): v'Av / y'Av of
+ * the last step, the estimate of the smallest eigenvalue of B^{-1}A.
+ * Returns NTD_ENOCONV if an inner solve misses inner_tol in inner_maxit
+ * steps, NTD_EBREAKDOWN on a non-positive curvature.  Synchronises. */
+int ntd_filter_target(ntd_handle *h, double *v, int outer, double inner_tol, int inner_maxit,
+                      double floor, double *work, int *inner_iters, double *lambda, void *stream);
+
+/* v[0..n) <- max(v / m, floor), m = the entry of v of largest magnitude (the
+ * first one on ties), so that the largest entry becomes +1; floor <= -1 leaves
+ * the scaled vector unclipped.  partials: [2048] device FP64 scratch owned by
+ * the caller; *scale (HOST) = 1/m.  NTD_EINVAL if v is zero or not finite.
+ * Synchronises. */
+int ntd_vec_normalize(double *v, long long n, double floor, double *partials, double *scale,
+                      void *stream);
+
 /* Copy an internal array of the handle into dst ([N] device FP64), for tests
  * and diagnostics.  which: 0..3 = bands d, ax, ay, az of A; 4 = e1 (x-band of
  * the line blocks T); 5 = 1/pivot of T; 6 = f2 (y-band of the plane blocks P);

@@ -26,6 +26,8 @@ SMOOTHER = {"none": 0, "ilu0": 1, "ilu0sym": 2}
 EXPORTS = {"d": 0, "ax": 1, "ay": 2, "az": 3, "e1": 4, "minv": 5, "f2": 6, "dT": 7, "dP": 8,
            "xP": 9, "dt": 10}
 MAX_NX = 1024
+# ntd_progress_fn: (iteration, relres, ctx)
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_int, ctypes.c_double, ctypes.c_void_p)
 
 _lib = None
 
@@ -65,6 +67,14 @@ def lib() -> ctypes.CDLL:
         L.ntd_pcg_solve_history.argtypes = [P, P, P, D, I, ctypes.POINTER(I), ctypes.POINTER(D),
                                             ctypes.POINTER(D), P]
         L.ntd_pcg_solve_history.restype = I
+        L.ntd_pcg_solve_progress.argtypes = [P, P, P, D, I, ctypes.POINTER(I),
+                                             ctypes.POINTER(D), P, I, PROGRESS_FN, P, P]
+        L.ntd_pcg_solve_progress.restype = I
+        L.ntd_filter_target.argtypes = [P, P, I, D, I, D, P, ctypes.POINTER(I),
+                                        ctypes.POINTER(D), P]
+        L.ntd_filter_target.restype = I
+        L.ntd_vec_normalize.argtypes = [P, ctypes.c_longlong, D, P, ctypes.POINTER(D), P]
+        L.ntd_vec_normalize.restype = I
         L.ntd_export.argtypes = [P, I, P, P]
         L.ntd_export.restype = I
         L.ntd_load_factors.argtypes = [P, P, P, P, P]
@@ -111,6 +121,21 @@ def lib() -> ctypes.CDLL:
         L.ntd_cnn_adam.restype = I
         _lib = L
     return _lib
+
+
+def vec_normalize(v: torch.Tensor, floor: float = -2.0) -> float:
+    """v <- max(v / (its entry of largest magnitude), floor) in place on the
+    device (ntd_vec_normalize); floor <= -1 leaves it unclipped.  Returns the
+    scale applied."""
+    if not (v.is_cuda and v.dtype == torch.float64 and v.is_contiguous()):
+        raise ValueError("v must be a contiguous float64 CUDA tensor")
+    part = torch.empty(2048, dtype=torch.float64, device=v.device)
+    sc = ctypes.c_double(0.0)
+    st = lib().ntd_vec_normalize(_dptr(v), v.numel(), float(floor), _dptr(part), ctypes.byref(sc),
+                                 _stream_ptr(v.device))
+    if st != OK:
+        raise NTDError(st, "ntd_vec_normalize")
+    return sc.value
 
 
 def strerror(status: int) -> str:
@@ -228,22 +253,30 @@ class Solver:
         return res.value
 
     def pcg(self, b: torch.Tensor, tol: float = 1e-8, maxit: int = 200,
-            x: torch.Tensor | None = None):
+            x: torch.Tensor | None = None, progress=None, every: int = 100):
         """Solve A x = b; returns (x, iterations, true relative residual, status).
-        status is OK, ENOCONV or EBREAKDOWN; other failures raise."""
+        status is OK, ENOCONV or EBREAKDOWN; other failures raise.  progress,
+        if given, is called as progress(iteration, relres) after every
+        `every`-th iteration (ntd_pcg_solve_progress)."""
         _check_vec(b, self.shape, self.device, "b")
         x = torch.empty_like(b) if x is None else x
         _check_vec(x, self.shape, self.device, "x")
         it = ctypes.c_int(0)
         rr = ctypes.c_double(0.0)
-        st = lib().ntd_pcg_solve(self._h, _dptr(b), _dptr(x), float(tol), int(maxit),
-                                 ctypes.byref(it), ctypes.byref(rr), _stream_ptr(self.device))
+        if progress is None:
+            st = lib().ntd_pcg_solve(self._h, _dptr(b), _dptr(x), float(tol), int(maxit),
+                                     ctypes.byref(it), ctypes.byref(rr), _stream_ptr(self.device))
+        else:
+            cb = PROGRESS_FN(lambda i, r, _ctx: progress(i, r))
+            st = lib().ntd_pcg_solve_progress(self._h, _dptr(b), _dptr(x), float(tol), int(maxit),
+                                              ctypes.byref(it), ctypes.byref(rr), None,
+                                              int(every), cb, None, _stream_ptr(self.device))
         if st not in (OK, ENOCONV, EBREAKDOWN):
             raise NTDError(st, "ntd_pcg_solve")
         return x, it.value, rr.value, st
 
     def pcg_history(self, b: torch.Tensor, tol: float = 1e-8, maxit: int = 200,
-                    x: torch.Tensor | None = None):
+                    x: torch.Tensor | None = None, progress=None, every: int = 100):
         """As pcg, plus the recursive relative residual after every iteration:
         returns (x, iterations, true relative residual, status, history)."""
         _check_vec(b, self.shape, self.device, "b")
@@ -252,12 +285,36 @@ class Solver:
         it = ctypes.c_int(0)
         rr = ctypes.c_double(0.0)
         hist = (ctypes.c_double * max(int(maxit), 1))()
-        st = lib().ntd_pcg_solve_history(self._h, _dptr(b), _dptr(x), float(tol), int(maxit),
-                                         ctypes.byref(it), ctypes.byref(rr), hist,
-                                         _stream_ptr(self.device))
+        if progress is None:
+            st = lib().ntd_pcg_solve_history(self._h, _dptr(b), _dptr(x), float(tol), int(maxit),
+                                             ctypes.byref(it), ctypes.byref(rr), hist,
+                                             _stream_ptr(self.device))
+        else:
+            cb = PROGRESS_FN(lambda i, r, _ctx: progress(i, r))
+            st = lib().ntd_pcg_solve_progress(self._h, _dptr(b), _dptr(x), float(tol), int(maxit),
+                                              ctypes.byref(it), ctypes.byref(rr), hist,
+                                              int(every), cb, None, _stream_ptr(self.device))
         if st not in (OK, ENOCONV, EBREAKDOWN):
             raise NTDError(st, "ntd_pcg_solve_history")
         return x, it.value, rr.value, st, list(hist[: it.value])
+
+    def filter_target(self, v0: torch.Tensor | None = None, outer: int = 20,
+                      inner_tol: float = 1e-10, inner_maxit: int = 5000, floor: float = 1e-3):
+        """The smallest-eigenvalue eigenvector of B^{-1}A by inverse iteration
+        (ntd_filter_target), clipped below at floor; returns (t, inner CG steps,
+        eigenvalue estimate)."""
+        v = torch.ones(self.shape, dtype=torch.float64, device=self.device) if v0 is None \
+            else v0.clone()
+        _check_vec(v, self.shape, self.device, "v0")
+        work = torch.empty((7,) + tuple(self.shape), dtype=torch.float64, device=self.device)
+        it = ctypes.c_int(0)
+        lam = ctypes.c_double(0.0)
+        st = lib().ntd_filter_target(self._h, _dptr(v), int(outer), float(inner_tol),
+                                     int(inner_maxit), float(floor), _dptr(work),
+                                     ctypes.byref(it), ctypes.byref(lam), _stream_ptr(self.device))
+        if st != OK:
+            raise NTDError(st, "ntd_filter_target")
+        return v, it.value, lam.value
 
     # -- inspection ---------------------------------------------------------
     def export(self, which: str) -> torch.Tensor:

@@ -411,8 +411,15 @@ int ntd_pcg_solve(ntd_handle *h, const double *b, double *x, double tol, int max
 
 int ntd_pcg_solve_history(ntd_handle *h, const double *b, double *x, double tol, int maxit,
                           int *iters, double *relres, double *hist, void *stream) {
+    return ntd_pcg_solve_progress(h, b, x, tol, maxit, iters, relres, hist, 0, nullptr, nullptr,
+                                  stream);
+}
+
+int ntd_pcg_solve_progress(ntd_handle *h, const double *b, double *x, double tol, int maxit,
+                           int *iters, double *relres, double *hist, int every,
+                           ntd_progress_fn progress, void *ctx, void *stream) {
     if (!h || !b || !x || b == x || !iters || !relres) return NTD_EINVAL;
-    if (!(tol > 0.0) || maxit < 1) return NTD_EINVAL;
+    if (!(tol > 0.0) || maxit < 1 || every < 0 || (progress && every < 1)) return NTD_EINVAL;
     hipStream_t s = S(stream);
     const long long N = h->N;
     ntd::Grid g = grid_of(h);
@@ -447,6 +454,7 @@ int ntd_pcg_solve_history(ntd_handle *h, const double *b, double *x, double tol,
         }
         ++it;
         if (hist) hist[it - 1] = sqrt(hs.rr) / bn;
+        if (progress && it % every == 0) progress(it, sqrt(hs.rr) / bn, ctx);
         if (sqrt(hs.rr) / bn <= tol) {
             double tr = 0.0;
             if ((st = true_relres(h, b, x, bn, &tr, s)) != NTD_OK) return st;

@@ -5,18 +5,22 @@ filter vector t close to A's eigenvectors of smallest eigenvalue should serve
 that end of the spectrum better than the rowsum choice t = 1.  Here a small 3D
 network (FilterNet, kernels in ntd_cnn.hip) predicts t from kappa.
 
-* Targets: the lowest eigenvector of A, by inverse iteration
-  v <- A^{-1} v / max(A^{-1} v) from v = 1, every solve a batched FP64 PCG of
-  the library (B(1), diagonal Schur blocks), clipped below at 1e-3.  A is a
-  symmetric M-matrix, so the eigenvector is positive, as a filter vector must be.
+* Targets, two kinds:
+  - binva_targets: the eigenvector of B^{-1}A (B = B(t = 1)) of smallest
+    eigenvalue, by inverse iteration in the library (ntd_filter_target), the
+    error component the filtered iteration damps slowest (Sec. 1), clipped
+    below at 1e-3 (it can change sign);
+  - eigen_targets: the lowest eigenvector of A, by inverse iteration
+    v <- A^{-1} v / max(A^{-1} v) from v = 1, every solve a batched FP64 PCG of
+    the library (B(1), diagonal Schur blocks), clipped below at 1e-3.  A is a
+    symmetric M-matrix, so this eigenvector is positive.
 * Training: Adam on mean (t - t*)^2, one field per step.
 * Evaluation: PCG iterations and time to a tolerance with t = 1 and with the
   predicted t on held-out fields.  If the factorization with the predicted t
   loses a positive pivot, t = 1 is used (and reported).
 
-Every convolution, loss, gradient, optimizer step, factorization and PCG runs
-in the library's kernels; the glue between the inverse-iteration solves (a max
-and a division per field) uses torch element-wise ops on the device.
+Every convolution, loss, gradient, optimizer step, factorization, PCG,
+inverse iteration and normalisation runs in the library's kernels.
 """
 from __future__ import annotations
 
@@ -25,7 +29,7 @@ import time
 import numpy as np
 import torch
 
-from . import ENOTSPD, OK, Batch, FilterNet, NTDError, Solver
+from . import ENOTSPD, OK, Batch, FilterNet, NTDError, Solver, vec_normalize
 
 
 def eigen_targets(kappas, bcs, iters: int = 20, tol: float = 1e-6, floor: float = 1e-3,
@@ -47,10 +51,39 @@ def eigen_targets(kappas, bcs, iters: int = 20, tol: float = 1e-6, floor: float 
             if bad:
                 raise RuntimeError("inverse iteration: PCG failed (field, status, relres, "
                                    "iterations): %s" % bad)
-            vs = [x / x.max() for x in xs]
+            for x in xs:
+                vec_normalize(x)           # largest entry +1 (the iterates stay positive)
+            vs = xs
     finally:
         B.close()
-    return [torch.clamp(v, min=floor) for v in vs]
+    for v in vs:
+        vec_normalize(v, floor)
+    return vs
+
+
+def binva_targets(kappas, bcs, starts, schur: str = "newton", outer: int = 20,
+                  inner_tol: float = 1e-10, inner_maxit: int = 20000, floor: float = 1e-3,
+                  progress=None):
+    """Smallest-eigenvalue eigenvectors of B^{-1}A, B = B(t = 1) with the given
+    Schur block, clipped below at floor (ntd_filter_target), from the start
+    vectors `starts` (t = 1 itself is an eigenvector of B(1)^{-1}A, since
+    B t = A t, so a start must carry other components); returns the targets and
+    the eigenvalue estimates.  progress(i, lam, inner_steps, seconds), if
+    given, is called after each field."""
+    out, lams = [], []
+    for i, (k, bc, v0) in enumerate(zip(kappas, bcs, starts)):
+        t0 = time.perf_counter()
+        S = Solver(k, bc, prec="fp64", schur=schur)
+        try:
+            t, inner, lam = S.filter_target(v0, outer=outer, inner_tol=inner_tol,
+                                            inner_maxit=inner_maxit, floor=floor)
+        finally:
+            S.close()
+        out.append(t)
+        lams.append(lam)
+        if progress is not None:
+            progress(i, lam, inner, time.perf_counter() - t0)
+    return out, lams
 
 
 def train(net: FilterNet, kappas, targets, epochs: int, lr: float, seed: int = 0):

@@ -184,3 +184,24 @@ def test_spheres96_converges_to_its_attainable_tolerance():
     print("spheres96: %d iterations, relres %.3e, oracle-recomputed %.3e" % (it, rr, tr))
     assert st == P().OK and rr <= 1e-6 and len(hist) == it
     assert tr <= 1.01e-6 and abs(tr - rr) <= 1e-3 * rr
+
+
+def test_pcg_progress_callback_leaves_the_solve_unchanged():
+    """ntd_pcg_solve_progress: the callback sees every 7th iteration with the
+    recursive residual that the history records, and the solution, the
+    iteration count and the residual are bitwise those of ntd_pcg_solve."""
+    w = W.workload("poisson32")
+    S = P().Solver(G(w["kappa"]), w["bc"], prec="mixed", schur="newton", smoother="ilu0sym")
+    b = G(w["b"])
+    x0, it0, rr0, st0 = S.pcg(b, tol=1e-10, maxit=500)
+    seen = []
+    x1, it1, rr1, st1, hist = S.pcg_history(b, tol=1e-10, maxit=500, every=7,
+                                            progress=lambda i, r: seen.append((i, r)))
+    assert st0 == st1 == P().OK and it0 == it1 and rr0 == rr1
+    assert torch.equal(x0, x1)
+    assert [i for i, _ in seen] == list(range(7, it1 + 1, 7))
+    assert all(r == hist[i - 1] for i, r in seen)
+    seen2 = []
+    x2, it2, rr2, st2 = S.pcg(b, tol=1e-10, maxit=500, every=5,
+                              progress=lambda i, r: seen2.append(i))
+    assert torch.equal(x0, x2) and it2 == it0 and seen2 == list(range(5, it0 + 1, 5))
