@@ -130,4 +130,5 @@ def compare(net: FilterNet, kappa, bc, b, tol=1e-8, maxit=5000, prec="mixed", sc
     learned = solve_with(kappa, bc, b, t, tol, maxit, prec, schur, smoother)
     learned["seconds"] += pred_s
     learned["predict_s"] = pred_s
+    learned["t_max_over_min"] = float(t.max() / t.min())
     return dict(ones=ones, learned=learned)
