@@ -35,7 +35,7 @@ namespace ntd {
 
 namespace {
 
-constexpr int kSetupThreads = 256;  // two chain wavefronts + two helpers for plane-wide work
+constexpr int kSetupThreads = 512;  // two chain wavefronts + six helpers for plane-wide work
 
 // ---------------------------------------------------------------------------
 // Buffer I/O.
@@ -675,9 +675,14 @@ struct PolPlain {
 // loses, for each neighbour line nb, phi Y phi with g = (T_nb^{-1} v)./v,
 // v = phi .* t_m, phi = the y-coupling of the two lines and Y = 2g - g T_nb g
 // (Newton) or Y = g (diagonal); then the twisted pivots of T_m.
+// The LDS of a wave (5 * nx doubles: dT, e, M then 1/M, and two work lines)
+// keeps the factors of the last line it set up; a neighbour's factors are read
+// from there (nbsh0, nbsh1: the LDS of the wave that set up nb0, nb1), not
+// from the global arrays it has just written.
 template <int EPL>
 __device__ void line_setup(const SetupArgs &a, long long pk, int m, int nnb, int nb0, int nb1,
-                           double *sh /* per-wave LDS: 5 * nx doubles */) {
+                           double *sh /* this wave's LDS */, const double *nbsh0,
+                           const double *nbsh1) {
     const int nx = a.nx;
     const LineGeom G(nx, EPL);
     const int lane = threadIdx.x & 63;
@@ -688,26 +693,27 @@ __device__ void line_setup(const SetupArgs &a, long long pk, int m, int nnb, int
     load_line(G, a.xP + lm, ev);
     for (int q = 0; q < nnb; ++q) {
         const int nb = q == 0 ? nb0 : nb1;
-        const long long ln = pk + (long long)nb * nx;
+        const double *nbs = q == 0 ? nbsh0 : nbsh1;
+        const double *nd = nbs, *ne = nbs + nx, *nmv = nbs + 2 * nx;
         const long long lc = pk + (long long)(m < nb ? m : nb) * nx;
         double phi[EPL], v[EPL], zl[EPL], gam[EPL], dTn[EPL], en[EPL];
         load_line(G, a.f2 + lc, phi);
+        LineIn<double, EPL> C;
 #pragma unroll
         for (int s = 0; s < EPL; ++s) {
-            int c = G.pos(s, EPL);
-            v[s] = G.ok(c) ? phi[s] * tval(a.t, lm + G.elem(c)) : 0.0;
+            const int c = G.pos(s, EPL);
+            const bool ok = G.ok(c);
+            const int e = G.elem(c);
+            v[s] = ok ? phi[s] * tval(a.t, lm + e) : 0.0;
+            C.c0[s] = ok ? nmv[e] : 0.0;                 // 1/M of the neighbour
+            C.c1[s] = ok ? ne[e] : 0.0;                  // its coupling e -- e+1
+            C.c2[s] = (ok && e > 0) ? ne[e - 1] : 0.0;   // and e-1 -- e
+            dTn[s] = ok ? nd[e] : 0.0;
+            en[s] = C.c1[s];
         }
-        LineIn<double, EPL> C;
-        NatFmt<double, EPL> F(nx);
-        F.e1 = make_rsrc(a.e1 + ln);
-        F.mv = make_rsrc(a.mv + ln);
-        F.mv64 = a.mv + ln;
-        F.soT = 0;
-        F.lineB = (unsigned)nx * 8u;
-        F.load_coef(0, C);
+        C.mvj = nmv[G.ca - 1];
+        const NatFmt<double, EPL> F(nx);
         F.solve(C, v, zl);
-        load_line(G, a.dT + ln, dTn);
-        load_line(G, a.e1 + ln, en);
 #pragma unroll
         for (int s = 0; s < EPL; ++s) {
             bool ok = G.ok(G.pos(s, EPL));
@@ -737,60 +743,109 @@ __device__ void line_setup(const SetupArgs &a, long long pk, int m, int nnb, int
             wave_sync();
         }
     }
-    // Twisted pivots: lane 0 walks chain A up to j-1, lane 32 chain B down to
-    // j+1, then lane 0 takes the twist row with both neighbours.
+    // Twisted pivots M_c = d_c - e_c^2 / M_{c-1} along chain A (elements 0..j-1)
+    // and chain B (n-1 down to j+1), e_c the coupling of c to its predecessor;
+    // then the twist row j with both neighbours.  With the continuants p_c =
+    // d_c p_{c-1} - e_c^2 p_{c-2} (p_{-1} = 1, p_0 = d_0), M_c = p_c / p_{c-1}.
+    // Scaled as q_c = p_c / (d_0 ... d_c) they obey
+    //     q_c = q_{c-1} - alpha_c q_{c-2},  alpha_c = e_c^2 / (d_c d_{c-1}),
+    // so the walk along a chain is one FMA per element (the alphas and the
+    // ratios M_c = d_c q_c / q_{c-1} are formed by all lanes in parallel), and a
+    // rounding error propagates exactly as in the recurrence for M_c itself.
+    // An exact power-of-2 rescale every 16 elements keeps q from underflowing.
     store_line(G, sd, dT);
     store_line(G, se, ev);
     wave_sync();
     const int j = G.ca - 1;
-    if (G.hl == 0) {
-        // M_i = d_i - e^2 / M_{i-1}: the previous pivot stays in a register, and
-        // 1/M_{i-1} is the hardware reciprocal refined by two Newton steps
-        // (r <- r + r(1 - M r)), a shorter dependent chain than an IEEE division
-        const int len = G.half ? G.cb : j;
-        if (len > 0) {
-            const int di = G.half ? -1 : 1;
-            int i = G.half ? nx - 1 : 0;
-            double Mp = sd[i];
-            sM[i] = Mp;
-#pragma unroll 4
-            for (int q = 1; q < len; ++q) {
-                i += di;
-                const double ec = G.half ? se[i] : se[i - 1];
-                double r = __builtin_amdgcn_rcp(Mp);
-                r = __builtin_fma(r, __builtin_fma(-Mp, r, 1.0), r);
-                r = __builtin_fma(r, __builtin_fma(-Mp, r, 1.0), r);
-                const double Mi = __builtin_fma(-ec * ec, r, sd[i]);
-                sM[i] = Mi;
-                Mp = Mi;
+    const int len = G.half ? G.cb : j;  // this lane's chain, without the twist element
+    double *sA = sg, *sP = sp, *sQ = sM;  // alpha_c; q_c and q_{c-1} in one scale
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) {
+        const int c = G.pos(s, EPL);
+        if (G.ok(c) && c >= 1 && c < len) {
+            const int e = G.elem(c);
+            const int ep = G.half ? e + 1 : e - 1;
+            const double ec = G.half ? ev[s] : se[e - 1];
+            sA[e] = ec * ec / (dT[s] * sd[ep]);
+        }
+    }
+    wave_sync();
+    if (G.hl == 0 && len > 0) {  // lanes 0 and 32: the two chains side by side
+        const int di = G.half ? -1 : 1;
+        int e = G.half ? nx - 1 : 0;
+        double q2 = 1.0, q1 = 1.0;  // q_{c-2}, q_{c-1}
+        sP[e] = 1.0;
+        sQ[e] = 1.0;
+        // 16 elements at a time: their alphas are read first and their q stored
+        // after the walk, so that no LDS access waits inside the FMA chain
+        // (the lines share one LDS block, and the compiler cannot move a read
+        // of one above a write of another).
+        int c = 1;
+        for (; c + 16 <= len; c += 16) {
+            double al[16], qv[16], qp[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) al[u] = sA[e + (u + 1) * di];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                qv[u] = __builtin_fma(-al[u], q2, q1);
+                qp[u] = q1;
+                q2 = q1;
+                q1 = qv[u];
             }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                sP[e + (u + 1) * di] = qv[u];
+                sQ[e + (u + 1) * di] = qp[u];
+            }
+            e += 16 * di;
+            const int x = -__builtin_amdgcn_frexp_exp(q1);
+            q1 = __builtin_amdgcn_ldexp(q1, x);
+            q2 = __builtin_amdgcn_ldexp(q2, x);
+        }
+        for (; c < len; ++c) {
+            e += di;
+            const double q = __builtin_fma(-sA[e], q2, q1);
+            sP[e] = q;
+            sQ[e] = q1;
+            q2 = q1;
+            q1 = q;
+        }
+    }
+    wave_sync();
+    // 1/M_c = q_{c-1} / (d_c q_c) for the chain elements, into sM (over q_{c-1})
+    double mv[EPL];
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) {
+        const int c = G.pos(s, EPL);
+        mv[s] = 0.0;
+        if (G.ok(c) && c < len) {
+            const int e = G.elem(c);
+            mv[s] = sQ[e] / (dT[s] * sP[e]);
+            sM[e] = mv[s];
         }
     }
     wave_sync();
     if (lane == 0) {
         double Mj = sd[j];
-        if (j > 0) Mj -= se[j - 1] * se[j - 1] / sM[j - 1];
-        if (j < nx - 1) Mj -= se[j] * se[j] / sM[j + 1];
-        sM[j] = Mj;
+        if (j > 0) Mj -= se[j - 1] * se[j - 1] * sM[j - 1];
+        if (j < nx - 1) Mj -= se[j] * se[j] * sM[j + 1];
+        sM[j] = 1.0 / Mj;
     }
     wave_sync();
-    double mv[EPL];
     bool bad = false;
 #pragma unroll
     for (int s = 0; s < EPL; ++s) {
-        int c = G.pos(s, EPL);
+        const int c = G.pos(s, EPL);
         if (G.ok(c)) {
-            double M = sM[G.elem(c)];
-            if (!(M > 0.0) || !isfinite(M)) bad = true;
-            mv[s] = 1.0 / M;
-        } else {
-            mv[s] = 0.0;
+            if (c == len) mv[s] = sM[G.elem(c)];  // the twist element (chain A)
+            if (!(mv[s] > 0.0) || !isfinite(mv[s])) bad = true;
         }
     }
     wave_sync();
     store_line(G, a.mv + lm, mv);
     store_line(G, a.dT + lm, dT);
-    store_line(G, a.e1 + lm, ev);
+    store_line(G, a.e1 + lm, ev);  // LDS holds this line's dT, e and 1/M
+    wave_sync();
     if (bad) atomicOr(a.flag, kFlagNotSPD);
 }
 
@@ -801,21 +856,89 @@ __device__ void plane_lines_setup(const SetupArgs &a, int k, double *sh) {
     const long long pk = (long long)k * a.nx * ny;
     const int wv = threadIdx.x >> 6;
     const int j2 = (ny - 1) / 2;
-    double *mine = sh + (wv & 1) * 5 * a.nx;
+    double *lds0 = sh, *lds1 = sh + 5 * a.nx;  // the LDS of waves 0 and 1
+    double *mine = (wv & 1) ? lds1 : lds0;
     if (wv == 0) {
-        for (int m = 0; m < j2; ++m) line_setup<EPL>(a, pk, m, m > 0 ? 1 : 0, m - 1, 0, mine);
+        for (int m = 0; m < j2; ++m)
+            line_setup<EPL>(a, pk, m, m > 0 ? 1 : 0, m - 1, 0, mine, mine, mine);
     } else if (wv == 1) {
         for (int m = ny - 1; m > j2; --m)
-            line_setup<EPL>(a, pk, m, m < ny - 1 ? 1 : 0, m + 1, 0, mine);
+            line_setup<EPL>(a, pk, m, m < ny - 1 ? 1 : 0, m + 1, 0, mine, mine, mine);
     }
     __syncthreads();
-    if (wv == 0) {
+    if (wv == 0) {  // the twist line: line j2-1 in wave 0's LDS, j2+1 in wave 1's
         int nnb = 0, n0 = 0, n1 = 0;
+        const double *s0 = lds0, *s1 = lds1;
         if (j2 > 0) { n0 = j2 - 1; ++nnb; }
-        if (j2 < ny - 1) { if (nnb == 0) n0 = j2 + 1; else n1 = j2 + 1; ++nnb; }
-        line_setup<EPL>(a, pk, j2, nnb, n0, n1, mine);
+        if (j2 < ny - 1) {
+            if (nnb == 0) { n0 = j2 + 1; s0 = lds1; }
+            else n1 = j2 + 1;
+            ++nnb;
+        }
+        line_setup<EPL>(a, pk, j2, nnb, n0, n1, mine, s0, s1);
     }
     __syncthreads();
+}
+
+// One neighbour's correction of plane k's blocks (the plane recurrence of
+// Sec. 2.1), element by element over the plane: with b = z./w, z = Pt_nb^{-1} w,
+// the diagonal loses psi^2 b (diagonal Schur blocks) or psi (2b - b P_nb b) psi
+// plus the compensation psi b (w - P_nb z)./t (Newton), and the x- and
+// y-couplings lose psi_u (-b_u P_uv b_v) psi_v.  FROM_BANDS: the plane's first
+// correction, which starts from the assembled bands (no separate copy pass);
+// else the blocks are corrected in place.  The pointers are restrict-qualified:
+// the plane's own blocks, the neighbour's and the work lines do not overlap.
+template <bool FROM_BANDS>
+__device__ __forceinline__ void plane_update(const SetupArgs &a, long long pk, long long pn,
+                                             const double *__restrict__ psi,
+                                             const double *__restrict__ w,
+                                             const double *__restrict__ z) {
+    const int nx = a.nx, ny = a.ny;
+    const long long nxy = (long long)nx * ny;
+    double *__restrict__ dP = a.dP + pk, *__restrict__ xP = a.xP + pk;
+    double *__restrict__ yP = a.f2 + pk;
+    const double *__restrict__ d0 = a.d + pk, *__restrict__ x0 = a.ax + pk;
+    const double *__restrict__ y0 = a.ay + pk;
+    const double *__restrict__ dPn = a.dP + pn, *__restrict__ xPn = a.xP + pn;
+    const double *__restrict__ yPn = a.f2 + pn;
+    const double *__restrict__ t = a.t;
+    for (long long u = threadIdx.x; u < nxy; u += blockDim.x) {
+        const int i = (int)(u % nx), jl = (int)(u / nx);
+        double dv, xv, yv;
+        if constexpr (FROM_BANDS) {
+            dv = d0[u];
+            xv = x0[u];
+            yv = y0[u];
+        } else {
+            dv = dP[u];
+            xv = xP[u];
+            yv = yP[u];
+        }
+        const double b = z[u] / w[u];
+        if (a.schur == 1) {
+            dv -= psi[u] * psi[u] * b;
+        } else {
+            double Pz = dPn[u] * z[u];
+            if (i > 0) Pz += xPn[u - 1] * z[u - 1];
+            if (i < nx - 1) Pz += xPn[u] * z[u + 1];
+            if (jl > 0) Pz += yPn[u - nx] * z[u - nx];
+            if (jl < ny - 1) Pz += yPn[u] * z[u + nx];
+            const double xuu = 2.0 * b - b * dPn[u] * b;
+            dv -= psi[u] * xuu * psi[u];
+            if (i < nx - 1) {
+                const double b1 = z[u + 1] / w[u + 1];
+                xv -= psi[u] * (-b * xPn[u] * b1) * psi[u + 1];
+            }
+            if (jl < ny - 1) {
+                const double bn = z[u + nx] / w[u + nx];
+                yv -= psi[u] * (-b * yPn[u] * bn) * psi[u + nx];
+            }
+            dv += psi[u] * b * (w[u] - Pz) / (t ? t[pk + u] : 1.0);
+        }
+        dP[u] = dv;
+        xP[u] = xv;
+        yP[u] = yv;
+    }
 }
 
 // Plane k: P_k starts as D^_k and loses, for each neighbour plane nb,
@@ -828,18 +951,30 @@ __device__ void plane_setup(const SetupArgs &a, int k, int nnb, int nb0, int nb1
     const int nx = a.nx, ny = a.ny;
     const long long nxy = (long long)nx * ny;
     const long long pk = k * nxy;
-    for (long long u = threadIdx.x; u < nxy; u += blockDim.x) {
-        a.dP[pk + u] = a.d[pk + u];
-        a.xP[pk + u] = a.ax[pk + u];
-        a.f2[pk + u] = a.ay[pk + u];
+    if (nnb == 0) {  // no neighbour plane: the blocks are the assembled bands
+        double *__restrict__ dP = a.dP + pk, *__restrict__ xP = a.xP + pk;
+        double *__restrict__ yP = a.f2 + pk;
+        const double *__restrict__ d0 = a.d + pk, *__restrict__ x0 = a.ax + pk;
+        const double *__restrict__ y0 = a.ay + pk;
+#pragma unroll 4
+        for (long long u = threadIdx.x; u < nxy; u += blockDim.x) {
+            dP[u] = d0[u];
+            xP[u] = x0[u];
+            yP[u] = y0[u];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     for (int q = 0; q < nnb; ++q) {
         const int nb = q == 0 ? nb0 : nb1;
         const long long pn = nb * nxy;
-        const double *psi = a.az + (k < nb ? k : nb) * nxy;
-        for (long long u = threadIdx.x; u < nxy; u += blockDim.x)
-            wbuf[u] = psi[u] * tval(a.t, pk + u);
+        const double *__restrict__ psi = a.az + (k < nb ? k : nb) * nxy;
+        {
+            double *__restrict__ w = wbuf;
+            const double *__restrict__ t = a.t;
+#pragma unroll 4
+            for (long long u = threadIdx.x; u < nxy; u += blockDim.x)
+                w[u] = psi[u] * (t ? t[pk + u] : 1.0);
+        }
         __syncthreads();
         PolPlain<EPL> pol;
         pol.y = make_rsrc(wbuf);
@@ -857,34 +992,8 @@ __device__ void plane_setup(const SetupArgs &a, int k, int nnb, int nb0, int nb1
         F.ny = ny;
         plane_solve<1>(ny, F, pol, lds_x);
         __syncthreads();
-        const double *dPn = a.dP + pn, *xPn = a.xP + pn, *yPn = a.f2 + pn;
-        for (long long u = threadIdx.x; u < nxy; u += blockDim.x) {
-            const int i = (int)(u % nx), jl = (int)(u / nx);
-            const double b = zbuf[u] / wbuf[u];
-            if (a.schur == 1) {
-                a.dP[pk + u] -= psi[u] * psi[u] * b;
-                continue;
-            }
-            double Pz = dPn[u] * zbuf[u];
-            if (i > 0) Pz += xPn[u - 1] * zbuf[u - 1];
-            if (i < nx - 1) Pz += xPn[u] * zbuf[u + 1];
-            if (jl > 0) Pz += yPn[u - nx] * zbuf[u - nx];
-            if (jl < ny - 1) Pz += yPn[u] * zbuf[u + nx];
-            const double xuu = 2.0 * b - b * dPn[u] * b;
-            double dnew = a.dP[pk + u] - psi[u] * xuu * psi[u];
-            if (i < nx - 1) {
-                const double b1 = zbuf[u + 1] / wbuf[u + 1];
-                const double x01 = -b * xPn[u] * b1;
-                a.xP[pk + u] -= psi[u] * x01 * psi[u + 1];
-            }
-            if (jl < ny - 1) {
-                const double bn = zbuf[u + nx] / wbuf[u + nx];
-                const double x0n = -b * yPn[u] * bn;
-                a.f2[pk + u] -= psi[u] * x0n * psi[u + nx];
-            }
-            dnew += psi[u] * b * (wbuf[u] - Pz) / tval(a.t, pk + u);
-            a.dP[pk + u] = dnew;
-        }
+        if (q == 0) plane_update<true>(a, pk, pn, psi, wbuf, zbuf);
+        else plane_update<false>(a, pk, pn, psi, wbuf, zbuf);
         __syncthreads();
     }
     plane_lines_setup<EPL>(a, k, lds_lines);
