@@ -35,7 +35,12 @@ namespace ntd {
 
 namespace {
 
-constexpr int kSetupThreads = 512;  // two chain wavefronts + six helpers for plane-wide work
+// Threads of a factorization workgroup: two chain wavefronts plus helpers for
+// the plane-wide work.  Up to 4 values per lane, 512 (two waves per SIMD); with
+// more, 256, so that a wave may use 512 registers (VGPRs and AGPRs) and spill
+// into AGPRs rather than scratch.
+template <int EPL>
+constexpr int kSetupThreads = EPL <= 4 ? 512 : 256;
 
 // ---------------------------------------------------------------------------
 // Buffer I/O.
@@ -1032,13 +1037,13 @@ __device__ __forceinline__ void setup_twist(const SetupArgs &a, double *smem) {
 }
 
 template <int EPL>
-__global__ void __launch_bounds__(kSetupThreads) k_setup_halves(SetupArgs a) {
+__global__ void __launch_bounds__(kSetupThreads<EPL>) k_setup_halves(SetupArgs a) {
     extern __shared__ double smem[];
     setup_halves<EPL>(a, blockIdx.x, smem);
 }
 
 template <int EPL>
-__global__ void __launch_bounds__(kSetupThreads) k_setup_twist(SetupArgs a) {
+__global__ void __launch_bounds__(kSetupThreads<EPL>) k_setup_twist(SetupArgs a) {
     extern __shared__ double smem[];
     setup_twist<EPL>(a, smem);
 }
@@ -1046,13 +1051,13 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup_twist(SetupArgs a) {
 // A batch of independent systems (blockIdx.y selects the system's arguments):
 // their level-3 chains run at the same time.
 template <int EPL>
-__global__ void __launch_bounds__(kSetupThreads) k_setup_halves_b(const SetupArgs *tab) {
+__global__ void __launch_bounds__(kSetupThreads<EPL>) k_setup_halves_b(const SetupArgs *tab) {
     extern __shared__ double smem[];
     setup_halves<EPL>(load_uniform(tab + blockIdx.y), blockIdx.x, smem);
 }
 
 template <int EPL>
-__global__ void __launch_bounds__(kSetupThreads) k_setup_twist_b(const SetupArgs *tab) {
+__global__ void __launch_bounds__(kSetupThreads<EPL>) k_setup_twist_b(const SetupArgs *tab) {
     extern __shared__ double smem[];
     setup_twist<EPL>(load_uniform(tab + blockIdx.y), smem);
 }
@@ -1071,8 +1076,8 @@ hipError_t setup_impl(const SetupArgs &a, hipStream_t s) {
         (void)hipFuncSetAttribute((const void *)k_setup_twist<EPL>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     }
-    hipLaunchKernelGGL((k_setup_halves<EPL>), dim3(2), dim3(kSetupThreads), sh, s, a);
-    hipLaunchKernelGGL((k_setup_twist<EPL>), dim3(1), dim3(kSetupThreads), sh, s, a);
+    hipLaunchKernelGGL((k_setup_halves<EPL>), dim3(2), dim3(kSetupThreads<EPL>), sh, s, a);
+    hipLaunchKernelGGL((k_setup_twist<EPL>), dim3(1), dim3(kSetupThreads<EPL>), sh, s, a);
     return hipGetLastError();
 }
 
@@ -1085,8 +1090,8 @@ hipError_t setup_batch_impl(const SetupArgs *tab, int count, int max_nx, hipStre
         (void)hipFuncSetAttribute((const void *)k_setup_twist_b<EPL>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     }
-    hipLaunchKernelGGL((k_setup_halves_b<EPL>), dim3(2, count), dim3(kSetupThreads), sh, s, tab);
-    hipLaunchKernelGGL((k_setup_twist_b<EPL>), dim3(1, count), dim3(kSetupThreads), sh, s, tab);
+    hipLaunchKernelGGL((k_setup_halves_b<EPL>), dim3(2, count), dim3(kSetupThreads<EPL>), sh, s, tab);
+    hipLaunchKernelGGL((k_setup_twist_b<EPL>), dim3(1, count), dim3(kSetupThreads<EPL>), sh, s, tab);
     return hipGetLastError();
 }
 
