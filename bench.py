@@ -94,6 +94,10 @@ def parse():
                     help="skip the solve with the filter network's t (trained first)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle PCG iterations sampled")
+    ap.add_argument("--cpu-oracle-solve", action="store_true",
+                    help="no GPU: the FP64 oracle's whole solve of the workload to --tol "
+                         "(--maxit), single thread; prints its iterations, true residual, "
+                         "setup and solve times as one JSON line (minutes at 256^3)")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-precond-legs", action="store_true",
                     help="skip the one-off solves with eq. com and with the diagonal block alone")
@@ -186,12 +190,14 @@ def cpu_model() -> str:
     return "model unknown"
 
 
-def cpu_baseline_child(args):
+def cpu_baseline_child(args, full: bool = False):
     """The CPU baseline's own process (started by the benchmark before it
     touches the GPU; it imports no torch): the FP64 oracle, single thread, on
     the benchmark's workload -- assembly, setup and the ILU(0) factorization on
     the full grid, then --cpu-iters PCG iterations with the same
-    preconditioner.  Prints one JSON object."""
+    preconditioner (full: the whole solve to --tol within --maxit, and the true
+    relative residual of its solution).  Prints one JSON object."""
+    import numpy as np
     import oracle as O
     import workloads as W
     n = args.n
@@ -201,13 +207,20 @@ def cpu_baseline_child(args):
     F = O.setup(bands, mode=args.schur)
     dt = O.ilu0(bands, 2)[0] if args.smoother != "none" else None
     t1 = time.perf_counter()
-    x, it, rr, st, hist = O.pcg(bands, F, w["b"], 1e-30, args.cpu_iters, dt=dt,
+    x, it, rr, st, hist = O.pcg(bands, F, w["b"], args.tol if full else 1e-30,
+                                args.maxit if full else args.cpu_iters, dt=dt,
                                 smoother=args.smoother)
     t2 = time.perf_counter()
-    print(json.dumps({"setup_s": t1 - t0, "iters": it, "solve_s": t2 - t1,
-                      "s_per_iter": (t2 - t1) / max(it, 1), "status": st,
-                      "recursive_relres_last": float(hist[-1]) if len(hist) else None,
-                      "model": cpu_model(), "host_cores": os.cpu_count() or 0}), flush=True)
+    out = {"setup_s": t1 - t0, "iters": it, "solve_s": t2 - t1,
+           "s_per_iter": (t2 - t1) / max(it, 1), "status": st,
+           "recursive_relres_last": float(hist[-1]) if len(hist) else None,
+           "model": cpu_model(), "host_cores": os.cpu_count() or 0}
+    if full:
+        out.update({"workload": "jump%d" % n, "schur": args.schur, "smoother": args.smoother,
+                    "tol": args.tol, "overall_s": t2 - t0, "threads": 1,
+                    "true_relres": float(np.linalg.norm(w["b"] - O.spmv(bands, x))
+                                         / np.linalg.norm(w["b"]))})
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline_start(args):
@@ -670,8 +683,8 @@ def learned_suite(args):
 
 def main():
     args = parse()
-    if args.cpu_baseline_child:
-        cpu_baseline_child(args)
+    if args.cpu_baseline_child or args.cpu_oracle_solve:
+        cpu_baseline_child(args, full=args.cpu_oracle_solve)
         return
     if args.gpus != 1:
         print("bench.py: runs on one GPU only (--gpus 1); the level-3 twist split "
