@@ -21,7 +21,7 @@
 namespace {
 
 constexpr int kTB = 256;
-constexpr int kTMaxBlocks = 2048;
+constexpr int kTMaxBlocks = ntd::kMaxBlocks;  // the partials of a handle hold this many
 
 inline int tblocks(long long n) {
     long long b = (n + kTB - 1) / kTB;
@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(kTB) k_tgt_dir(double *__restrict__ p, double 
 }
 
 // Per block: the entry of largest magnitude (the first in index order on
-// ties), as a signed value.
+// ties), as a signed value; a NaN entry wins, so that the caller sees it.
 __global__ void __launch_bounds__(kTB) k_tgt_maxabs(const double *__restrict__ v, long long n,
                                                     double *__restrict__ part) {
     __shared__ double best[kTB];
@@ -68,17 +68,19 @@ __global__ void __launch_bounds__(kTB) k_tgt_maxabs(const double *__restrict__ v
     for (long long i = blockIdx.x * (long long)kTB + threadIdx.x; i < n;
          i += (long long)gridDim.x * kTB) {
         const double x = v[i];
-        if (bi < 0 || fabs(x) > fabs(b)) { b = x; bi = i; }
+        if (bi < 0 || (b == b && !(fabs(x) <= fabs(b)))) { b = x; bi = i; }
     }
     best[threadIdx.x] = b;
     where[threadIdx.x] = bi < 0 ? n : bi;
     __syncthreads();
     for (int h = kTB / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) {
-            const double o = best[threadIdx.x + h];
+            const double o = best[threadIdx.x + h], mine = best[threadIdx.x];
             const long long oi = where[threadIdx.x + h];
-            if (fabs(o) > fabs(best[threadIdx.x]) ||
-                (fabs(o) == fabs(best[threadIdx.x]) && oi < where[threadIdx.x])) {
+            const bool nan_o = o != o, nan_m = mine != mine;
+            if ((nan_o && !nan_m) || (!nan_m && fabs(o) > fabs(mine)) ||
+                (nan_o == nan_m && fabs(o) == fabs(mine) && oi < where[threadIdx.x]) ||
+                (nan_o && nan_m && oi < where[threadIdx.x])) {
                 best[threadIdx.x] = o;
                 where[threadIdx.x] = oi;
             }
@@ -118,8 +120,10 @@ int signed_maxabs(const double *v, long long n, double *part, double *out, hipSt
     TCK(hipMemcpyAsync(h.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, s));
     TCK(hipStreamSynchronize(s));
     double b = 0.0;
-    for (int i = 0; i < nb; ++i)
+    for (int i = 0; i < nb; ++i) {
+        if (h[i] != h[i]) { b = h[i]; break; }  // NaN: reported as not finite
         if (fabs(h[i]) > fabs(b)) b = h[i];
+    }
     *out = b;
     return NTD_OK;
 }

@@ -86,6 +86,26 @@ def binva_targets(kappas, bcs, starts, schur: str = "newton", outer: int = 20,
     return out, lams
 
 
+def train_on_binva_targets(kappas, bcs, starts, params, epochs: int = 20, lr: float = 2e-3,
+                           outer: int = 8, inner_tol: float = 1e-6, progress=None):
+    """A network trained on the method's own targets: for each field the
+    smallest-eigenvalue eigenvector of B(1)^{-1}A with Newton Schur blocks
+    (binva_targets from `starts`, `outer` inverse iterations, inner solves to
+    inner_tol), then Adam for `epochs` epochs from the initial weights
+    `params`.  Returns (net, loss per epoch, seconds spent on the targets,
+    eigenvalue estimates)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tgt, lams = binva_targets(kappas, bcs, starts, schur="newton", outer=outer,
+                              inner_tol=inner_tol, inner_maxit=200000, progress=progress)
+    torch.cuda.synchronize()
+    t_targets = time.perf_counter() - t0
+    net = FilterNet(params, device=kappas[0].device)
+    hist = train(net, kappas, tgt, epochs, lr)
+    net.release_workspaces()
+    return net, hist, t_targets, lams
+
+
 def train(net: FilterNet, kappas, targets, epochs: int, lr: float, seed: int = 0):
     """Adam over the fields in a seeded random order each epoch; returns the
     mean loss of every epoch."""

@@ -19,10 +19,12 @@ Asserted, as observed on one MI355X (and at 32^3 by the benchmark suite):
     (observed 74-99.7 %; the eigenvector changes sign, and a positive t
     cannot follow it);
   * the exact target gains nothing: on every field it takes at least as many
-    iterations as t = 1 (observed: 41, 28, 13, 12 against 21, 11, 7, 6);
+    iterations as t = 1 (observed: 41, 24, 13, 12 against 21, 11, 7, 6);
   * the network's t is never worse than t = 1 by more than max(2, 10 %) on a
-    field (observed: 15, 11, 7, 6 -- one field 29 % faster, three the same;
-    on 8 fields at 32^3 the suite saw 7 the same and one 9 % slower).
+    field (observed: 17, 11, 7, 6 -- one field 19 % faster, three the same;
+    on 8 fields at 32^3 the suite saw 7 the same and one 9 % slower).  The
+    counts move by a few iterations with rounding-level changes of the
+    factorization, so the bars are inequalities.
 """
 from __future__ import annotations
 
@@ -48,15 +50,17 @@ def test_learned_filter_gain_on_inverse_iteration_targets():
     bc = W.BC_ALL_DIRICHLET
     kap = [G(W.kappa_mixture(N, 10000 + i)) for i in range(16)]
     starts = [G(W.filter_random(N, N, N, 40000 + i)) for i in range(16)]
-    tgt, lams = Lr.binva_targets(kap, [bc] * 16, starts, schur="newton", outer=8,
-                                 inner_tol=1e-6, inner_maxit=200000)
+    tgt, lams = Lr.binva_targets(kap, [bc] * 16, [s.clone() for s in starts], schur="newton",
+                                 outer=8, inner_tol=1e-6, inner_maxit=200000)
     floor_frac = [float((t <= 1e-3).double().mean()) for t in tgt]
     print("training targets: lambda %s, at the floor %s"
           % (["%.2e" % x for x in lams], ["%.3f" % f for f in floor_frac]))
     assert all(0.0 < x < 1.0 for x in lams)
     assert min(floor_frac) >= 0.7
-    net = P.FilterNet(W.cnn_init_params(0))
-    hist = Lr.train(net, kap, tgt, 20, 2e-3)
+    # the benchmark's training helper: the same targets, then 20 epochs of Adam
+    net, hist, _, lams2 = Lr.train_on_binva_targets(kap, [bc] * 16, starts,
+                                                    W.cnn_init_params(0), epochs=20)
+    assert lams2 == lams
     print("loss first / last epoch: %.4e / %.4e" % (hist[0], hist[-1]))
     assert hist[-1] < hist[0]
 

@@ -83,3 +83,20 @@ def test_vec_normalize():
     assert np.array_equal(C(g2), v * (1.0 / -9.0))
     with pytest.raises(P.NTDError):
         P.vec_normalize(G(np.zeros(10)))
+
+
+@pytest.mark.parametrize("where", [0, 777, 100002])
+def test_vec_normalize_rejects_nan_and_zero(where):
+    """A NaN entry anywhere (first, inside, last element) wins the largest-
+    magnitude reduction, so the scale is not finite and the call fails with
+    NTD_EINVAL; so does an all-zero vector."""
+    import paper_1909_09771_amd as P
+    v = np.random.default_rng(4).standard_normal(100003)
+    v[5000] = 50.0                     # a larger finite entry elsewhere
+    v[where] = np.nan
+    with pytest.raises(P.NTDError) as e:
+        P.vec_normalize(G(v), floor=1e-3)
+    assert e.value.status == P.EINVAL
+    with pytest.raises(P.NTDError) as e:
+        P.vec_normalize(G(np.zeros(4097)), floor=1e-3)
+    assert e.value.status == P.EINVAL
