@@ -123,14 +123,23 @@ __device__ __forceinline__ bool in_block(long long p, int b, const IluGrid &g) {
     return g.nblocks == 1 || ((p >= g.M) == (b == 1));
 }
 
-// Grid line (j, k) at tile row w, line anti-diagonal ll of tile (b, ty, tz),
-// or false if it does not exist.
-__device__ __forceinline__ bool tile_line(const IluGrid &g, int b, int ty, int tz, int w, int ll,
-                                          int &j, int &k) {
+// Grid line (j, k) at tile row w, line anti-diagonal ll of tile (ty, tz) of
+// the block that spans planes kb0..kb1, or false if it does not exist.
+__device__ __forceinline__ bool tile_line(const IluGrid &g, int kb0, int kb1, int ty, int tz,
+                                          int w, int ll, int &j, int &k) {
     const int kl = ll - w;
     j = ty * kIluTile + w;
-    k = g.kb0[b] + tz * kIluTile + kl;
-    return kl >= 0 && kl < kIluTile && j < g.ny && k <= g.kb1[b];
+    k = kb0 + tz * kIluTile + kl;
+    return kl >= 0 && kl < kIluTile && j < g.ny && k <= kb1;
+}
+
+// The plane range of block b, read once per workgroup: selected from both
+// entries rather than indexed, so that it stays in scalar registers (an
+// indexed read of the argument would be a scalar memory load, and its wait
+// would also drain the LDS accesses in flight, on every line diagonal).
+__device__ __forceinline__ void block_planes(const IluGrid &g, int b, int &kb0, int &kb1) {
+    kb0 = b == 0 ? g.kb0[0] : g.kb0[1];
+    kb1 = b == 0 ? g.kb1[0] : g.kb1[1];
 }
 
 // Does row M (the block split) fall strictly inside the x-line starting at base?
@@ -224,6 +233,8 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, 
     extern __shared__ double lds[];  // two anti-diagonals of kIluTile lines, [s][lane]
     int b, ty, tz;
     if (!tile_of(g, L, b, ty, tz)) return;
+    int kb0, kb1;
+    block_planes(g, b, kb0, kb1);
     const IluBufs B(P);
     // the wavefront index is uniform per wavefront; say so, or every buffer
     // access with an offset derived from it becomes a per-lane loop
@@ -239,7 +250,7 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, 
     // takes from LDS instead, are never used.
     auto load = [&](int ll, IluLine<E> &d) {
         int j, k;
-        const bool ok = tile_line(g, b, ty, tz, w, ll, j, k);
+        const bool ok = tile_line(g, kb0, kb1, ty, tz, w, ll, j, k);
         const unsigned so = ok ? 8u * (unsigned)(((long long)k * g.ny + j) * nx) : 0u;
         const unsigned sy = ok && j > 0 ? so - nx8 : so;
         const unsigned sz = ok && k > 0 ? so - nxy8 : so;
@@ -258,7 +269,7 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, 
     };
     auto solve = [&](int ll, const IluLine<E> &d) {
         int j, k;
-        if (!tile_line(g, b, ty, tz, w, ll, j, k)) return;
+        if (!tile_line(g, kb0, kb1, ty, tz, w, ll, j, k)) return;
         const int kl = ll - w;
         const long long base = ((long long)k * g.ny + j) * nx;
         const unsigned so = 8u * (unsigned)base;
@@ -345,6 +356,8 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_bwd_tile(IluGrid g, int L, 
     extern __shared__ double lds[];
     int b, ty, tz;
     if (!tile_of(g, L, b, ty, tz)) return;
+    int kb0, kb1;
+    block_planes(g, b, kb0, kb1);
     const IluBufs B(P);
     // the wavefront index is uniform per wavefront; say so, or every buffer
     // access with an offset derived from it becomes a per-lane loop
@@ -356,7 +369,7 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_bwd_tile(IluGrid g, int L, 
     // every load issued, as in the forward sweep
     auto load = [&](int ll, IluLine<E> &d) {
         int j, k;
-        const bool ok = tile_line(g, b, ty, tz, w, ll, j, k);
+        const bool ok = tile_line(g, kb0, kb1, ty, tz, w, ll, j, k);
         const unsigned so = ok ? 8u * (unsigned)(((long long)k * g.ny + j) * nx) : 0u;
         const unsigned sy = ok && j < g.ny - 1 ? so + nx8 : so;
         const unsigned sz = ok && k < g.nz - 1 ? so + nxy8 : so;
@@ -370,7 +383,7 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_bwd_tile(IluGrid g, int L, 
     };
     auto solve = [&](int ll, const IluLine<E> &d) {
         int j, k;
-        if (!tile_line(g, b, ty, tz, w, ll, j, k)) return;
+        if (!tile_line(g, kb0, kb1, ty, tz, w, ll, j, k)) return;
         const int kl = ll - w;
         const long long base = ((long long)k * g.ny + j) * nx;
         const unsigned so = 8u * (unsigned)base;
