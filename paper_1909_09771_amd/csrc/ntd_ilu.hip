@@ -186,6 +186,22 @@ __device__ __forceinline__ void ld(rsrc_t r, unsigned so, const IluLanes<E, REV>
     }
 }
 
+// ld, or (use false) the same load with every lane out of bounds: zeros, and
+// no data moved through the cache path.
+template <int E, bool REV, bool VEC>
+__device__ __forceinline__ void ld_if(rsrc_t r, unsigned so, const IluLanes<E, REV> &L,
+                                      double (&v)[E], bool use) {
+    if constexpr (VEC) {
+        double t[E];
+        vload(r, use ? L.co : kOOB, so, t);
+#pragma unroll
+        for (int s = 0; s < E; ++s) v[s] = REV ? t[E - 1 - s] : t[s];
+    } else {
+#pragma unroll
+        for (int s = 0; s < E; ++s) v[s] = bload((double *)nullptr, r, use ? L.eo[s] : kOOB, so);
+    }
+}
+
 template <int E, bool REV, bool VEC>
 __device__ __forceinline__ void st(rsrc_t r, unsigned so, const IluLanes<E, REV> &L,
                                    const double (&v)[E]) {
@@ -263,9 +279,9 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, 
             d.cx[s] = bload((double *)nullptr, B.ax, o, so);
         }
         ld<E, false, VEC>(B.ay, sy, Ln, d.cy);
-        ld<E, false, VEC>(B.y, sy, Ln, d.vy);  // used at w = 0: tile ty-1
+        ld_if<E, false, VEC>(B.y, sy, Ln, d.vy, w == 0);  // used at w = 0: tile ty-1
         ld<E, false, VEC>(B.az, sz, Ln, d.cz);
-        ld<E, false, VEC>(B.y, sz, Ln, d.vz);  // used at ll - w = 0: tile tz-1
+        ld_if<E, false, VEC>(B.y, sz, Ln, d.vz, ll - w == 0);  // at ll - w = 0: tile tz-1
     };
     auto solve = [&](int ll, const IluLine<E> &d) {
         int j, k;
@@ -377,9 +393,9 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_bwd_tile(IluGrid g, int L, 
         ld<E, true, VEC>(B.di, so, Ln, d.di);
         ld<E, true, VEC>(B.ax, so, Ln, d.cx);
         ld<E, true, VEC>(B.ay, so, Ln, d.cy);
-        ld<E, true, VEC>(B.y, sy, Ln, d.vy);  // used at w = kIluTile-1: tile ty+1
+        ld_if<E, true, VEC>(B.y, sy, Ln, d.vy, w == kIluTile - 1);  // tile ty+1
         ld<E, true, VEC>(B.az, so, Ln, d.cz);
-        ld<E, true, VEC>(B.y, sz, Ln, d.vz);  // used at ll - w = kIluTile-1: tile tz+1
+        ld_if<E, true, VEC>(B.y, sz, Ln, d.vz, ll - w == kIluTile - 1);  // tile tz+1
     };
     auto solve = [&](int ll, const IluLine<E> &d) {
         int j, k;
