@@ -54,9 +54,11 @@ size_t layout(ntd_handle *h, void *ws, int nx, int ny, int nz, int prec, int smo
         h->rp = (void *)c.take<char>(npack * tsz);
     }
     h->dt = h->dtinv = h->zi = h->tv = nullptr;
+    h->fcoef = nullptr;
     if (smoother != NTD_SMOOTHER_NONE) {
         double **ilu[] = {&h->dt, &h->dtinv, &h->zi, &h->tv};
         for (double **a : ilu) *a = c.take<double>(N);
+        if (prec == NTD_PREC_MIXED) h->fcoef = c.take<float>(4 * N);
     }
     const size_t setup_scr = 6 * (size_t)nxy * sizeof(double);
     const size_t apply_scr = 2 * (size_t)ny * lane_slots * tsz;
@@ -137,7 +139,7 @@ int ntd_solve_any(ntd_handle *h, const double *r, const double *zi, double *z, d
 
 // z = B_ILU^{-1} r (block-diagonal ILU(0)).
 int ilu_internal(ntd_handle *h, const double *r, double *z, hipStream_t s) {
-    CK(ntd::launch_ilu_apply(h->ilu, h->ax, h->ay, h->az, h->dtinv, r, z, s));
+    CK(ntd::launch_ilu_apply(h->ilu, h->ax, h->ay, h->az, h->dtinv, h->fcoef, r, z, s));
     return NTD_OK;
 }
 
@@ -314,6 +316,8 @@ int setup_handle(int nx, int ny, int nz, const double *kappa, const int *bc, con
     HK(ntd::launch_setup(handle_setup_args(h, t), h->epl, s));
     if (smoother != NTD_SMOOTHER_NONE)
         HK(ntd::launch_ilu_factor(h->ilu, h->d, h->ax, h->ay, h->az, h->dt, h->dtinv, h->flag, s));
+    if (h->fcoef)
+        HK(ntd::launch_ilu_coef_f32(h->ilu, h->ax, h->ay, h->az, h->dtinv, h->fcoef, s));
     if ((st = handle_flag_async(h, &hflag, s)) != NTD_OK) goto fail;
     HK(hipStreamSynchronize(s));
     if (hflag & ntd::kFlagNotSPD) FAIL(NTD_ENOTSPD);

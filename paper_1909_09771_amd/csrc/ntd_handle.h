@@ -12,6 +12,7 @@ struct ntd_handle {
     int nx, ny, nz, prec, schur, smoother, epl;
     ntd::IluGrid ilu;                         // ILU(0) level schedule (smoother only)
     double *dt, *dtinv, *zi, *tv;             // ILU(0) diagonal, its inverse, two work vectors
+    float *fcoef;                             // MIXED: ax, ay, az, 1/dt in FP32 for the ILU(0) sweeps
     long long N, nxy, npack;                  // npack = ny*nz*64*epl packed slots
     size_t used;
     double *d, *ax, *ay, *az;                 // bands of A

@@ -153,8 +153,8 @@ __device__ __forceinline__ bool cut_by_split(const IluGrid &g, long long base) {
 // byte offset co (kOOB when outside the line).
 template <int E, bool REV>
 struct IluLanes {
-    unsigned eo[E];
-    unsigned co;
+    unsigned eo[E], eo4[E];  // for 8- and 4-byte arrays
+    unsigned co, co4;
     __device__ IluLanes(int nx) {
         const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -162,9 +162,11 @@ struct IluLanes {
             const int c = lane * E + s;
             const int i = REV ? 64 * E - 1 - c : c;
             eo[s] = i < nx ? 8u * (unsigned)i : kOOB;
+            eo4[s] = i < nx ? 4u * (unsigned)i : kOOB;
         }
         const int i0 = REV ? 64 * E - E - lane * E : lane * E;
         co = i0 + E - 1 < nx ? 8u * (unsigned)i0 : kOOB;
+        co4 = i0 + E - 1 < nx ? 4u * (unsigned)i0 : kOOB;
     }
     __device__ int elem(int s) const {
         const int c = (threadIdx.x & 63) * E + s;
@@ -183,6 +185,24 @@ __device__ __forceinline__ void ld(rsrc_t r, unsigned so, const IluLanes<E, REV>
     } else {
 #pragma unroll
         for (int s = 0; s < E; ++s) v[s] = bload((double *)nullptr, r, L.eo[s], so);
+    }
+}
+
+// A coefficient line of type CT (double, or float in MIXED): so is the byte
+// offset of the line in an 8-byte array (halved for a 4-byte one).
+template <int E, bool REV, bool VEC, typename CT>
+__device__ __forceinline__ void ldc(rsrc_t r, unsigned so, const IluLanes<E, REV> &L,
+                                    CT (&v)[E]) {
+    if constexpr (sizeof(CT) == 8) {
+        ld<E, REV, VEC>(r, so, L, v);
+    } else if constexpr (VEC) {
+        CT t[E];
+        vload(r, L.co4, so >> 1, t);
+#pragma unroll
+        for (int s = 0; s < E; ++s) v[s] = REV ? t[E - 1 - s] : t[s];
+    } else {
+#pragma unroll
+        for (int s = 0; s < E; ++s) v[s] = bload((CT *)nullptr, r, L.eo4[s], so >> 1);
     }
 }
 
@@ -220,19 +240,24 @@ __device__ __forceinline__ void st(rsrc_t r, unsigned so, const IluLanes<E, REV>
 // results inside the tile (loaded one anti-diagonal ahead): the right-hand
 // side (forward) or forward result (backward), 1/dt, the couplings, and the
 // neighbour lines that lie in earlier tiles (zero when absent).
-template <int E>
+// The coefficients (1/dt and the couplings) are stored as CT and used in FP64.
+template <int E, typename CT>
 struct IluLine {
-    double rv[E], di[E], cx[E], cy[E], cz[E], vy[E], vz[E];
+    double rv[E], vy[E], vz[E];
+    CT di[E], cx[E], cy[E], cz[E];
 };
 
+template <typename CT>
 struct IluPtrs {
-    const double *ax, *ay, *az, *di, *r;
+    const CT *ax, *ay, *az, *di;
+    const double *r;
     double *y;
 };
 
 struct IluBufs {
     rsrc_t ax, ay, az, di, r, y;
-    __device__ explicit IluBufs(const IluPtrs &p)
+    template <typename CT>
+    __device__ explicit IluBufs(const IluPtrs<CT> &p)
         : ax(make_rsrc(p.ax)), ay(make_rsrc(p.ay)), az(make_rsrc(p.az)), di(make_rsrc(p.di)),
           r(make_rsrc(p.r)), y(make_rsrc(p.y)) {}
 };
@@ -244,8 +269,8 @@ __device__ __forceinline__ bool same_block(const IluGrid &g, long long base, lon
 
 // Forward sweep (Dt + L) y = r on the tiles of anti-diagonal L:
 // y_p = (r_p - sum over kept lower neighbours q of a_qp y_q) / dt_p.
-template <int E, bool VEC>
-__global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, IluPtrs P) {
+template <int E, bool VEC, typename CT>
+__global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, IluPtrs<CT> P) {
     extern __shared__ double lds[];  // two anti-diagonals of kIluTile lines, [s][lane]
     int b, ty, tz;
     if (!tile_of(g, L, b, ty, tz)) return;
@@ -264,26 +289,29 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, 
     // waits before the next solve unable to count, and they would drain the
     // loads in flight.  Values of absent neighbours, and neighbours that solve
     // takes from LDS instead, are never used.
-    auto load = [&](int ll, IluLine<E> &d) {
+    auto load = [&](int ll, IluLine<E, CT> &d) {
         int j, k;
         const bool ok = tile_line(g, kb0, kb1, ty, tz, w, ll, j, k);
         const unsigned so = ok ? 8u * (unsigned)(((long long)k * g.ny + j) * nx) : 0u;
         const unsigned sy = ok && j > 0 ? so - nx8 : so;
         const unsigned sz = ok && k > 0 ? so - nxy8 : so;
         ld<E, false, VEC>(B.r, so, Ln, d.rv);
-        ld<E, false, VEC>(B.di, so, Ln, d.di);
+        ldc<E, false, VEC>(B.di, so, Ln, d.di);
         // ax of element i-1 (0 at i = 0 and past the line)
 #pragma unroll
         for (int s = 0; s < E; ++s) {
-            const unsigned o = (Ln.eo[s] != kOOB && Ln.elem(s) > 0) ? Ln.eo[s] - 8u : kOOB;
-            d.cx[s] = bload((double *)nullptr, B.ax, o, so);
+            const bool in = Ln.eo[s] != kOOB && Ln.elem(s) > 0;
+            if constexpr (sizeof(CT) == 8)
+                d.cx[s] = bload((CT *)nullptr, B.ax, in ? Ln.eo[s] - 8u : kOOB, so);
+            else
+                d.cx[s] = bload((CT *)nullptr, B.ax, in ? Ln.eo4[s] - 4u : kOOB, so >> 1);
         }
-        ld<E, false, VEC>(B.ay, sy, Ln, d.cy);
+        ldc<E, false, VEC>(B.ay, sy, Ln, d.cy);
         ld_if<E, false, VEC>(B.y, sy, Ln, d.vy, w == 0);  // used at w = 0: tile ty-1
-        ld<E, false, VEC>(B.az, sz, Ln, d.cz);
+        ldc<E, false, VEC>(B.az, sz, Ln, d.cz);
         ld_if<E, false, VEC>(B.y, sz, Ln, d.vz, ll - w == 0);  // at ll - w = 0: tile tz-1
     };
-    auto solve = [&](int ll, const IluLine<E> &d) {
+    auto solve = [&](int ll, const IluLine<E, CT> &d) {
         int j, k;
         if (!tile_line(g, kb0, kb1, ty, tz, w, ll, j, k)) return;
         const int kl = ll - w;
@@ -311,7 +339,7 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, 
                 if (yk) c -= d.cy[s] * ny_[s];
                 if (zk) c -= d.cz[s] * nz_[s];
                 v[s] = Ln.eo[s] != kOOB ? d.di[s] * c : 0.0;
-                a[s] = -d.di[s] * d.cx[s];
+                a[s] = -(double)d.di[s] * (double)d.cx[s];
             }
         } else {
 #pragma unroll
@@ -325,7 +353,7 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, 
                     if (j > 0 && kept(p - nx, p, g)) c -= d.cy[s] * ny_[s];
                     if (k > 0 && kept(p - g.nxy, p, g)) c -= d.cz[s] * nz_[s];
                     v[s] = d.di[s] * c;
-                    if (i > 0 && kept(p - 1, p, g)) a[s] = -d.di[s] * d.cx[s];
+                    if (i > 0 && kept(p - 1, p, g)) a[s] = -(double)d.di[s] * (double)d.cx[s];
                 }
             }
         }
@@ -343,7 +371,7 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, 
         }
     };
     constexpr int NL = 2 * kIluTile - 1;
-    IluLine<E> A, Bq;
+    IluLine<E, CT> A, Bq;
 #pragma unroll
     for (int s = 0; s < E; ++s) A.cy[s] = A.cz[s] = A.vy[s] = A.vz[s] = Bq.cy[s] = Bq.cz[s] =
         Bq.vy[s] = Bq.vz[s] = 0.0;
@@ -367,8 +395,8 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_fwd_tile(IluGrid g, int L, 
 // (visited in decreasing order): z_p = y_p - (sum over kept upper neighbours q
 // of a_pq z_q) / dt_p.  Lanes take the positions of the line in reverse
 // (c = 0 is element nx-1 padded to 64*E), so the recurrence runs forward in c.
-template <int E, bool VEC>
-__global__ void __launch_bounds__(kIluThreads) k_ilu_bwd_tile(IluGrid g, int L, IluPtrs P) {
+template <int E, bool VEC, typename CT>
+__global__ void __launch_bounds__(kIluThreads) k_ilu_bwd_tile(IluGrid g, int L, IluPtrs<CT> P) {
     extern __shared__ double lds[];
     int b, ty, tz;
     if (!tile_of(g, L, b, ty, tz)) return;
@@ -383,21 +411,21 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_bwd_tile(IluGrid g, int L, 
     const unsigned nx8 = 8u * nx, nxy8 = 8u * (unsigned)g.nxy;
     const IluLanes<E, true> Ln(nx);
     // every load issued, as in the forward sweep
-    auto load = [&](int ll, IluLine<E> &d) {
+    auto load = [&](int ll, IluLine<E, CT> &d) {
         int j, k;
         const bool ok = tile_line(g, kb0, kb1, ty, tz, w, ll, j, k);
         const unsigned so = ok ? 8u * (unsigned)(((long long)k * g.ny + j) * nx) : 0u;
         const unsigned sy = ok && j < g.ny - 1 ? so + nx8 : so;
         const unsigned sz = ok && k < g.nz - 1 ? so + nxy8 : so;
         ld<E, true, VEC>(B.y, so, Ln, d.rv);  // the forward result of this line
-        ld<E, true, VEC>(B.di, so, Ln, d.di);
-        ld<E, true, VEC>(B.ax, so, Ln, d.cx);
-        ld<E, true, VEC>(B.ay, so, Ln, d.cy);
+        ldc<E, true, VEC>(B.di, so, Ln, d.di);
+        ldc<E, true, VEC>(B.ax, so, Ln, d.cx);
+        ldc<E, true, VEC>(B.ay, so, Ln, d.cy);
         ld_if<E, true, VEC>(B.y, sy, Ln, d.vy, w == kIluTile - 1);  // tile ty+1
-        ld<E, true, VEC>(B.az, so, Ln, d.cz);
+        ldc<E, true, VEC>(B.az, so, Ln, d.cz);
         ld_if<E, true, VEC>(B.y, sz, Ln, d.vz, ll - w == kIluTile - 1);  // tile tz+1
     };
-    auto solve = [&](int ll, const IluLine<E> &d) {
+    auto solve = [&](int ll, const IluLine<E, CT> &d) {
         int j, k;
         if (!tile_line(g, kb0, kb1, ty, tz, w, ll, j, k)) return;
         const int kl = ll - w;
@@ -425,7 +453,7 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_bwd_tile(IluGrid g, int L, 
                 if (yk) c += d.cy[s] * ny_[s];
                 if (zk) c += d.cz[s] * nz_[s];
                 v[s] = Ln.eo[s] != kOOB ? d.rv[s] - d.di[s] * c : 0.0;
-                a[s] = i < nx - 1 ? -d.di[s] * d.cx[s] : 0.0;
+                a[s] = i < nx - 1 ? -(double)d.di[s] * (double)d.cx[s] : 0.0;
             }
         } else {
 #pragma unroll
@@ -439,7 +467,7 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_bwd_tile(IluGrid g, int L, 
                     if (j < g.ny - 1 && kept(p, p + nx, g)) c += d.cy[s] * ny_[s];
                     if (k < g.nz - 1 && kept(p, p + g.nxy, g)) c += d.cz[s] * nz_[s];
                     v[s] = d.rv[s] - d.di[s] * c;
-                    if (i < nx - 1 && kept(p, p + 1, g)) a[s] = -d.di[s] * d.cx[s];
+                    if (i < nx - 1 && kept(p, p + 1, g)) a[s] = -(double)d.di[s] * (double)d.cx[s];
                 }
             }
         }
@@ -457,7 +485,7 @@ __global__ void __launch_bounds__(kIluThreads) k_ilu_bwd_tile(IluGrid g, int L, 
         }
     };
     constexpr int NL = 2 * kIluTile - 1;
-    IluLine<E> A, Bq;
+    IluLine<E, CT> A, Bq;
 #pragma unroll
     for (int s = 0; s < E; ++s) A.cy[s] = A.cz[s] = A.vy[s] = A.vz[s] = Bq.cy[s] = Bq.cz[s] =
         Bq.vy[s] = Bq.vz[s] = 0.0;
@@ -531,46 +559,80 @@ int tiles_on(const IluGrid &g, int L) {
     return n;
 }
 
-template <int E, bool VEC>
-hipError_t ilu_apply_e(const IluGrid &g, const double *ax, const double *ay, const double *az,
-                       const double *dtinv, const double *r, double *z, hipStream_t s) {
+template <int E, bool VEC, typename CT>
+hipError_t ilu_apply_e(const IluGrid &g, const IluPtrs<CT> &fb, hipStream_t s) {
     const size_t sh = 2 * (size_t)kIluTile * 64 * E * sizeof(double);
     if (sh > 65536) {
-        (void)hipFuncSetAttribute((const void *)k_ilu_fwd_tile<E, VEC>,
+        (void)hipFuncSetAttribute((const void *)k_ilu_fwd_tile<E, VEC, CT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-        (void)hipFuncSetAttribute((const void *)k_ilu_bwd_tile<E, VEC>,
+        (void)hipFuncSetAttribute((const void *)k_ilu_bwd_tile<E, VEC, CT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     }
-    IluPtrs fb{ax, ay, az, dtinv, r, z};
     for (int L = 0; L < g.tlevels; ++L)
-        hipLaunchKernelGGL((k_ilu_fwd_tile<E, VEC>), dim3(tiles_on(g, L)), dim3(kIluThreads), sh,
-                           s, g, L, fb);
+        hipLaunchKernelGGL((k_ilu_fwd_tile<E, VEC, CT>), dim3(tiles_on(g, L)), dim3(kIluThreads),
+                           sh, s, g, L, fb);
     for (int L = g.tlevels - 1; L >= 0; --L)
-        hipLaunchKernelGGL((k_ilu_bwd_tile<E, VEC>), dim3(tiles_on(g, L)), dim3(kIluThreads), sh,
-                           s, g, L, fb);
+        hipLaunchKernelGGL((k_ilu_bwd_tile<E, VEC, CT>), dim3(tiles_on(g, L)), dim3(kIluThreads),
+                           sh, s, g, L, fb);
     return hipGetLastError();
 }
 
-template <int E>
-hipError_t ilu_apply_v(const IluGrid &g, const double *ax, const double *ay, const double *az,
-                       const double *dtinv, const double *r, double *z, hipStream_t s) {
-    if (g.nx % E == 0) return ilu_apply_e<E, true>(g, ax, ay, az, dtinv, r, z, s);
-    return ilu_apply_e<E, false>(g, ax, ay, az, dtinv, r, z, s);
+template <int E, typename CT>
+hipError_t ilu_apply_v(const IluGrid &g, const IluPtrs<CT> &fb, hipStream_t s) {
+    if (g.nx % E == 0) return ilu_apply_e<E, true>(g, fb, s);
+    return ilu_apply_e<E, false>(g, fb, s);
+}
+
+template <typename CT>
+hipError_t ilu_apply_t(const IluGrid &g, const IluPtrs<CT> &fb, hipStream_t s) {
+    const int e = (g.nx + 63) / 64;
+    if (e <= 1) return ilu_apply_v<1>(g, fb, s);
+    if (e <= 2) return ilu_apply_v<2>(g, fb, s);
+    if (e <= 4) return ilu_apply_v<4>(g, fb, s);
+    // 6 per lane (nx up to 384, e.g. 350) keeps the two input buffers in registers,
+    // where 8 per lane spills
+    if (e <= 6) return ilu_apply_v<6>(g, fb, s);
+    if (e <= 8) return ilu_apply_v<8>(g, fb, s);
+    return ilu_apply_v<16>(g, fb, s);
+}
+
+// The coefficients of the sweeps in FP32: ax, ay, az, 1/dt one after another.
+__global__ void __launch_bounds__(256) k_ilu_coef_f32(const double *__restrict__ ax,
+                                                      const double *__restrict__ ay,
+                                                      const double *__restrict__ az,
+                                                      const double *__restrict__ dtinv,
+                                                      float *__restrict__ out, long long n) {
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        out[i] = (float)ax[i];
+        out[n + i] = (float)ay[i];
+        out[2 * n + i] = (float)az[i];
+        out[3 * n + i] = (float)dtinv[i];
+    }
 }
 
 }  // namespace
 
 hipError_t launch_ilu_apply(const IluGrid &g, const double *ax, const double *ay, const double *az,
-                            const double *dtinv, const double *r, double *z, hipStream_t s) {
-    const int e = (g.nx + 63) / 64;
-    if (e <= 1) return ilu_apply_v<1>(g, ax, ay, az, dtinv, r, z, s);
-    if (e <= 2) return ilu_apply_v<2>(g, ax, ay, az, dtinv, r, z, s);
-    if (e <= 4) return ilu_apply_v<4>(g, ax, ay, az, dtinv, r, z, s);
-    // 6 per lane (nx up to 384, e.g. 350) keeps the two input buffers in registers,
-    // where 8 per lane spills
-    if (e <= 6) return ilu_apply_v<6>(g, ax, ay, az, dtinv, r, z, s);
-    if (e <= 8) return ilu_apply_v<8>(g, ax, ay, az, dtinv, r, z, s);
-    return ilu_apply_v<16>(g, ax, ay, az, dtinv, r, z, s);
+                            const double *dtinv, const float *fcoef, const double *r, double *z,
+                            hipStream_t s) {
+    if (fcoef) {
+        const long long n = g.N;
+        const IluPtrs<float> fb{fcoef, fcoef + n, fcoef + 2 * n, fcoef + 3 * n, r, z};
+        return ilu_apply_t(g, fb, s);
+    }
+    const IluPtrs<double> fb{ax, ay, az, dtinv, r, z};
+    return ilu_apply_t(g, fb, s);
+}
+
+hipError_t launch_ilu_coef_f32(const IluGrid &g, const double *ax, const double *ay,
+                               const double *az, const double *dtinv, float *fcoef,
+                               hipStream_t s) {
+    long long nb = (g.N + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_ilu_coef_f32, dim3((unsigned)nb), dim3(256), 0, s, ax, ay, az, dtinv,
+                       fcoef, g.N);
+    return hipGetLastError();
 }
 
 }  // namespace ntd

@@ -220,8 +220,15 @@ IluGrid ilu_grid(int nx, int ny, int nz, int nblocks);
 hipError_t launch_ilu_factor(const IluGrid &g, const double *d, const double *ax, const double *ay,
                              const double *az, double *dt, double *dtinv, int *flag,
                              hipStream_t s);
+// z = B_ILU^{-1} r; fcoef (MIXED, else NULL): ax, ay, az and 1/dt in FP32,
+// 4 N floats, which the sweeps then read instead of the FP64 arrays (the
+// arithmetic stays FP64).
 hipError_t launch_ilu_apply(const IluGrid &g, const double *ax, const double *ay, const double *az,
-                            const double *dtinv, const double *r, double *z, hipStream_t s);
+                            const double *dtinv, const float *fcoef, const double *r, double *z,
+                            hipStream_t s);
+hipError_t launch_ilu_coef_f32(const IluGrid &g, const double *ax, const double *ay,
+                               const double *az, const double *dtinv, float *fcoef,
+                               hipStream_t s);
 
 hipError_t launch_check_positive(const double *kappa, const double *t, long long N, int *flag,
                                  hipStream_t s);

@@ -302,6 +302,21 @@ def test_ilu0_factor_and_apply_parity(shape, kind):
     assert relmax(z, O.ilu0_apply(bands, dt, r, 2)) <= 1e-12
 
 
+@pytest.mark.parametrize("shape,kind", ILU_SHAPES + ILU_WIDE_SHAPES + ILU_TILED_WIDE_SHAPES)
+def test_ilu0_apply_parity_mixed(shape, kind):
+    """MIXED reads the ILU(0) sweeps' coefficients (the couplings and 1/dt) in
+    FP32, with FP64 arithmetic: every values-per-lane variant, with and without
+    vector loads, within 1e-5 of the oracle element by element."""
+    kappa, bc = case(shape, kind)
+    S = ntd().Solver(G(kappa), bc, prec="mixed", schur="newton", smoother="ilu0")
+    bands = O.assemble(kappa, bc)
+    dt, st = O.ilu0(bands, 2)
+    assert st == 0
+    np.testing.assert_allclose(C(S.export("dt")), dt, rtol=1e-13)
+    r = np.random.default_rng(24).uniform(-1, 1, shape)
+    assert relmax(C(S.apply_ilu0(G(r))), O.ilu0_apply(bands, dt, r, 2)) <= 1e-5
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("mixed", 1e-5)])
 @pytest.mark.parametrize("shape,kind", ILU_SHAPES[:4])
 def test_combination_apply_parity(shape, kind, prec, tol):
