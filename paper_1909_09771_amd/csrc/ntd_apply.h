@@ -98,7 +98,34 @@ __device__ __forceinline__ double fmad(double a, double b, double c) { return __
 // lanes starting at this one toward the end of the row (entry 9 is 0 in rows 1
 // and 3).  Entry 10 is the chain-B seed: in lane 63 the coefficient u of
 // element j+1 (its coupling to the twist value), 0 elsewhere; in the packed u
-// array that coefficient is replaced by 0.
+// array that coefficient is replaced by 0.  They depend on the factors only,
+// and are formed in the sweep from the loaded a and u (scan_mults): reading
+// them from the record would add 44 B per lane to every line step's loads.
+template <typename T, int EPL>
+__device__ __forceinline__ void scan_mults(const T (&a)[EPL], const T (&u)[EPL], T seed,
+                                           T (&m)[kRecMul]) {
+    T A = T(1), U = T(1);
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) {
+        A *= a[s];
+        U *= u[s];
+    }
+    m[0] = A;
+    m[1] = m[0] * dpp<kRowShr1>(T(1), m[0]);
+    m[2] = m[1] * dpp<kRowShr2>(T(1), m[1]);
+    m[3] = m[2] * dpp<kRowShr4>(T(1), m[2]);
+    m[4] = m[3] * dpp<kRowShr8>(T(1), m[3]);
+    m[5] = U;
+    m[6] = m[5] * dpp<kRowShl1>(T(1), m[5]);
+    m[7] = m[6] * dpp<kRowShl2>(T(1), m[6]);
+    m[8] = m[7] * dpp<kRowShl4>(T(1), m[7]);
+    m[9] = m[8] * dpp<kRowShl8>(T(1), m[8]);
+    const int lane = threadIdx.x & 63;
+    const bool odd_row = ((lane >> 4) & 1) != 0;
+    m[4] = odd_row ? m[4] : T(0);  // the forward cross-row step feeds rows 1 and 3
+    m[9] = odd_row ? T(0) : m[9];  // the backward one rows 0 and 2
+    m[10] = lane == 63 ? seed : T(0);
+}
 template <typename T>
 __device__ __forceinline__ T scan_fwd(T B, const T (&m)[kRecMul]) {
     B = fmad(zmov<kRowShr1>(B), m[0], B);
@@ -174,30 +201,27 @@ struct RecFmt {
     using Ty = T;
     static constexpr int kEPL = EPL;
     static constexpr unsigned kArr = rec_arr_bytes(sizeof(T), EPL);
-    static constexpr unsigned kMul = rec_mul_off(sizeof(T), EPL);
     static constexpr unsigned kTw = rec_tw_off(sizeof(T), EPL);
     static constexpr unsigned kRec = rec_bytes(sizeof(T), EPL);
     static constexpr unsigned kLine = 64u * EPL * sizeof(T);
     rsrc_t rec;       // the records of the plane
     rsrc_t W;         // lower-sweep results of the plane
     unsigned vA;      // this lane's byte offset inside a packed array
-    unsigned vM;      // this lane's multipliers inside a record
     __device__ RecFmt() {
         const unsigned lane = threadIdx.x & 63;
         vA = lane * EPL * (unsigned)sizeof(T);
-        vM = kMul + lane * kRecMul * (unsigned)sizeof(T);
     }
     __device__ void load_coef(int m, LineIn<T, EPL> &in) const {
         const unsigned so = (unsigned)m * kRec;
         vload(rec, vA + kRecMv * kArr, so, in.c0);
         vload(rec, vA + kRecA * kArr, so, in.c1);
         vload(rec, vA + kRecU * kArr, so, in.c2);
-        vload(rec, vM, so, in.mul);
-        double tw[2];
+        double tw[4];
         vload(rec, kTw, so, tw);
         in.mvj = tw[0];
         in.cpj = tw[1];
-        in.cnj = bload((double *)nullptr, rec, kTw + 16u, so);
+        in.cnj = tw[2];
+        in.seed = tw[3];
     }
     // y-coupling of line m to line m+1 (up) or m-1 (down)
     __device__ void load_fc(int m, bool up, T (&f)[EPL]) const {
@@ -208,7 +232,9 @@ struct RecFmt {
         vstore(W, vA, (unsigned)m * kLine, w);
     }
     __device__ void solve(const LineIn<T, EPL> &in, const T (&y)[EPL], T (&x)[EPL]) const {
-        solve_rec(in.c1, in.c0, in.c2, in.mul, in.mvj, in.cpj, in.cnj, y, x);
+        T m[kRecMul];
+        scan_mults(in.c1, in.c2, (T)in.seed, m);
+        solve_rec(in.c1, in.c0, in.c2, m, in.mvj, in.cpj, in.cnj, y, x);
     }
 };
 
@@ -508,29 +534,6 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs p) {
         v[kRecGdn][s] = k > 0 ? p.g3[base - nxy + e] : 0.0;
         v[kRecGup][s] = k < p.nz - 1 ? p.g3[base + e] : 0.0;
     }
-    // scan multipliers
-    double A = 1.0, U = 1.0;
-#pragma unroll
-    for (int s = 0; s < EPL; ++s) {
-        A *= v[kRecA][s];
-        U *= v[kRecU][s];
-    }
-    double mul[kRecMul];
-    mul[0] = A;
-    mul[1] = mul[0] * dpp<kRowShr1>(1.0, mul[0]);
-    mul[2] = mul[1] * dpp<kRowShr2>(1.0, mul[1]);
-    mul[3] = mul[2] * dpp<kRowShr4>(1.0, mul[2]);
-    mul[4] = mul[3] * dpp<kRowShr8>(1.0, mul[3]);
-    mul[5] = U;
-    mul[6] = mul[5] * dpp<kRowShl1>(1.0, mul[5]);
-    mul[7] = mul[6] * dpp<kRowShl2>(1.0, mul[6]);
-    mul[8] = mul[7] * dpp<kRowShl4>(1.0, mul[7]);
-    mul[9] = mul[8] * dpp<kRowShl8>(1.0, mul[8]);
-    const int row = lane >> 4;
-    if ((row & 1) == 0) mul[4] = 0.0;  // the forward cross-row step feeds rows 1 and 3
-    else mul[9] = 0.0;                  // the backward one rows 0 and 2
-    mul[10] = lane == 63 ? seed : 0.0;
-    mul[11] = 0.0;
     char *rec = (char *)p.rec + (size_t)line * R::kRec;
 #pragma unroll
     for (int q = 0; q < kRecArrays; ++q) {
@@ -538,15 +541,19 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs p) {
 #pragma unroll
         for (int s = 0; s < EPL; ++s) arr[lane * EPL + s] = (T)v[q][s];
     }
-    T *mt = (T *)(rec + R::kMul);
-#pragma unroll
-    for (int q = 0; q < kRecMul; ++q) mt[lane * kRecMul + q] = (T)mul[q];
+    // the chain-B seed (held by the lane of element j+1) goes with the twist row
+    {
+        const unsigned long long sb = __builtin_bit_cast(unsigned long long, seed);
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)sb, 63);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(sb >> 32), 63);
+        seed = __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+    }
     if (lane == 0) {
         double *tw = (double *)(rec + R::kTw);
         tw[0] = p.mv[base + j];
         tw[1] = j > 0 ? p.e1[base + j - 1] : 0.0;
         tw[2] = j < n - 1 ? p.e1[base + j] : 0.0;
-        tw[3] = 0.0;
+        tw[3] = seed;
     }
 }
 

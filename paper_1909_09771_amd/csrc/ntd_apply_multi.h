@@ -18,16 +18,15 @@ namespace ntd {
 
 namespace {
 
-// Inputs of one line step for NR right-hand sides: the shared coefficients,
-// couplings and multipliers, and three per-right-hand-side lines (their use
-// depends on the sweep: see the policies below).
+// Inputs of one line step for NR right-hand sides: the shared coefficients
+// and couplings, and three per-right-hand-side lines (their use depends on the
+// sweep: see the policies below).
 template <typename T, int EPL, int NR>
 struct LineInM {
     T c0[EPL], c1[EPL], c2[EPL];  // 1/M, a, u
     T f[EPL];                     // y-coupling to the chain predecessor
     T g[EPL], g2[EPL];            // z-couplings (level 3)
-    T mul[kRecMul];
-    double mvj, cpj, cnj;
+    double mvj, cpj, cnj, seed;
     T q0[NR][EPL], q1[NR][EPL], q2[NR][EPL];
 };
 
@@ -39,23 +38,22 @@ struct RecFmtM {
     using R = RecFmt<T, EPL>;
     rsrc_t rec;
     rsrc_t W[NR];  // lower-sweep results of the plane, one buffer per right-hand side
-    unsigned vA, vM;
+    unsigned vA;
     __device__ RecFmtM() {
         const unsigned lane = threadIdx.x & 63;
         vA = lane * EPL * (unsigned)sizeof(T);
-        vM = R::kMul + lane * kRecMul * (unsigned)sizeof(T);
     }
     __device__ void load_coef(int m, LineInM<T, EPL, NR> &in) const {
         const unsigned so = (unsigned)m * R::kRec;
         vload(rec, vA + kRecMv * R::kArr, so, in.c0);
         vload(rec, vA + kRecA * R::kArr, so, in.c1);
         vload(rec, vA + kRecU * R::kArr, so, in.c2);
-        vload(rec, vM, so, in.mul);
-        double tw[2];
+        double tw[4];
         vload(rec, R::kTw, so, tw);
         in.mvj = tw[0];
         in.cpj = tw[1];
-        in.cnj = bload((double *)nullptr, rec, R::kTw + 16u, so);
+        in.cnj = tw[2];
+        in.seed = tw[3];
     }
     __device__ void load_fc(int m, bool up, T (&f)[EPL]) const {
         vload(rec, vA + (up ? kRecFup : kRecFdn) * R::kArr, (unsigned)m * R::kRec, f);
@@ -67,8 +65,13 @@ struct RecFmtM {
     __device__ void store_w(int m, int q, const T (&w)[EPL]) const {
         vstore(W[q], vA, (unsigned)m * R::kLine, w);
     }
-    __device__ void solve(const LineInM<T, EPL, NR> &in, const T (&y)[EPL], T (&x)[EPL]) const {
-        solve_rec(in.c1, in.c0, in.c2, in.mul, in.mvj, in.cpj, in.cnj, y, x);
+    // the scan multipliers of the step's line, shared by its NR solves
+    __device__ void mults(const LineInM<T, EPL, NR> &in, T (&m)[kRecMul]) const {
+        scan_mults(in.c1, in.c2, (T)in.seed, m);
+    }
+    __device__ void solve(const LineInM<T, EPL, NR> &in, const T (&m)[kRecMul], const T (&y)[EPL],
+                          T (&x)[EPL]) const {
+        solve_rec(in.c1, in.c0, in.c2, m, in.mvj, in.cpj, in.cnj, y, x);
     }
 };
 
@@ -204,8 +207,12 @@ __device__ void plane_solve_m(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty
         for (int q = 0; q < NR; ++q)
 #pragma unroll
             for (int s = 0; s < EPL; ++s) y[q][s] = pol.rhs(in, q, s) - in.f[s] * prev[q][s];
+        {
+            T mm[kRecMul];
+            fmt.mults(in, mm);
 #pragma unroll
-        for (int q = 0; q < NR; ++q) fmt.solve(in, y[q], w[q]);
+            for (int q = 0; q < NR; ++q) fmt.solve(in, mm, y[q], w[q]);
+        }
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
             fmt.store_w(m, q, w[q]);
@@ -219,8 +226,12 @@ __device__ void plane_solve_m(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty
         for (int q = 0; q < NR; ++q)
 #pragma unroll
             for (int s = 0; s < EPL; ++s) y[q][s] = in.f[s] * prev[q][s];
+        {
+            T mm[kRecMul];
+            fmt.mults(in, mm);
 #pragma unroll
-        for (int q = 0; q < NR; ++q) fmt.solve(in, y[q], w[q]);
+            for (int q = 0; q < NR; ++q) fmt.solve(in, mm, y[q], w[q]);
+        }
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
 #pragma unroll
@@ -297,8 +308,12 @@ __device__ void plane_solve_m(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty
 #pragma unroll
             for (int s = 0; s < EPL; ++s)
                 y[q][s] = pol.rhs(A, q, s) - A.f[s] * prev[q][s] - fhi[s] * L2(q, 1, s);
+        {
+            T mm[kRecMul];
+            fmt.mults(A, mm);
 #pragma unroll
-        for (int q = 0; q < NR; ++q) fmt.solve(A, y[q], w[q]);
+            for (int q = 0; q < NR; ++q) fmt.solve(A, mm, y[q], w[q]);
+        }
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
             pol.out(j2, q, w[q], A);

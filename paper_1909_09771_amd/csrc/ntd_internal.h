@@ -56,21 +56,19 @@ struct Grid {
 // The factors of line L form one record of rec_bytes() bytes: seven packed
 // arrays (1/M; a = -cp/M, the coupling to the chain predecessor; u = -cn/M,
 // toward the twist; the y-couplings f to lines m-1 and m+1; the z-couplings g
-// to planes k-1 and k+1), then per lane kRecMul scan multipliers, then the FP64
-// twist row (1/M_j, e1[j-1], e1[j], 0).
+// to planes k-1 and k+1), then the FP64 twist row (1/M_j, e1[j-1], e1[j], and
+// the chain-B seed: the coupling u of element j+1 to the twist element).  The
+// kRecMul scan multipliers of a lane are formed from a and u by the sweeps.
 constexpr int kRecArrays = 7;
-constexpr int kRecMul = 12;  // forward stage multipliers 0-4, backward 0-4, chain-B seed, pad
+constexpr int kRecMul = 11;  // forward stage multipliers 0-4, backward 0-4, chain-B seed
 enum RecArray : int { kRecMv = 0, kRecA = 1, kRecU = 2, kRecFdn = 3, kRecFup = 4, kRecGdn = 5,
                       kRecGup = 6 };
 
 __host__ __device__ constexpr unsigned rec_arr_bytes(unsigned tsz, int epl) {
     return 64u * (unsigned)epl * tsz;
 }
-__host__ __device__ constexpr unsigned rec_mul_off(unsigned tsz, int epl) {
-    return kRecArrays * rec_arr_bytes(tsz, epl);
-}
 __host__ __device__ constexpr unsigned rec_tw_off(unsigned tsz, int epl) {
-    return rec_mul_off(tsz, epl) + 64u * kRecMul * tsz;
+    return kRecArrays * rec_arr_bytes(tsz, epl);
 }
 __host__ __device__ constexpr unsigned rec_bytes(unsigned tsz, int epl) {
     return (rec_tw_off(tsz, epl) + 32u + 255u) & ~255u;

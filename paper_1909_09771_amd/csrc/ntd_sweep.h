@@ -424,8 +424,7 @@ struct LineIn {
     T f[EPL], w[EPL];
     T a0[EPL], a1[EPL], a2[EPL], a3[EPL];
     double d0[EPL], d1[EPL], d2[EPL];
-    T mul[kRecMul];  // packed: the lane's scan multipliers
-    double mvj, cpj, cnj;
+    double mvj, cpj, cnj, seed;  // packed: the twist row and the chain-B seed
 };
 
 // Natural layout (the factorization's own arrays, FP64): lines of nx elements,
