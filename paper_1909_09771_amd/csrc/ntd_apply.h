@@ -101,6 +101,25 @@ __device__ __forceinline__ double fmad(double a, double b, double c) { return __
 // array that coefficient is replaced by 0.  They depend on the factors only,
 // and are formed in the sweep from the loaded a and u (scan_mults): reading
 // them from the record would add 44 B per lane to every line step's loads.
+// The recurrence coefficients of the packed slots, from 1/M and the coupling p
+// to the chain predecessor: a = -p/M (lower) and u = -p'/M (upper, p' that of
+// the next chain position: the lane's next slot, or the next lane's first).
+// The last slot of chain A (the twist element) takes p' from chain B's first
+// slot and the last of chain B from beyond lane 63: both 0, the first as the
+// twist row takes both couplings itself, the second as the chain-B seed does.
+// Unused slots (1/M = 0) get a = u = 0: they hold zeros, and a zero a at a
+// chain's start already cuts every scan window that reaches back into them.
+template <typename T, int EPL>
+__device__ __forceinline__ void line_coefs(const T (&mv)[EPL], const T (&p)[EPL], T (&a)[EPL],
+                                           T (&u)[EPL]) {
+    const T pn = zmov<kWaveShl1>(p[0]);  // the next lane's first coupling
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) {
+        a[s] = -mv[s] * p[s];
+        u[s] = -mv[s] * (s + 1 < EPL ? p[s + 1] : pn);
+    }
+}
+
 template <typename T, int EPL>
 __device__ __forceinline__ void scan_mults(const T (&a)[EPL], const T (&u)[EPL], T seed,
                                            T (&m)[kRecMul]) {
@@ -214,8 +233,7 @@ struct RecFmt {
     __device__ void load_coef(int m, LineIn<T, EPL> &in) const {
         const unsigned so = (unsigned)m * kRec;
         vload(rec, vA + kRecMv * kArr, so, in.c0);
-        vload(rec, vA + kRecA * kArr, so, in.c1);
-        vload(rec, vA + kRecU * kArr, so, in.c2);
+        vload(rec, vA + kRecP * kArr, so, in.c1);
         double tw[4];
         vload(rec, kTw, so, tw);
         in.mvj = tw[0];
@@ -232,9 +250,10 @@ struct RecFmt {
         vstore(W, vA, (unsigned)m * kLine, w);
     }
     __device__ void solve(const LineIn<T, EPL> &in, const T (&y)[EPL], T (&x)[EPL]) const {
-        T m[kRecMul];
-        scan_mults(in.c1, in.c2, (T)in.seed, m);
-        solve_rec(in.c1, in.c0, in.c2, m, in.mvj, in.cpj, in.cnj, y, x);
+        T a[EPL], u[EPL], m[kRecMul];
+        line_coefs(in.c0, in.c1, a, u);
+        scan_mults(a, u, (T)in.seed, m);
+        solve_rec(a, in.c0, u, m, in.mvj, in.cpj, in.cnj, y, x);
     }
 };
 
@@ -507,8 +526,8 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs p) {
 #pragma unroll
     for (int s = 0; s < EPL; ++s) {
         const int c = G.pos(s, EPL);
-        if (!G.ok(c)) {  // identity slot
-            v[kRecMv][s] = 0.0; v[kRecA][s] = 1.0; v[kRecU][s] = 0.0;
+        if (!G.ok(c)) {  // unused slot
+            v[kRecMv][s] = v[kRecP][s] = 0.0;
             v[kRecFdn][s] = v[kRecFup][s] = v[kRecGdn][s] = v[kRecGup][s] = 0.0;
             continue;
         }
@@ -523,12 +542,8 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs p) {
             cn = p.e1[base + e - 1];
         }
         v[kRecMv][s] = M;
-        v[kRecA][s] = -M * cp;
-        v[kRecU][s] = -M * cn;
-        if (G.half == 1 && c == G.cb - 1) {  // element j+1: its coupling seeds chain B
-            seed = v[kRecU][s];
-            v[kRecU][s] = 0.0;
-        }
+        v[kRecP][s] = cp;
+        if (G.half == 1 && c == G.cb - 1) seed = -M * cn;  // element j+1: it seeds chain B
         v[kRecFdn][s] = m > 0 ? p.f2[base - n + e] : 0.0;
         v[kRecFup][s] = m < ny - 1 ? p.f2[base + e] : 0.0;
         v[kRecGdn][s] = k > 0 ? p.g3[base - nxy + e] : 0.0;

@@ -46,8 +46,7 @@ struct RecFmtM {
     __device__ void load_coef(int m, LineInM<T, EPL, NR> &in) const {
         const unsigned so = (unsigned)m * R::kRec;
         vload(rec, vA + kRecMv * R::kArr, so, in.c0);
-        vload(rec, vA + kRecA * R::kArr, so, in.c1);
-        vload(rec, vA + kRecU * R::kArr, so, in.c2);
+        vload(rec, vA + kRecP * R::kArr, so, in.c1);
         double tw[4];
         vload(rec, R::kTw, so, tw);
         in.mvj = tw[0];
@@ -65,13 +64,18 @@ struct RecFmtM {
     __device__ void store_w(int m, int q, const T (&w)[EPL]) const {
         vstore(W[q], vA, (unsigned)m * R::kLine, w);
     }
-    // the scan multipliers of the step's line, shared by its NR solves
-    __device__ void mults(const LineInM<T, EPL, NR> &in, T (&m)[kRecMul]) const {
-        scan_mults(in.c1, in.c2, (T)in.seed, m);
+    // the recurrence coefficients and scan multipliers of the step's line,
+    // shared by its NR solves
+    struct Prep {
+        T a[EPL], u[EPL], m[kRecMul];
+    };
+    __device__ void prep(const LineInM<T, EPL, NR> &in, Prep &p) const {
+        line_coefs(in.c0, in.c1, p.a, p.u);
+        scan_mults(p.a, p.u, (T)in.seed, p.m);
     }
-    __device__ void solve(const LineInM<T, EPL, NR> &in, const T (&m)[kRecMul], const T (&y)[EPL],
+    __device__ void solve(const LineInM<T, EPL, NR> &in, const Prep &p, const T (&y)[EPL],
                           T (&x)[EPL]) const {
-        solve_rec(in.c1, in.c0, in.c2, m, in.mvj, in.cpj, in.cnj, y, x);
+        solve_rec(p.a, in.c0, p.u, p.m, in.mvj, in.cpj, in.cnj, y, x);
     }
 };
 
@@ -208,10 +212,10 @@ __device__ void plane_solve_m(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty
 #pragma unroll
             for (int s = 0; s < EPL; ++s) y[q][s] = pol.rhs(in, q, s) - in.f[s] * prev[q][s];
         {
-            T mm[kRecMul];
-            fmt.mults(in, mm);
+            typename Fmt::Prep pp;
+            fmt.prep(in, pp);
 #pragma unroll
-            for (int q = 0; q < NR; ++q) fmt.solve(in, mm, y[q], w[q]);
+            for (int q = 0; q < NR; ++q) fmt.solve(in, pp, y[q], w[q]);
         }
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
@@ -227,10 +231,10 @@ __device__ void plane_solve_m(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty
 #pragma unroll
             for (int s = 0; s < EPL; ++s) y[q][s] = in.f[s] * prev[q][s];
         {
-            T mm[kRecMul];
-            fmt.mults(in, mm);
+            typename Fmt::Prep pp;
+            fmt.prep(in, pp);
 #pragma unroll
-            for (int q = 0; q < NR; ++q) fmt.solve(in, mm, y[q], w[q]);
+            for (int q = 0; q < NR; ++q) fmt.solve(in, pp, y[q], w[q]);
         }
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
@@ -309,10 +313,10 @@ __device__ void plane_solve_m(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty
             for (int s = 0; s < EPL; ++s)
                 y[q][s] = pol.rhs(A, q, s) - A.f[s] * prev[q][s] - fhi[s] * L2(q, 1, s);
         {
-            T mm[kRecMul];
-            fmt.mults(A, mm);
+            typename Fmt::Prep pp;
+            fmt.prep(A, pp);
 #pragma unroll
-            for (int q = 0; q < NR; ++q) fmt.solve(A, mm, y[q], w[q]);
+            for (int q = 0; q < NR; ++q) fmt.solve(A, pp, y[q], w[q]);
         }
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
