@@ -47,7 +47,9 @@ typedef struct ntd_handle ntd_handle;
 /* Arithmetic of the preconditioner.  FP64: factors and sweeps in double.
  * MIXED: factors rounded to float after an FP64 setup and sweeps in float,
  * except the twist (meeting) row of every line, whose pivot and update stay in
- * double; CG vectors, SpMV, dot products and residual updates are always FP64. */
+ * double; with an ILU(0) smoother its sweeps read the couplings and 1/dt
+ * rounded to float and compute in double.  CG vectors, SpMV, dot products and
+ * residual updates are always FP64. */
 #define NTD_PREC_FP64 0
 #define NTD_PREC_MIXED 1
 
