@@ -43,7 +43,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_traffic.json")
 # Sources of the sweep kernels; the recorded byte counts hold only for them.
 SWEEP_SRCS = [os.path.join(ROOT, "paper_1909_09771_amd", "csrc", f)
               for f in ("ntd_sweep.h", "ntd_apply.h", "ntd_internal.h", "ntd_apply_f32.hip",
-                        "ntd_apply_f64.hip")]
+                        "ntd_apply_f64.hip", "ntd_apply_multi.h", "ntd_apply_multi_f32.hip",
+                        "ntd_apply_multi_f64.hip", "ntd_vec.hip")]
 
 # Algorithmic HBM bytes per unknown of each sweep launch (e = bytes of the
 # factor precision).  Lower: the packed right-hand side, the four factor arrays

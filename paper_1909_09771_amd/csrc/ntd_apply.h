@@ -241,9 +241,11 @@ struct RecFmt {
         in.cnj = tw[2];
         in.seed = tw[3];
     }
-    // y-coupling of line m to line m+1 (up) or m-1 (down)
+    // y-coupling of line m to line m+1 (up) or m-1 (down): f of line m or m-1,
+    // 0 below line 0 (an out-of-range offset: the load is still issued)
     __device__ void load_fc(int m, bool up, T (&f)[EPL]) const {
-        vload(rec, vA + (up ? kRecFup : kRecFdn) * kArr, (unsigned)m * kRec, f);
+        const int lc = up ? m : m - 1;
+        vload(rec, lc < 0 ? kOOB : vA + kRecF * kArr, lc < 0 ? 0u : (unsigned)lc * kRec, f);
     }
     __device__ void load_w(int m, T (&w)[EPL]) const { vload(W, vA, (unsigned)m * kLine, w); }
     __device__ void store_w(int m, const T (&w)[EPL]) const {
@@ -271,25 +273,31 @@ __device__ __forceinline__ rsrc_t plane_rsrc(const T *base, int k, int ny) {
     return make_rsrc(base + (size_t)k * ny * 64 * EPL);
 }
 
+// The records of plane k.
+template <typename T, int EPL>
+__device__ __forceinline__ rsrc_t rec_plane(const void *rec, int k, int ny) {
+    return make_rsrc((const char *)rec + (size_t)k * ny * RecFmt<T, EPL>::kRec);
+}
+
 template <typename T, int EPL>
 __device__ __forceinline__ RecFmt<T, EPL> rec_fmt(const ApplyArgs<T> &a, int k, rsrc_t W) {
     RecFmt<T, EPL> F;
-    F.rec = make_rsrc((const char *)a.rec + (size_t)k * a.ny * RecFmt<T, EPL>::kRec);
+    F.rec = rec_plane<T, EPL>(a.rec, k, a.ny);
     F.W = W;
     return F;
 }
 
 // Lower level-3 step of plane k: rhs = r_k - g * z_kn, with g the z-coupling of
-// plane k toward its finished neighbour kn (absent for the first plane).
+// planes k and kn (absent for the first plane), held by the lower of the two.
 template <typename T, int EPL, bool HAS>
 struct PolLower {
-    rsrc_t rp, Zn, Zk;
-    unsigned vA, vG;  // lane offsets: in a packed line; of the coupling array in a record
-    __device__ void load_rhs(int m, const RecFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
+    rsrc_t rp, Zn, Zk, Gr;  // Gr: the records holding g
+    unsigned vA, vG;        // lane offsets: in a packed line; of g in a record
+    __device__ void load_rhs(int m, const RecFmt<T, EPL> &, LineIn<T, EPL> &in) const {
         constexpr unsigned kLine = RecFmt<T, EPL>::kLine;
         vload(rp, vA, (unsigned)m * kLine, in.a2);
         if constexpr (HAS) {
-            vload(F.rec, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.a0);
+            vload(Gr, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.a0);
             vload(Zn, vA, (unsigned)m * kLine, in.a1);
         }
     }
@@ -304,24 +312,25 @@ struct PolLower {
 };
 
 // The twist plane: rhs = r - g_dn * z_{k-1} - g_up * z_{k+1}; the result is final.
+// g_dn is g of plane k-1 (records Glo), g_up g of plane k (records Ghi).
 template <typename T, int EPL>
 struct PolTwist {
-    rsrc_t rp, Zlo, Zhi, Zk;
-    unsigned vA, vGdn, vGup;
+    rsrc_t rp, Zlo, Zhi, Zk, Glo, Ghi;
+    unsigned vA, vG;
     bool lo_nb, hi_nb;
-    __device__ void load_rhs(int m, const RecFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
+    __device__ void load_rhs(int m, const RecFmt<T, EPL> &, LineIn<T, EPL> &in) const {
         constexpr unsigned kLine = RecFmt<T, EPL>::kLine;
         const unsigned so = (unsigned)m * RecFmt<T, EPL>::kRec;
         vload(rp, vA, (unsigned)m * kLine, in.a2);
         if (lo_nb) {
-            vload(F.rec, vGdn, so, in.a0);
+            vload(Glo, vG, so, in.a0);
             vload(Zlo, vA, (unsigned)m * kLine, in.a1);
         } else {
             zero_line(in.a0);
             zero_line(in.a1);
         }
         if (hi_nb) {
-            vload(F.rec, vGup, so, in.a3);
+            vload(Ghi, vG, so, in.a3);
             vload(Zhi, vA, (unsigned)m * kLine, in.w);
         } else {
             zero_line(in.a3);
@@ -341,10 +350,10 @@ struct PolTwist {
 // neighbour toward the twist plane; x_k = z_k - c over Z.
 template <typename T, int EPL>
 struct PolUpper {
-    rsrc_t Zn, Zk;
+    rsrc_t Zn, Zk, Gr;  // Gr: the records holding g (the lower of planes k, kn)
     unsigned vA, vG;
-    __device__ void load_rhs(int m, const RecFmt<T, EPL> &F, LineIn<T, EPL> &in) const {
-        vload(F.rec, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.a0);
+    __device__ void load_rhs(int m, const RecFmt<T, EPL> &, LineIn<T, EPL> &in) const {
+        vload(Gr, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.a0);
         vload(Zn, vA, (unsigned)m * RecFmt<T, EPL>::kLine, in.a1);
     }
     __device__ T rhs(const LineIn<T, EPL> &in, int s) const { return in.a0[s] * in.a1[s]; }
@@ -367,8 +376,9 @@ __device__ __forceinline__ void lower_plane(const ApplyArgs<T> &a, int k, int kn
     pol.Zk = plane_rsrc<T, EPL>(a.Z, k, a.ny);
     pol.Zn = plane_rsrc<T, EPL>(a.Z, HAS ? kn : k, a.ny);
     const RecFmt<T, EPL> F = rec_fmt<T, EPL>(a, k, pol.Zk);
+    pol.Gr = rec_plane<T, EPL>(a.rec, kn < k ? kn : k, a.ny);
     pol.vA = F.vA;
-    pol.vG = F.vA + (kn < k ? kRecGdn : kRecGup) * kArr;
+    pol.vG = F.vA + kRecG * kArr;
     plane_solve<kApplyDepth<T, EPL>>(a.ny, F, pol, lds);
 }
 
@@ -397,9 +407,10 @@ __device__ __forceinline__ void apply_twist(const ApplyArgs<T> &a, T *lds) {
     pol.Zlo = plane_rsrc<T, EPL>(a.Z, pol.lo_nb ? k - 1 : k, a.ny);
     pol.Zhi = plane_rsrc<T, EPL>(a.Z, pol.hi_nb ? k + 1 : k, a.ny);
     const RecFmt<T, EPL> F = rec_fmt<T, EPL>(a, k, pol.Zk);
+    pol.Glo = rec_plane<T, EPL>(a.rec, pol.lo_nb ? k - 1 : k, a.ny);
+    pol.Ghi = F.rec;
     pol.vA = F.vA;
-    pol.vGdn = F.vA + kRecGdn * kArr;
-    pol.vGup = F.vA + kRecGup * kArr;
+    pol.vG = F.vA + kRecG * kArr;
     plane_solve<kApplyDepth<T, EPL>>(a.ny, F, pol, lds);
 }
 
@@ -417,8 +428,9 @@ __device__ __forceinline__ void apply_upper(const ApplyArgs<T> &a, int h, T *lds
         pol.Zk = plane_rsrc<T, EPL>(a.Z, k, ny);
         pol.Zn = plane_rsrc<T, EPL>(a.Z, kn, ny);
         const RecFmt<T, EPL> F = rec_fmt<T, EPL>(a, k, W);
+        pol.Gr = rec_plane<T, EPL>(a.rec, kn < k ? kn : k, ny);
         pol.vA = F.vA;
-        pol.vG = F.vA + (kn < k ? kRecGdn : kRecGup) * kArr;
+        pol.vG = F.vA + kRecG * kArr;
         plane_solve<kApplyDepth<T, EPL>>(ny, F, pol, lds);
     }
 }
@@ -516,7 +528,6 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs p) {
     if (line >= (long long)p.ny * p.nz) return;  // whole wavefronts; no barrier below
     const int n = p.nx, ny = p.ny;
     const int k = (int)(line / ny), m = (int)(line - (long long)k * ny);
-    const long long nxy = (long long)n * ny;
     const LineGeom G(n, EPL);
     const int lane = threadIdx.x & 63;
     const int j = G.ca - 1;
@@ -528,7 +539,7 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs p) {
         const int c = G.pos(s, EPL);
         if (!G.ok(c)) {  // unused slot
             v[kRecMv][s] = v[kRecP][s] = 0.0;
-            v[kRecFdn][s] = v[kRecFup][s] = v[kRecGdn][s] = v[kRecGup][s] = 0.0;
+            v[kRecF][s] = v[kRecG][s] = 0.0;
             continue;
         }
         const int e = G.elem(c);
@@ -544,10 +555,8 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs p) {
         v[kRecMv][s] = M;
         v[kRecP][s] = cp;
         if (G.half == 1 && c == G.cb - 1) seed = -M * cn;  // element j+1: it seeds chain B
-        v[kRecFdn][s] = m > 0 ? p.f2[base - n + e] : 0.0;
-        v[kRecFup][s] = m < ny - 1 ? p.f2[base + e] : 0.0;
-        v[kRecGdn][s] = k > 0 ? p.g3[base - nxy + e] : 0.0;
-        v[kRecGup][s] = k < p.nz - 1 ? p.g3[base + e] : 0.0;
+        v[kRecF][s] = m < ny - 1 ? p.f2[base + e] : 0.0;
+        v[kRecG][s] = k < p.nz - 1 ? p.g3[base + e] : 0.0;
     }
     char *rec = (char *)p.rec + (size_t)line * R::kRec;
 #pragma unroll

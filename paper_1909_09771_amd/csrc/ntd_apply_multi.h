@@ -54,8 +54,10 @@ struct RecFmtM {
         in.cnj = tw[2];
         in.seed = tw[3];
     }
+    // f of line m (up) or m-1 (down), 0 below line 0, as RecFmt::load_fc
     __device__ void load_fc(int m, bool up, T (&f)[EPL]) const {
-        vload(rec, vA + (up ? kRecFup : kRecFdn) * R::kArr, (unsigned)m * R::kRec, f);
+        const int lc = up ? m : m - 1;
+        vload(rec, lc < 0 ? kOOB : vA + kRecF * R::kArr, lc < 0 ? 0u : (unsigned)lc * R::kRec, f);
     }
     __device__ void load_w(int m, T (&w)[NR][EPL]) const {
 #pragma unroll
@@ -82,14 +84,14 @@ struct RecFmtM {
 // Lower level-3 step of plane k for NR right-hand sides: rhs_q = r_q - g z_q(kn).
 template <typename T, int EPL, int NR, bool HAS>
 struct PolLowerM {
-    rsrc_t rp[NR], Zn[NR], Zk[NR];
+    rsrc_t rp[NR], Zn[NR], Zk[NR], Gr;  // Gr: the records holding g
     unsigned vA, vG;
-    __device__ void load_rhs(int m, const RecFmtM<T, EPL, NR> &F, LineInM<T, EPL, NR> &in) const {
+    __device__ void load_rhs(int m, const RecFmtM<T, EPL, NR> &, LineInM<T, EPL, NR> &in) const {
         constexpr unsigned kLine = RecFmt<T, EPL>::kLine;
 #pragma unroll
         for (int q = 0; q < NR; ++q) vload(rp[q], vA, (unsigned)m * kLine, in.q2[q]);
         if constexpr (HAS) {
-            vload(F.rec, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.g);
+            vload(Gr, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.g);
 #pragma unroll
             for (int q = 0; q < NR; ++q) vload(Zn[q], vA, (unsigned)m * kLine, in.q1[q]);
         }
@@ -107,16 +109,16 @@ struct PolLowerM {
 // The twist plane for NR right-hand sides.
 template <typename T, int EPL, int NR>
 struct PolTwistM {
-    rsrc_t rp[NR], Zlo[NR], Zhi[NR], Zk[NR];
-    unsigned vA, vGdn, vGup;
+    rsrc_t rp[NR], Zlo[NR], Zhi[NR], Zk[NR], Glo, Ghi;  // g of planes k-1 and k
+    unsigned vA, vG;
     bool lo_nb, hi_nb;
-    __device__ void load_rhs(int m, const RecFmtM<T, EPL, NR> &F, LineInM<T, EPL, NR> &in) const {
+    __device__ void load_rhs(int m, const RecFmtM<T, EPL, NR> &, LineInM<T, EPL, NR> &in) const {
         constexpr unsigned kLine = RecFmt<T, EPL>::kLine;
         const unsigned so = (unsigned)m * RecFmt<T, EPL>::kRec;
 #pragma unroll
         for (int q = 0; q < NR; ++q) vload(rp[q], vA, (unsigned)m * kLine, in.q2[q]);
         if (lo_nb) {
-            vload(F.rec, vGdn, so, in.g);
+            vload(Glo, vG, so, in.g);
 #pragma unroll
             for (int q = 0; q < NR; ++q) vload(Zlo[q], vA, (unsigned)m * kLine, in.q1[q]);
         } else {
@@ -125,7 +127,7 @@ struct PolTwistM {
             for (int q = 0; q < NR; ++q) zero_line(in.q1[q]);
         }
         if (hi_nb) {
-            vload(F.rec, vGup, so, in.g2);
+            vload(Ghi, vG, so, in.g2);
 #pragma unroll
             for (int q = 0; q < NR; ++q) vload(Zhi[q], vA, (unsigned)m * kLine, in.q0[q]);
         } else {
@@ -147,10 +149,10 @@ struct PolTwistM {
 // x_q(k) = z_q(k) - c_q over Z_q.  q0 carries the level-2 lower result (load_w).
 template <typename T, int EPL, int NR>
 struct PolUpperM {
-    rsrc_t Zn[NR], Zk[NR];
+    rsrc_t Zn[NR], Zk[NR], Gr;  // Gr: the records holding g (the lower of planes k, kn)
     unsigned vA, vG;
-    __device__ void load_rhs(int m, const RecFmtM<T, EPL, NR> &F, LineInM<T, EPL, NR> &in) const {
-        vload(F.rec, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.g);
+    __device__ void load_rhs(int m, const RecFmtM<T, EPL, NR> &, LineInM<T, EPL, NR> &in) const {
+        vload(Gr, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.g);
 #pragma unroll
         for (int q = 0; q < NR; ++q)
             vload(Zn[q], vA, (unsigned)m * RecFmt<T, EPL>::kLine, in.q1[q]);
@@ -350,7 +352,7 @@ constexpr int kApplyDepthM = (sizeof(T) * EPL * NR <= 32) ? 2 : 1;
 template <typename T, int EPL, int NR>
 __device__ __forceinline__ RecFmtM<T, EPL, NR> rec_fmt_m(const ApplyArgs<T> (&a)[NR], int k) {
     RecFmtM<T, EPL, NR> F;
-    F.rec = make_rsrc((const char *)a[0].rec + (size_t)k * a[0].ny * RecFmt<T, EPL>::kRec);
+    F.rec = rec_plane<T, EPL>(a[0].rec, k, a[0].ny);
     return F;
 }
 
@@ -367,8 +369,9 @@ __device__ __forceinline__ void lower_plane_m(const ApplyArgs<T> (&a)[NR], int k
         pol.Zn[q] = plane_rsrc<T, EPL>(a[q].Z, HAS ? kn : k, ny);
         F.W[q] = pol.Zk[q];
     }
+    pol.Gr = rec_plane<T, EPL>(a[0].rec, kn < k ? kn : k, ny);
     pol.vA = F.vA;
-    pol.vG = F.vA + (kn < k ? kRecGdn : kRecGup) * kArr;
+    pol.vG = F.vA + kRecG * kArr;
     plane_solve_m<kApplyDepthM<T, EPL, NR>>(ny, F, pol, lds);
 }
 
@@ -399,9 +402,10 @@ __device__ __forceinline__ void apply_twist_m(const ApplyArgs<T> (&a)[NR], T *ld
         pol.Zhi[q] = plane_rsrc<T, EPL>(a[q].Z, pol.hi_nb ? k + 1 : k, ny);
         F.W[q] = pol.Zk[q];
     }
+    pol.Glo = rec_plane<T, EPL>(a[0].rec, pol.lo_nb ? k - 1 : k, ny);
+    pol.Ghi = F.rec;
     pol.vA = F.vA;
-    pol.vGdn = F.vA + kRecGdn * kArr;
-    pol.vGup = F.vA + kRecGup * kArr;
+    pol.vG = F.vA + kRecG * kArr;
     plane_solve_m<kApplyDepthM<T, EPL, NR>>(ny, F, pol, lds);
 }
 
@@ -420,8 +424,9 @@ __device__ __forceinline__ void apply_upper_m(const ApplyArgs<T> (&a)[NR], int h
             pol.Zn[q] = plane_rsrc<T, EPL>(a[q].Z, kn, ny);
             F.W[q] = make_rsrc(a[q].scratch + (size_t)h * ny * 64 * EPL);
         }
+        pol.Gr = rec_plane<T, EPL>(a[0].rec, kn < k ? kn : k, ny);
         pol.vA = F.vA;
-        pol.vG = F.vA + (kn < k ? kRecGdn : kRecGup) * kArr;
+        pol.vG = F.vA + kRecG * kArr;
         plane_solve_m<kApplyDepthM<T, EPL, NR>>(ny, F, pol, lds);
     }
 }

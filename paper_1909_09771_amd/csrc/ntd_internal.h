@@ -53,17 +53,19 @@ struct Grid {
 // this layout (the packed right-hand side and results) take 64*EPL*sizeof(T)
 // bytes per line, line L = k*ny + m at L*64*EPL slots.
 //
-// The factors of line L form one record of rec_bytes() bytes: six packed
+// The factors of line L form one record of rec_bytes() bytes: four packed
 // arrays (1/M; p, the coupling of the slot's element to its chain predecessor,
-// 0 at a chain's start and in unused slots; the y-couplings f to lines m-1 and
-// m+1; the z-couplings g to planes k-1 and k+1), then the FP64 twist row (1/M_j,
-// e1[j-1], e1[j], and the chain-B seed: the coefficient u of element j+1 toward
-// the twist element).  The sweeps form the recurrence coefficients a = -p/M and
-// u = -p'/M (p' the next chain position's coupling) and the kRecMul scan
-// multipliers of a lane themselves.
-constexpr int kRecArrays = 6;
+// 0 at a chain's start and in unused slots; f, the y-coupling to line m+1; g,
+// the z-coupling to plane k+1; f and g are 0 past the last line and plane),
+// then the FP64 twist row (1/M_j, e1[j-1], e1[j], and the chain-B seed: the
+// coefficient u of element j+1 toward the twist element).  A coupling is stored
+// once: a sweep that needs line m's coupling to line m-1 (plane k's to plane
+// k-1) reads f of line m-1 (g of plane k-1).  The sweeps form the recurrence
+// coefficients a = -p/M and u = -p'/M (p' the next chain position's coupling)
+// and the kRecMul scan multipliers of a lane themselves.
+constexpr int kRecArrays = 4;
 constexpr int kRecMul = 11;  // forward stage multipliers 0-4, backward 0-4, chain-B seed
-enum RecArray : int { kRecMv = 0, kRecP = 1, kRecFdn = 2, kRecFup = 3, kRecGdn = 4, kRecGup = 5 };
+enum RecArray : int { kRecMv = 0, kRecP = 1, kRecF = 2, kRecG = 3 };
 
 __host__ __device__ constexpr unsigned rec_arr_bytes(unsigned tsz, int epl) {
     return 64u * (unsigned)epl * tsz;
