@@ -132,6 +132,9 @@ def parse():
                     help="time the batched apply only (no PCG)")
     ap.add_argument("--batch-nr", type=int, default=1,
                     help="right-hand sides per wavefront pair in the line sweeps (1, 2, 4)")
+    ap.add_argument("--batch-plane-lds", type=int, default=1, choices=[0, 1],
+                    help="1 (default): the line sweeps keep each plane in LDS when every "
+                         "workgroup fits at once (ntd_batch_set_plane_lds); 0: through memory")
     ap.add_argument("--batch-tune-sweeps", action="store_true",
                     help="autotune the right-hand sides per wavefront pair (ntd_batch_tune_sweeps)")
     ap.add_argument("--learn-train", type=int, default=32, help="training fields (--suite learned)")
@@ -404,6 +407,8 @@ def batch_suite(args):
         elif args.batch_nr != 1:
             B.set_sweep_group(args.batch_nr)
         sweep_group["nr"] = sweep_group.get("tuned", args.batch_nr)
+        sweep_group["plane_lds"] = B.set_plane_lds(bool(args.batch_plane_lds))
+        log("line sweeps: planes in %s" % ("LDS" if sweep_group["plane_lds"] else "memory"))
         if args.batch_apply_only:
             t2 = t3 = t1
             xs, its, rrs, sts = [], [0], [0.0], [0]
@@ -422,7 +427,9 @@ def batch_suite(args):
         prof = [B.apply_profile(bs, zs) for _ in range(5)]
         lower_ms, twist_ms, upper_ms, rest_ms = [sorted(p[i] for p in prof)[2] for i in range(4)]
         units = sum(n ** 3 - n ** 2 for n in sides)
-        kname_b = "k_apply_lower_b" if sweep_group["nr"] == 1 else "k_apply_lower_bm%d" % sweep_group["nr"]
+        kname_b = "k_apply_lower_b" + ("m" if sweep_group["nr"] != 1 else "") + \
+            ("l" if sweep_group["plane_lds"] else "") + \
+            ("%d" % sweep_group["nr"] if sweep_group["nr"] != 1 else "")
         by = sum((n ** 3 - n ** 2) * (4 * e + 2 * e * nrhs) for n in sides)
         achieved = by / (lower_ms * 1e-3) / 1e9
         line = {"suite": "batch" + ("-apply" if args.batch_apply_only else ""),

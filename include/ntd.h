@@ -325,6 +325,21 @@ int ntd_batch_tune(ntd_batch *b, int *gx, void *stream);
  * unsupported nr.  Discards a captured iteration graph if nr changes. */
 int ntd_batch_set_sweep_group(ntd_batch *b, int nr);
 
+/* Plane buffers of the batch's line sweeps in LDS (on = 1, the default) or in
+ * device memory (on = 0).  Each level-3 step hands a plane to the next: the
+ * finished neighbour plane, the level-2 lower results and the plane's final
+ * values.  With on = 1 each workgroup keeps that plane in its own LDS, so it
+ * passes through no memory.  Only the final results and the right-hand sides
+ * still move through HBM.  This is used when the device can hold every
+ * workgroup of a sweep at once with its nr buffers (ntd_batch_set_sweep_group)
+ * of (2 + ny_max) * 64 * epl values each.  For example, 64 systems at 128^3
+ * with 4 right-hand sides in MIXED need 65 KB per workgroup at nr = 1 (two
+ * workgroups per CU) and 130 KB at nr = 2 (one per CU).
+ * Results are bitwise the same either way.  *used (HOST, may be NULL) is set to
+ * 1 when the sweeps will use the LDS buffers.  Returns NTD_EINVAL for on
+ * other than 0 or 1.  Discards a captured iteration graph if on changes. */
+int ntd_batch_set_plane_lds(ntd_batch *b, int on, int *used);
+
 /* Autotune the line-sweep shape: time one batched sweep (on zero right-hand
  * sides) for every supported right-hand sides per wavefront pair (1, 2, 4) and
  * keep the fastest; *nr (HOST) receives it.  Overwrites the batch's CG vectors

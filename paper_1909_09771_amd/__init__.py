@@ -103,6 +103,8 @@ def lib() -> ctypes.CDLL:
         L.ntd_batch_set_sweep_group.argtypes = [P, I]
         L.ntd_batch_set_sweep_group.restype = I
         L.ntd_batch_tune_sweeps.argtypes = [P, ctypes.POINTER(I), P]
+        L.ntd_batch_set_plane_lds.argtypes = [P, I, ctypes.POINTER(I)]
+        L.ntd_batch_set_plane_lds.restype = I
         L.ntd_batch_tune_sweeps.restype = I
         L.ntd_batch_solve_stats.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(D),
                                             ctypes.POINTER(D)]
@@ -472,6 +474,17 @@ class Batch:
         st = lib().ntd_batch_set_sweep_group(self._h, int(nr))
         if st != OK:
             raise NTDError(st, "ntd_batch_set_sweep_group")
+
+    def set_plane_lds(self, on: bool) -> bool:
+        """Plane buffers of the line sweeps in LDS (True, the default) or in
+        device memory (ntd_batch_set_plane_lds); returns whether the sweeps
+        will use LDS buffers (every workgroup of a sweep resident at once with
+        its buffers, at the current sweep group)."""
+        used = ctypes.c_int(0)
+        st = lib().ntd_batch_set_plane_lds(self._h, 1 if on else 0, ctypes.byref(used))
+        if st != OK:
+            raise NTDError(st, "ntd_batch_set_plane_lds")
+        return bool(used.value)
 
     def solve_stats(self):
         """(passes, gap_ms, solve_ms) of the last pcg: host checks, the stream's

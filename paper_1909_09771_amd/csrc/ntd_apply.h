@@ -18,6 +18,8 @@
 //     the r.z partials live in bandwidth-bound kernels before and after them.
 #pragma once
 
+#include <type_traits>
+
 #include "ntd_sweep.h"
 
 namespace ntd {
@@ -259,6 +261,34 @@ struct RecFmt {
     }
 };
 
+// One lane's EPL slots of a line in LDS.
+template <typename T, int EPL>
+__device__ __forceinline__ void lds_ld(const T *p, T (&v)[EPL]) {
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) v[s] = p[s];
+}
+template <typename T, int EPL>
+__device__ __forceinline__ void lds_st(T *p, const T (&v)[EPL]) {
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) p[s] = v[s];
+}
+
+// The packed format with a plane buffer in LDS (batched sweeps whose planes fit
+// the workgroup's LDS): line m of the plane at pl + m*64*EPL.  Along a level-3
+// sweep the buffer holds, line by line, the finished neighbour plane's values,
+// then the level-2 lower results written over them as each line's right-hand
+// side is formed, then the plane's final values, which the next plane reads as
+// its neighbour.  Each line is read and written by one wavefront only (the
+// level-2 half that owns it), in program order, so no barrier guards it.
+template <typename T, int EPL>
+struct RecFmtL : RecFmt<T, EPL> {
+    T *pl;  // this lane's slots of line 0
+    __device__ void load_w(int m, T (&w)[EPL]) const { lds_ld<T, EPL>(pl + m * 64 * EPL, w); }
+    __device__ void store_w(int m, const T (&w)[EPL]) const {
+        lds_st<T, EPL>(pl + m * 64 * EPL, w);
+    }
+};
+
 // Prefetch depth of the sweeps: two lines ahead while three input buffers fit
 // the register file comfortably, else one.
 template <typename T, int EPL>
@@ -279,9 +309,9 @@ __device__ __forceinline__ rsrc_t rec_plane(const void *rec, int k, int ny) {
     return make_rsrc((const char *)rec + (size_t)k * ny * RecFmt<T, EPL>::kRec);
 }
 
-template <typename T, int EPL>
-__device__ __forceinline__ RecFmt<T, EPL> rec_fmt(const ApplyArgs<T> &a, int k, rsrc_t W) {
-    RecFmt<T, EPL> F;
+template <typename T, int EPL, class Fmt = RecFmt<T, EPL>>
+__device__ __forceinline__ Fmt rec_fmt(const ApplyArgs<T> &a, int k, rsrc_t W) {
+    Fmt F;
     F.rec = rec_plane<T, EPL>(a.rec, k, a.ny);
     F.W = W;
     return F;
@@ -289,16 +319,19 @@ __device__ __forceinline__ RecFmt<T, EPL> rec_fmt(const ApplyArgs<T> &a, int k, 
 
 // Lower level-3 step of plane k: rhs = r_k - g * z_kn, with g the z-coupling of
 // planes k and kn (absent for the first plane), held by the lower of the two.
-template <typename T, int EPL, bool HAS>
+// LP: z_kn comes from the LDS plane buffer, and z_k goes there too.
+template <typename T, int EPL, bool HAS, bool LP = false>
 struct PolLower {
     rsrc_t rp, Zn, Zk, Gr;  // Gr: the records holding g
     unsigned vA, vG;        // lane offsets: in a packed line; of g in a record
+    T *pl;                  // LP: this lane's slots of the plane buffer
     __device__ void load_rhs(int m, const RecFmt<T, EPL> &, LineIn<T, EPL> &in) const {
         constexpr unsigned kLine = RecFmt<T, EPL>::kLine;
         vload(rp, vA, (unsigned)m * kLine, in.a2);
         if constexpr (HAS) {
             vload(Gr, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.a0);
-            vload(Zn, vA, (unsigned)m * kLine, in.a1);
+            if constexpr (LP) lds_ld<T, EPL>(pl + m * 64 * EPL, in.a1);
+            else vload(Zn, vA, (unsigned)m * kLine, in.a1);
         }
     }
     __device__ T rhs(const LineIn<T, EPL> &in, int s) const {
@@ -308,6 +341,7 @@ struct PolLower {
     __device__ void load_out(int, const RecFmt<T, EPL> &, LineIn<T, EPL> &) const {}
     __device__ void out(int m, const RecFmt<T, EPL> &, const T (&x)[EPL], const LineIn<T, EPL> &) {
         vstore(Zk, vA, (unsigned)m * RecFmt<T, EPL>::kLine, x);
+        if constexpr (LP) lds_st<T, EPL>(pl + m * 64 * EPL, x);
     }
 };
 
@@ -348,13 +382,16 @@ struct PolTwist {
 
 // Upper level-3 step of plane k: c = Pt_k^{-1}(g * x_kn) with kn the final
 // neighbour toward the twist plane; x_k = z_k - c over Z.
-template <typename T, int EPL>
+// LPN: x_kn comes from the LDS plane buffer; LPO: x_k goes there too.
+template <typename T, int EPL, bool LPN = false, bool LPO = false>
 struct PolUpper {
     rsrc_t Zn, Zk, Gr;  // Gr: the records holding g (the lower of planes k, kn)
     unsigned vA, vG;
+    T *pl;              // LPN or LPO: this lane's slots of the plane buffer
     __device__ void load_rhs(int m, const RecFmt<T, EPL> &, LineIn<T, EPL> &in) const {
         vload(Gr, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.a0);
-        vload(Zn, vA, (unsigned)m * RecFmt<T, EPL>::kLine, in.a1);
+        if constexpr (LPN) lds_ld<T, EPL>(pl + m * 64 * EPL, in.a1);
+        else vload(Zn, vA, (unsigned)m * RecFmt<T, EPL>::kLine, in.a1);
     }
     __device__ T rhs(const LineIn<T, EPL> &in, int s) const { return in.a0[s] * in.a1[s]; }
     __device__ void load_out(int m, const RecFmt<T, EPL> &, LineIn<T, EPL> &in) const {
@@ -365,17 +402,32 @@ struct PolUpper {
 #pragma unroll
         for (int s = 0; s < EPL; ++s) xv[s] = in.a2[s] - c[s];
         vstore(Zk, vA, (unsigned)m * RecFmt<T, EPL>::kLine, xv);
+        if constexpr (LPO) lds_st<T, EPL>(pl + m * 64 * EPL, xv);
     }
 };
 
-template <typename T, int EPL, bool HAS>
-__device__ __forceinline__ void lower_plane(const ApplyArgs<T> &a, int k, int kn, T *lds) {
+// The plane format: records in memory, the level-2 lower results in memory
+// (W) or, with LP, in the LDS plane buffer pl (this lane's slots).
+template <typename T, int EPL, bool LP>
+using PlaneFmt = typename std::conditional<LP, RecFmtL<T, EPL>, RecFmt<T, EPL>>::type;
+
+template <typename T, int EPL, bool LP>
+__device__ __forceinline__ PlaneFmt<T, EPL, LP> plane_fmt(const ApplyArgs<T> &a, int k, rsrc_t W,
+                                                          T *pl) {
+    PlaneFmt<T, EPL, LP> F = rec_fmt<T, EPL, PlaneFmt<T, EPL, LP>>(a, k, W);
+    if constexpr (LP) F.pl = pl;
+    return F;
+}
+
+template <typename T, int EPL, bool HAS, bool LP>
+__device__ __forceinline__ void lower_plane(const ApplyArgs<T> &a, int k, int kn, T *lds, T *pl) {
     constexpr unsigned kArr = RecFmt<T, EPL>::kArr;
-    PolLower<T, EPL, HAS> pol;
+    PolLower<T, EPL, HAS, LP> pol;
     pol.rp = plane_rsrc<T, EPL>(a.rp, k, a.ny);
     pol.Zk = plane_rsrc<T, EPL>(a.Z, k, a.ny);
     pol.Zn = plane_rsrc<T, EPL>(a.Z, HAS ? kn : k, a.ny);
-    const RecFmt<T, EPL> F = rec_fmt<T, EPL>(a, k, pol.Zk);
+    pol.pl = pl;
+    const auto F = plane_fmt<T, EPL, LP>(a, k, pol.Zk, pl);
     pol.Gr = rec_plane<T, EPL>(a.rec, kn < k ? kn : k, a.ny);
     pol.vA = F.vA;
     pol.vG = F.vA + kRecG * kArr;
@@ -384,14 +436,16 @@ __device__ __forceinline__ void lower_plane(const ApplyArgs<T> &a, int k, int kn
 
 // Lower level-3 sweep of one half: half 0 takes planes 0..j3-1 upward, half 1
 // planes nz-1..j3+1 downward; z_k = Pt_k^{-1}(r_k - g * z_{k-+1}) into Z.
-template <typename T, int EPL>
-__device__ __forceinline__ void apply_lower(const ApplyArgs<T> &a, int h, T *lds) {
+// With LP, pl is this lane's slots of the LDS plane buffer (RecFmtL).
+template <typename T, int EPL, bool LP = false>
+__device__ __forceinline__ void apply_lower(const ApplyArgs<T> &a, int h, T *lds, T *pl = nullptr) {
     const int nz = a.nz, j3 = (nz - 1) / 2;
     const int dk = h == 0 ? 1 : -1;
     const int k0 = h == 0 ? 0 : nz - 1;
     if (h == 0 ? k0 >= j3 : k0 <= j3) return;
-    lower_plane<T, EPL, false>(a, k0, k0, lds);
-    for (int k = k0 + dk; h == 0 ? k < j3 : k > j3; k += dk) lower_plane<T, EPL, true>(a, k, k - dk, lds);
+    lower_plane<T, EPL, false, LP>(a, k0, k0, lds, pl);
+    for (int k = k0 + dk; h == 0 ? k < j3 : k > j3; k += dk)
+        lower_plane<T, EPL, true, LP>(a, k, k - dk, lds, pl);
 }
 
 // The twist plane j3 takes both neighbours; its result is final.
@@ -414,24 +468,34 @@ __device__ __forceinline__ void apply_twist(const ApplyArgs<T> &a, T *lds) {
     plane_solve<kApplyDepth<T, EPL>>(a.ny, F, pol, lds);
 }
 
-// Upper level-3 sweep: half 0 takes planes j3-1..0, half 1 planes j3+1..nz-1;
-// x_k = z_k - Pt_k^{-1}(g * x_{k+-1}), written over Z.
-template <typename T, int EPL>
-__device__ __forceinline__ void apply_upper(const ApplyArgs<T> &a, int h, T *lds) {
+template <typename T, int EPL, bool LPN, bool LP>
+__device__ __forceinline__ void upper_plane(const ApplyArgs<T> &a, int k, int kn, rsrc_t W, T *lds,
+                                            T *pl) {
     constexpr unsigned kArr = RecFmt<T, EPL>::kArr;
+    PolUpper<T, EPL, LPN, LP> pol;
+    pol.Zk = plane_rsrc<T, EPL>(a.Z, k, a.ny);
+    pol.Zn = plane_rsrc<T, EPL>(a.Z, kn, a.ny);
+    pol.pl = pl;
+    const auto F = plane_fmt<T, EPL, LP>(a, k, W, pl);
+    pol.Gr = rec_plane<T, EPL>(a.rec, kn < k ? kn : k, a.ny);
+    pol.vA = F.vA;
+    pol.vG = F.vA + kRecG * kArr;
+    plane_solve<kApplyDepth<T, EPL>>(a.ny, F, pol, lds);
+}
+
+// Upper level-3 sweep: half 0 takes planes j3-1..0, half 1 planes j3+1..nz-1;
+// x_k = z_k - Pt_k^{-1}(g * x_{k+-1}), written over Z.  With LP the first plane
+// reads the twist plane from Z and the others their neighbour from the LDS
+// plane buffer (pl, this lane's slots).
+template <typename T, int EPL, bool LP = false>
+__device__ __forceinline__ void apply_upper(const ApplyArgs<T> &a, int h, T *lds, T *pl = nullptr) {
     const int ny = a.ny, nz = a.nz, j3 = (nz - 1) / 2;
     const int dk = h == 0 ? -1 : 1;
     const rsrc_t W = make_rsrc(a.scratch + (size_t)h * ny * 64 * EPL);
     for (int k = j3 + dk; k >= 0 && k < nz; k += dk) {
         const int kn = k - dk;  // final neighbour, toward the twist plane
-        PolUpper<T, EPL> pol;
-        pol.Zk = plane_rsrc<T, EPL>(a.Z, k, ny);
-        pol.Zn = plane_rsrc<T, EPL>(a.Z, kn, ny);
-        const RecFmt<T, EPL> F = rec_fmt<T, EPL>(a, k, W);
-        pol.Gr = rec_plane<T, EPL>(a.rec, kn < k ? kn : k, ny);
-        pol.vA = F.vA;
-        pol.vG = F.vA + kRecG * kArr;
-        plane_solve<kApplyDepth<T, EPL>>(ny, F, pol, lds);
+        if (LP && kn != j3) upper_plane<T, EPL, LP, LP>(a, k, kn, W, lds, pl);
+        else upper_plane<T, EPL, false, LP>(a, k, kn, W, lds, pl);
     }
 }
 
@@ -515,6 +579,31 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply_upper_b(const ApplyArgs
     const BatchSlot b = batch_slot(count, nrhs, 2);
     if (!b.ok || !entry_active(active, b.e)) return;
     apply_upper<T, EPL>(load_uniform(tab + b.e), b.h, lds);
+}
+
+// The same with the plane buffer in LDS: plane_lds_bytes() of dynamic LDS, the
+// twist exchange (2*64*EPL values) and then the plane (ny lines of 64*EPL).
+extern __shared__ __attribute__((aligned(16))) unsigned char ntd_plane_lds[];
+
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_lower_bl(const ApplyArgs<T> *tab,
+                                                                  const int *active, int count,
+                                                                  int nrhs) {
+    T *lds = (T *)ntd_plane_lds;
+    T *pl = lds + 2 * 64 * EPL + (threadIdx.x & 63) * EPL;
+    const BatchSlot b = batch_slot(count, nrhs, 2);
+    if (!b.ok || !entry_active(active, b.e)) return;
+    apply_lower<T, EPL, true>(load_uniform(tab + b.e), b.h, lds, pl);
+}
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_upper_bl(const ApplyArgs<T> *tab,
+                                                                  const int *active, int count,
+                                                                  int nrhs) {
+    T *lds = (T *)ntd_plane_lds;
+    T *pl = lds + 2 * 64 * EPL + (threadIdx.x & 63) * EPL;
+    const BatchSlot b = batch_slot(count, nrhs, 2);
+    if (!b.ok || !entry_active(active, b.e)) return;
+    apply_upper<T, EPL, true>(load_uniform(tab + b.e), b.h, lds, pl);
 }
 
 // ---------------------------------------------------------------------------
@@ -698,21 +787,41 @@ hipError_t apply_impl(const ApplyArgs<T> &a, hipStream_t s, hipEvent_t *ev) {
 }
 
 // The sweeps of a batch of count systems x nrhs right-hand sides, as three
-// launches.
+// launches; plane_lds > 0: the lower and upper sweeps keep their planes in that
+// many bytes of LDS (plane_lds_bytes of the largest ny, after
+// apply_batch_lds_impl has allowed it).
 template <typename T, int EPL>
 hipError_t apply_batch_impl(const ApplyArgs<T> *tab, const int *active, int count, int nrhs,
-                            hipStream_t s, hipEvent_t *ev) {
+                            size_t plane_lds, hipStream_t s, hipEvent_t *ev) {
+    const dim3 g2(batch_grid(count, nrhs, 2)), g1(batch_grid(count, nrhs, 1));
+    const dim3 blk(kApplyThreads);
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL((k_apply_lower_b<T, EPL>), dim3(batch_grid(count, nrhs, 2)),
-                       dim3(kApplyThreads), 0, s, tab, active, count, nrhs);
+    if (plane_lds)
+        hipLaunchKernelGGL((k_apply_lower_bl<T, EPL>), g2, blk, plane_lds, s, tab, active, count,
+                           nrhs);
+    else
+        hipLaunchKernelGGL((k_apply_lower_b<T, EPL>), g2, blk, 0, s, tab, active, count, nrhs);
     if (ev) (void)hipEventRecord(ev[1], s);
-    hipLaunchKernelGGL((k_apply_twist_b<T, EPL>), dim3(batch_grid(count, nrhs, 1)),
-                       dim3(kApplyThreads), 0, s, tab, active, count, nrhs);
+    hipLaunchKernelGGL((k_apply_twist_b<T, EPL>), g1, blk, 0, s, tab, active, count, nrhs);
     if (ev) (void)hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL((k_apply_upper_b<T, EPL>), dim3(batch_grid(count, nrhs, 2)),
-                       dim3(kApplyThreads), 0, s, tab, active, count, nrhs);
+    if (plane_lds)
+        hipLaunchKernelGGL((k_apply_upper_bl<T, EPL>), g2, blk, plane_lds, s, tab, active, count,
+                           nrhs);
+    else
+        hipLaunchKernelGGL((k_apply_upper_b<T, EPL>), g2, blk, 0, s, tab, active, count, nrhs);
     if (ev) (void)hipEventRecord(ev[3], s);
     return hipGetLastError();
+}
+
+// Allow the LDS-plane sweeps `bytes` of dynamic LDS.
+template <typename T, int EPL>
+hipError_t apply_batch_lds_impl(size_t bytes) {
+    hipError_t e = hipFuncSetAttribute((const void *)&k_apply_lower_bl<T, EPL>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)&k_apply_upper_bl<T, EPL>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return e;
 }
 
 template <typename T, int EPL>

@@ -41,9 +41,20 @@ hipError_t launch_unpack_f64(const XferArgs<double> &x, int epl, hipStream_t s, 
 }
 
 hipError_t launch_apply_batch_f64(const ApplyArgs<double> *tab, const int *active, int count,
-                                  int nrhs, int epl, hipStream_t s, hipEvent_t *ev) {
+                                  int nrhs, int epl, size_t plane_lds, hipStream_t s,
+                                  hipEvent_t *ev) {
     switch (epl) {
-#define NTD_CASE(E) case E: return apply_batch_impl<double, E>(tab, active, count, nrhs, s, ev);
+#define NTD_CASE(E) \
+    case E: return apply_batch_impl<double, E>(tab, active, count, nrhs, plane_lds, s, ev);
+        NTD_BATCH_EPL_LIST(NTD_CASE)
+#undef NTD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t allow_apply_batch_lds_f64(int epl, size_t bytes) {
+    switch (epl) {
+#define NTD_CASE(E) case E: return apply_batch_lds_impl<double, E>(bytes);
         NTD_BATCH_EPL_LIST(NTD_CASE)
 #undef NTD_CASE
     default: return hipErrorInvalidValue;

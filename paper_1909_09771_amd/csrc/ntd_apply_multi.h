@@ -81,11 +81,30 @@ struct RecFmtM {
     }
 };
 
+// RecFmtM with the level-2 lower results in LDS plane buffers, one per
+// right-hand side (plane q at pl + q*ps), as RecFmtL.
+template <typename T, int EPL, int NR>
+struct RecFmtML : RecFmtM<T, EPL, NR> {
+    T *pl;  // this lane's slots of line 0 of plane buffer 0
+    int ps; // values per plane buffer (ny lines)
+    __device__ void load_w(int m, T (&w)[NR][EPL]) const {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) lds_ld<T, EPL>(pl + q * ps + m * 64 * EPL, w[q]);
+    }
+    __device__ void store_w(int m, int q, const T (&w)[EPL]) const {
+        lds_st<T, EPL>(pl + q * ps + m * 64 * EPL, w);
+    }
+};
+
 // Lower level-3 step of plane k for NR right-hand sides: rhs_q = r_q - g z_q(kn).
-template <typename T, int EPL, int NR, bool HAS>
+// LP: z_q(kn) comes from the LDS plane buffers (pl, ps as RecFmtML), and
+// z_q(k) goes there too.
+template <typename T, int EPL, int NR, bool HAS, bool LP = false>
 struct PolLowerM {
     rsrc_t rp[NR], Zn[NR], Zk[NR], Gr;  // Gr: the records holding g
     unsigned vA, vG;
+    T *pl;
+    int ps;
     __device__ void load_rhs(int m, const RecFmtM<T, EPL, NR> &, LineInM<T, EPL, NR> &in) const {
         constexpr unsigned kLine = RecFmt<T, EPL>::kLine;
 #pragma unroll
@@ -93,7 +112,10 @@ struct PolLowerM {
         if constexpr (HAS) {
             vload(Gr, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.g);
 #pragma unroll
-            for (int q = 0; q < NR; ++q) vload(Zn[q], vA, (unsigned)m * kLine, in.q1[q]);
+            for (int q = 0; q < NR; ++q) {
+                if constexpr (LP) lds_ld<T, EPL>(pl + q * ps + m * 64 * EPL, in.q1[q]);
+                else vload(Zn[q], vA, (unsigned)m * kLine, in.q1[q]);
+            }
         }
     }
     __device__ T rhs(const LineInM<T, EPL, NR> &in, int q, int s) const {
@@ -103,6 +125,7 @@ struct PolLowerM {
     __device__ void load_out(int, const RecFmtM<T, EPL, NR> &, LineInM<T, EPL, NR> &) const {}
     __device__ void out(int m, int q, const T (&x)[EPL], const LineInM<T, EPL, NR> &) {
         vstore(Zk[q], vA, (unsigned)m * RecFmt<T, EPL>::kLine, x);
+        if constexpr (LP) lds_st<T, EPL>(pl + q * ps + m * 64 * EPL, x);
     }
 };
 
@@ -147,15 +170,20 @@ struct PolTwistM {
 
 // Upper level-3 step of plane k for NR right-hand sides: c_q = Pt_k^{-1}(g x_q(kn)),
 // x_q(k) = z_q(k) - c_q over Z_q.  q0 carries the level-2 lower result (load_w).
-template <typename T, int EPL, int NR>
+// LPN: x_q(kn) comes from the LDS plane buffers; LPO: x_q(k) goes there too.
+template <typename T, int EPL, int NR, bool LPN = false, bool LPO = false>
 struct PolUpperM {
     rsrc_t Zn[NR], Zk[NR], Gr;  // Gr: the records holding g (the lower of planes k, kn)
     unsigned vA, vG;
+    T *pl;
+    int ps;
     __device__ void load_rhs(int m, const RecFmtM<T, EPL, NR> &, LineInM<T, EPL, NR> &in) const {
         vload(Gr, vG, (unsigned)m * RecFmt<T, EPL>::kRec, in.g);
 #pragma unroll
-        for (int q = 0; q < NR; ++q)
-            vload(Zn[q], vA, (unsigned)m * RecFmt<T, EPL>::kLine, in.q1[q]);
+        for (int q = 0; q < NR; ++q) {
+            if constexpr (LPN) lds_ld<T, EPL>(pl + q * ps + m * 64 * EPL, in.q1[q]);
+            else vload(Zn[q], vA, (unsigned)m * RecFmt<T, EPL>::kLine, in.q1[q]);
+        }
     }
     __device__ T rhs(const LineInM<T, EPL, NR> &in, int q, int s) const {
         return in.g[s] * in.q1[q][s];
@@ -170,6 +198,7 @@ struct PolUpperM {
 #pragma unroll
         for (int s = 0; s < EPL; ++s) xv[s] = in.q2[q][s] - c[s];
         vstore(Zk[q], vA, (unsigned)m * RecFmt<T, EPL>::kLine, xv);
+        if constexpr (LPO) lds_st<T, EPL>(pl + q * ps + m * 64 * EPL, xv);
     }
 };
 
@@ -349,19 +378,37 @@ __device__ void plane_solve_m(int ny, const Fmt &fmt, Pol &pol, typename Fmt::Ty
 template <typename T, int EPL, int NR>
 constexpr int kApplyDepthM = (sizeof(T) * EPL * NR <= 32) ? 2 : 1;
 
-template <typename T, int EPL, int NR>
-__device__ __forceinline__ RecFmtM<T, EPL, NR> rec_fmt_m(const ApplyArgs<T> (&a)[NR], int k) {
-    RecFmtM<T, EPL, NR> F;
+template <typename T, int EPL, int NR, class Fmt = RecFmtM<T, EPL, NR>>
+__device__ __forceinline__ Fmt rec_fmt_m(const ApplyArgs<T> (&a)[NR], int k) {
+    Fmt F;
     F.rec = rec_plane<T, EPL>(a[0].rec, k, a[0].ny);
     return F;
 }
 
-template <typename T, int EPL, int NR, bool HAS>
-__device__ __forceinline__ void lower_plane_m(const ApplyArgs<T> (&a)[NR], int k, int kn, T *lds) {
+// The plane format for NR right-hand sides; with LP the level-2 lower results
+// go to the LDS plane buffers (pl, ps).
+template <typename T, int EPL, int NR, bool LP>
+using PlaneFmtM =
+    typename std::conditional<LP, RecFmtML<T, EPL, NR>, RecFmtM<T, EPL, NR>>::type;
+
+template <typename T, int EPL, int NR, bool LP>
+__device__ __forceinline__ PlaneFmtM<T, EPL, NR, LP> plane_fmt_m(const ApplyArgs<T> (&a)[NR],
+                                                                 int k, T *pl, int ps) {
+    PlaneFmtM<T, EPL, NR, LP> F = rec_fmt_m<T, EPL, NR, PlaneFmtM<T, EPL, NR, LP>>(a, k);
+    if constexpr (LP) {
+        F.pl = pl;
+        F.ps = ps;
+    }
+    return F;
+}
+
+template <typename T, int EPL, int NR, bool HAS, bool LP>
+__device__ __forceinline__ void lower_plane_m(const ApplyArgs<T> (&a)[NR], int k, int kn, T *lds,
+                                              T *pl) {
     constexpr unsigned kArr = RecFmt<T, EPL>::kArr;
     const int ny = a[0].ny;
-    PolLowerM<T, EPL, NR, HAS> pol;
-    RecFmtM<T, EPL, NR> F = rec_fmt_m<T, EPL, NR>(a, k);
+    PolLowerM<T, EPL, NR, HAS, LP> pol;
+    auto F = plane_fmt_m<T, EPL, NR, LP>(a, k, pl, ny * 64 * EPL);
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         pol.rp[q] = plane_rsrc<T, EPL>(a[q].rp, k, ny);
@@ -369,21 +416,26 @@ __device__ __forceinline__ void lower_plane_m(const ApplyArgs<T> (&a)[NR], int k
         pol.Zn[q] = plane_rsrc<T, EPL>(a[q].Z, HAS ? kn : k, ny);
         F.W[q] = pol.Zk[q];
     }
+    pol.pl = pl;
+    pol.ps = ny * 64 * EPL;
     pol.Gr = rec_plane<T, EPL>(a[0].rec, kn < k ? kn : k, ny);
     pol.vA = F.vA;
     pol.vG = F.vA + kRecG * kArr;
     plane_solve_m<kApplyDepthM<T, EPL, NR>>(ny, F, pol, lds);
 }
 
-template <typename T, int EPL, int NR>
-__device__ __forceinline__ void apply_lower_m(const ApplyArgs<T> (&a)[NR], int h, T *lds) {
+// With LP, pl is this lane's slots of the first of NR LDS plane buffers of ny
+// lines each.
+template <typename T, int EPL, int NR, bool LP = false>
+__device__ __forceinline__ void apply_lower_m(const ApplyArgs<T> (&a)[NR], int h, T *lds,
+                                              T *pl = nullptr) {
     const int nz = a[0].nz, j3 = (nz - 1) / 2;
     const int dk = h == 0 ? 1 : -1;
     const int k0 = h == 0 ? 0 : nz - 1;
     if (h == 0 ? k0 >= j3 : k0 <= j3) return;
-    lower_plane_m<T, EPL, NR, false>(a, k0, k0, lds);
+    lower_plane_m<T, EPL, NR, false, LP>(a, k0, k0, lds, pl);
     for (int k = k0 + dk; h == 0 ? k < j3 : k > j3; k += dk)
-        lower_plane_m<T, EPL, NR, true>(a, k, k - dk, lds);
+        lower_plane_m<T, EPL, NR, true, LP>(a, k, k - dk, lds, pl);
 }
 
 template <typename T, int EPL, int NR>
@@ -409,25 +461,38 @@ __device__ __forceinline__ void apply_twist_m(const ApplyArgs<T> (&a)[NR], T *ld
     plane_solve_m<kApplyDepthM<T, EPL, NR>>(ny, F, pol, lds);
 }
 
-template <typename T, int EPL, int NR>
-__device__ __forceinline__ void apply_upper_m(const ApplyArgs<T> (&a)[NR], int h, T *lds) {
+template <typename T, int EPL, int NR, bool LPN, bool LP>
+__device__ __forceinline__ void upper_plane_m(const ApplyArgs<T> (&a)[NR], int h, int k, int kn,
+                                              T *lds, T *pl) {
     constexpr unsigned kArr = RecFmt<T, EPL>::kArr;
-    const int ny = a[0].ny, nz = a[0].nz, j3 = (nz - 1) / 2;
+    const int ny = a[0].ny;
+    PolUpperM<T, EPL, NR, LPN, LP> pol;
+    auto F = plane_fmt_m<T, EPL, NR, LP>(a, k, pl, ny * 64 * EPL);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        pol.Zk[q] = plane_rsrc<T, EPL>(a[q].Z, k, ny);
+        pol.Zn[q] = plane_rsrc<T, EPL>(a[q].Z, kn, ny);
+        F.W[q] = make_rsrc(a[q].scratch + (size_t)h * ny * 64 * EPL);
+    }
+    pol.pl = pl;
+    pol.ps = ny * 64 * EPL;
+    pol.Gr = rec_plane<T, EPL>(a[0].rec, kn < k ? kn : k, ny);
+    pol.vA = F.vA;
+    pol.vG = F.vA + kRecG * kArr;
+    plane_solve_m<kApplyDepthM<T, EPL, NR>>(ny, F, pol, lds);
+}
+
+// With LP the first plane reads the twist plane from Z and the others their
+// neighbour from the LDS plane buffers.
+template <typename T, int EPL, int NR, bool LP = false>
+__device__ __forceinline__ void apply_upper_m(const ApplyArgs<T> (&a)[NR], int h, T *lds,
+                                              T *pl = nullptr) {
+    const int nz = a[0].nz, j3 = (nz - 1) / 2;
     const int dk = h == 0 ? -1 : 1;
     for (int k = j3 + dk; k >= 0 && k < nz; k += dk) {
         const int kn = k - dk;
-        PolUpperM<T, EPL, NR> pol;
-        RecFmtM<T, EPL, NR> F = rec_fmt_m<T, EPL, NR>(a, k);
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            pol.Zk[q] = plane_rsrc<T, EPL>(a[q].Z, k, ny);
-            pol.Zn[q] = plane_rsrc<T, EPL>(a[q].Z, kn, ny);
-            F.W[q] = make_rsrc(a[q].scratch + (size_t)h * ny * 64 * EPL);
-        }
-        pol.Gr = rec_plane<T, EPL>(a[0].rec, kn < k ? kn : k, ny);
-        pol.vA = F.vA;
-        pol.vG = F.vA + kRecG * kArr;
-        plane_solve_m<kApplyDepthM<T, EPL, NR>>(ny, F, pol, lds);
+        if (LP && kn != j3) upper_plane_m<T, EPL, NR, LP, LP>(a, h, k, kn, lds, pl);
+        else upper_plane_m<T, EPL, NR, false, LP>(a, h, k, kn, lds, pl);
     }
 }
 
@@ -485,23 +550,67 @@ __global__ void __launch_bounds__(kApplyThreads) k_apply_upper_bm(const ApplyArg
     apply_upper_m<T, EPL, NR>(a, h, lds);
 }
 
+// The same with NR plane buffers in dynamic LDS: the twist exchange
+// (2*64*EPL*NR values), then NR planes of the group's ny lines.
+template <typename T, int EPL, int NR>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_lower_bml(const ApplyArgs<T> *tab,
+                                                                   const int *active, int count,
+                                                                   int nrhs) {
+    T *lds = (T *)ntd_plane_lds;
+    T *pl = lds + 2 * 64 * EPL * NR + (threadIdx.x & 63) * EPL;
+    ApplyArgs<T> a[NR];
+    int h;
+    if (!multi_slot<T, NR>(tab, active, count, nrhs, 2, a, h)) return;
+    apply_lower_m<T, EPL, NR, true>(a, h, lds, pl);
+}
+template <typename T, int EPL, int NR>
+__global__ void __launch_bounds__(kApplyThreads) k_apply_upper_bml(const ApplyArgs<T> *tab,
+                                                                   const int *active, int count,
+                                                                   int nrhs) {
+    T *lds = (T *)ntd_plane_lds;
+    T *pl = lds + 2 * 64 * EPL * NR + (threadIdx.x & 63) * EPL;
+    ApplyArgs<T> a[NR];
+    int h;
+    if (!multi_slot<T, NR>(tab, active, count, nrhs, 2, a, h)) return;
+    apply_upper_m<T, EPL, NR, true>(a, h, lds, pl);
+}
+
 // The sweeps of a batch with NR right-hand sides per wavefront pair (nrhs a
 // multiple of NR), as three launches; ev (optional, 4 events) brackets them.
+// plane_lds > 0: the lower and upper sweeps keep their NR planes in that many
+// bytes of LDS (NR * plane_lds_bytes of the largest ny, after
+// apply_batch_multi_lds_impl has allowed it).
 template <typename T, int EPL, int NR>
 hipError_t apply_batch_multi_impl(const ApplyArgs<T> *tab, const int *active, int count, int nrhs,
-                                  hipStream_t s, hipEvent_t *ev) {
-    const unsigned groups = (unsigned)(count * (nrhs / NR));
+                                  size_t plane_lds, hipStream_t s, hipEvent_t *ev) {
+    const dim3 g2(2 * (unsigned)(count * (nrhs / NR))), g1((unsigned)(count * (nrhs / NR)));
+    const dim3 blk(kApplyThreads);
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL((k_apply_lower_bm<T, EPL, NR>), dim3(2 * groups), dim3(kApplyThreads), 0, s,
-                       tab, active, count, nrhs);
+    if (plane_lds)
+        hipLaunchKernelGGL((k_apply_lower_bml<T, EPL, NR>), g2, blk, plane_lds, s, tab, active,
+                           count, nrhs);
+    else
+        hipLaunchKernelGGL((k_apply_lower_bm<T, EPL, NR>), g2, blk, 0, s, tab, active, count, nrhs);
     if (ev) (void)hipEventRecord(ev[1], s);
-    hipLaunchKernelGGL((k_apply_twist_bm<T, EPL, NR>), dim3(groups), dim3(kApplyThreads), 0, s,
-                       tab, active, count, nrhs);
+    hipLaunchKernelGGL((k_apply_twist_bm<T, EPL, NR>), g1, blk, 0, s, tab, active, count, nrhs);
     if (ev) (void)hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL((k_apply_upper_bm<T, EPL, NR>), dim3(2 * groups), dim3(kApplyThreads), 0, s,
-                       tab, active, count, nrhs);
+    if (plane_lds)
+        hipLaunchKernelGGL((k_apply_upper_bml<T, EPL, NR>), g2, blk, plane_lds, s, tab, active,
+                           count, nrhs);
+    else
+        hipLaunchKernelGGL((k_apply_upper_bm<T, EPL, NR>), g2, blk, 0, s, tab, active, count, nrhs);
     if (ev) (void)hipEventRecord(ev[3], s);
     return hipGetLastError();
+}
+
+template <typename T, int EPL, int NR>
+hipError_t apply_batch_multi_lds_impl(size_t bytes) {
+    hipError_t e = hipFuncSetAttribute((const void *)&k_apply_lower_bml<T, EPL, NR>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)&k_apply_upper_bml<T, EPL, NR>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return e;
 }
 
 }  // namespace

@@ -1,26 +1,56 @@
 // ntd_apply_multi_f64.hip -- instantiation of the batched sweeps with several
 // right-hand sides per wavefront pair, in double.
+#include <utility>
+
 #include "ntd_apply_multi.h"
 
 namespace ntd {
 
-hipError_t launch_apply_batch_multi_f64(const ApplyArgs<double> *tab, const int *active, int count,
-                                        int nrhs, int epl, int nr, hipStream_t s, hipEvent_t *ev) {
-    if (nr < 2 || nrhs % nr != 0 || !batch_multi_ok((int)sizeof(double), epl, nr))
-        return hipErrorInvalidValue;
+namespace {
+
+// The built (EPL, NR) instances, as ntd::batch_multi_ok lists them.
+template <template <typename, int, int> class F, typename... A>
+hipError_t dispatch_f64(int epl, int nr, A &&...args) {
     if (nr == 2) {
         switch (epl) {
-        case 1: return apply_batch_multi_impl<double, 1, 2>(tab, active, count, nrhs, s, ev);
-        case 2: return apply_batch_multi_impl<double, 2, 2>(tab, active, count, nrhs, s, ev);
+        case 1: return F<double, 1, 2>::run(std::forward<A>(args)...);
+        case 2: return F<double, 2, 2>::run(std::forward<A>(args)...);
         default: break;
         }
     } else if (nr == 4) {
         switch (epl) {
-        case 1: return apply_batch_multi_impl<double, 1, 4>(tab, active, count, nrhs, s, ev);
+        case 1: return F<double, 1, 4>::run(std::forward<A>(args)...);
         default: break;
         }
     }
     return hipErrorInvalidValue;
+}
+
+template <typename T, int EPL, int NR>
+struct Sweeps {
+    static hipError_t run(const ApplyArgs<T> *tab, const int *active, int count, int nrhs,
+                          size_t plane_lds, hipStream_t s, hipEvent_t *ev) {
+        return apply_batch_multi_impl<T, EPL, NR>(tab, active, count, nrhs, plane_lds, s, ev);
+    }
+};
+template <typename T, int EPL, int NR>
+struct AllowLds {
+    static hipError_t run(size_t bytes) { return apply_batch_multi_lds_impl<T, EPL, NR>(bytes); }
+};
+
+}  // namespace
+
+hipError_t launch_apply_batch_multi_f64(const ApplyArgs<double> *tab, const int *active, int count,
+                                        int nrhs, int epl, int nr, size_t plane_lds, hipStream_t s,
+                                        hipEvent_t *ev) {
+    if (nr < 2 || nrhs % nr != 0 || !batch_multi_ok((int)sizeof(double), epl, nr))
+        return hipErrorInvalidValue;
+    return dispatch_f64<Sweeps>(epl, nr, tab, active, count, nrhs, plane_lds, s, ev);
+}
+
+hipError_t allow_apply_batch_multi_lds_f64(int epl, int nr, size_t bytes) {
+    if (nr < 2 || !batch_multi_ok((int)sizeof(double), epl, nr)) return hipErrorInvalidValue;
+    return dispatch_f64<AllowLds>(epl, nr, bytes);
 }
 
 }  // namespace ntd

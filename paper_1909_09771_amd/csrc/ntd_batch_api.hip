@@ -41,6 +41,12 @@ using ntd_host::Carver;
 struct ntd_batch {
     int count = 0, nrhs = 0, prec = 0, epl = 0, gx = 0, gx_max = 0, D = 0;
     int nr = 1;  // right-hand sides per wavefront pair in the line sweeps
+    // LDS plane buffers of the line sweeps: wanted (the default), and for
+    // nr = 1, 2, 4 the dynamic LDS per workgroup when the device holds every
+    // workgroup of a sweep at once with its nr buffers (else 0: planes go
+    // through memory)
+    int lds_want = 1;
+    size_t plane_lds[3] = {0, 0, 0};
     size_t used = 0;
     std::vector<ntd_handle *> sys;
     // device tables
@@ -245,18 +251,57 @@ hipError_t pack_b(const ntd_batch *b, const void *tab, const int *act, hipStream
     return ntd::launch_pack_rhs_batch_f32((const ntd::XferArgs<float> *)tab, act, b->D, b->gx,
                                           b->epl, s);
 }
+int nr_index(int nr) { return nr == 1 ? 0 : nr == 2 ? 1 : 2; }
+
+size_t sweep_lds(const ntd_batch *b) { return b->lds_want ? b->plane_lds[nr_index(b->nr)] : 0; }
+
 hipError_t sweeps_b(const ntd_batch *b, const int *act, hipStream_t s, hipEvent_t *ev) {
     if (b->prec == NTD_PREC_FP64) {
         const auto *tab = (const ntd::ApplyArgs<double> *)b->tabA;
         if (b->nr > 1)
-            return ntd::launch_apply_batch_multi_f64(tab, act, b->count, b->nrhs, b->epl, b->nr, s,
-                                                     ev);
-        return ntd::launch_apply_batch_f64(tab, act, b->count, b->nrhs, b->epl, s, ev);
+            return ntd::launch_apply_batch_multi_f64(tab, act, b->count, b->nrhs, b->epl, b->nr,
+                                                     sweep_lds(b), s, ev);
+        return ntd::launch_apply_batch_f64(tab, act, b->count, b->nrhs, b->epl, sweep_lds(b), s,
+                                           ev);
     }
     const auto *tab = (const ntd::ApplyArgs<float> *)b->tabA;
     if (b->nr > 1)
-        return ntd::launch_apply_batch_multi_f32(tab, act, b->count, b->nrhs, b->epl, b->nr, s, ev);
-    return ntd::launch_apply_batch_f32(tab, act, b->count, b->nrhs, b->epl, s, ev);
+        return ntd::launch_apply_batch_multi_f32(tab, act, b->count, b->nrhs, b->epl, b->nr,
+                                                 sweep_lds(b), s, ev);
+    return ntd::launch_apply_batch_f32(tab, act, b->count, b->nrhs, b->epl, sweep_lds(b), s, ev);
+}
+
+// Dynamic LDS per workgroup for the LDS-plane sweeps of the batch with nr
+// right-hand sides per wavefront pair, or 0 when the device cannot hold every
+// workgroup of a sweep at once with its nr plane buffers: the sweeps are a
+// latency-bound chain per workgroup, and workgroups waiting for a free CU would
+// double the launch.
+size_t plane_lds_fit(int count, const int *dims, int nrhs, int prec, int epl, int nr) {
+    int ny_max = 1;
+    for (int s = 0; s < count; ++s)
+        if (dims[3 * s + 1] > ny_max) ny_max = dims[3 * s + 1];
+    const size_t tsz = prec == NTD_PREC_MIXED ? sizeof(float) : sizeof(double);
+    const size_t bytes = (size_t)nr * ntd::plane_lds_bytes(ny_max, epl, tsz);
+    int dev = 0, per_block = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (bytes > (size_t)per_block || per_cu <= 0 || cus <= 0) return 0;
+    const long long per = (long long)((size_t)per_cu / bytes);  // workgroups per CU
+    const long long wgs = 2LL * count * (nrhs / nr);            // two level-3 halves each
+    if (per * cus < wgs) return 0;
+    hipError_t e;
+    if (nr == 1)
+        e = prec == NTD_PREC_MIXED ? ntd::allow_apply_batch_lds_f32(epl, bytes)
+                                   : ntd::allow_apply_batch_lds_f64(epl, bytes);
+    else
+        e = prec == NTD_PREC_MIXED ? ntd::allow_apply_batch_multi_lds_f32(epl, nr, bytes)
+                                   : ntd::allow_apply_batch_multi_lds_f64(epl, nr, bytes);
+    return e == hipSuccess ? bytes : 0;
 }
 
 // Can the batch's sweeps run nr right-hand sides per wavefront pair?
@@ -476,6 +521,9 @@ int ntd_batch_setup(int count, const int *dims, const double *const *kappa, cons
                                                       : upload_static_tables<double>(b, *w, s);
         if (err != hipSuccess) st = NTD_EHIP;
     }
+    for (int nr : {1, 2, 4})
+        if (st == NTD_OK && nr_ok(b, nr))
+            b->plane_lds[nr_index(nr)] = plane_lds_fit(count, dims, nrhs, prec, b->epl, nr);
     delete w;
     if (st != NTD_OK) {
         release(b);
@@ -658,6 +706,14 @@ int ntd_batch_set_sweep_group(ntd_batch *b, int nr) {
     if (!b || !nr_ok(b, nr)) return NTD_EINVAL;
     if (b->nr != nr) drop_graph(b);
     b->nr = nr;
+    return NTD_OK;
+}
+
+int ntd_batch_set_plane_lds(ntd_batch *b, int on, int *used) {
+    if (!b || (on != 0 && on != 1)) return NTD_EINVAL;
+    if (b->lds_want != on) drop_graph(b);
+    b->lds_want = on;
+    if (used) *used = sweep_lds(b) > 0 ? 1 : 0;
     return NTD_OK;
 }
 

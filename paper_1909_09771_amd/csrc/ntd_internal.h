@@ -180,19 +180,36 @@ hipError_t launch_pack_f32(const PackArgs &p, int epl, hipStream_t s);
 // with nrhs right-hand sides each (the moves: `count` = all entries, one grid
 // row per entry); an entry whose active flag is 0 does nothing (active may be
 // null: all entries run).
+// plane_lds > 0: the lower and upper sweeps keep each plane in LDS, that many
+// bytes per workgroup (plane_lds_bytes of the batch's largest ny), after
+// allow_apply_batch_lds_* has allowed it; 0: planes go through memory.
 hipError_t launch_apply_batch_f32(const ApplyArgs<float> *tab, const int *active, int count,
-                                  int nrhs, int epl, hipStream_t s, hipEvent_t *ev);
+                                  int nrhs, int epl, size_t plane_lds, hipStream_t s,
+                                  hipEvent_t *ev);
 hipError_t launch_apply_batch_f64(const ApplyArgs<double> *tab, const int *active, int count,
-                                  int nrhs, int epl, hipStream_t s, hipEvent_t *ev);
+                                  int nrhs, int epl, size_t plane_lds, hipStream_t s,
+                                  hipEvent_t *ev);
+hipError_t allow_apply_batch_lds_f32(int epl, size_t bytes);
+hipError_t allow_apply_batch_lds_f64(int epl, size_t bytes);
+// Dynamic LDS of the LDS-plane sweeps: the twist exchange (two lines) and one
+// plane of ny lines, 64*epl slots each.
+constexpr size_t plane_lds_bytes(int ny, int epl, size_t tsz) {
+    return (size_t)(2 + ny) * 64u * (size_t)epl * tsz;
+}
 // The same sweeps with nr right-hand sides of one system per wavefront pair
 // (nr = 2 or 4 dividing nrhs; batch_multi_ok tells which (precision, EPL, nr)
 // are built).
 bool batch_multi_ok(int elem_bytes, int epl, int nr);
+// plane_lds as for launch_apply_batch_*: NR plane buffers, NR times
+// plane_lds_bytes of the largest ny, after allow_apply_batch_multi_lds_*.
 hipError_t launch_apply_batch_multi_f32(const ApplyArgs<float> *tab, const int *active, int count,
-                                        int nrhs, int epl, int nr, hipStream_t s, hipEvent_t *ev);
-hipError_t launch_apply_batch_multi_f64(const ApplyArgs<double> *tab, const int *active,
-                                        int count, int nrhs, int epl, int nr, hipStream_t s,
+                                        int nrhs, int epl, int nr, size_t plane_lds, hipStream_t s,
                                         hipEvent_t *ev);
+hipError_t launch_apply_batch_multi_f64(const ApplyArgs<double> *tab, const int *active,
+                                        int count, int nrhs, int epl, int nr, size_t plane_lds,
+                                        hipStream_t s, hipEvent_t *ev);
+hipError_t allow_apply_batch_multi_lds_f32(int epl, int nr, size_t bytes);
+hipError_t allow_apply_batch_multi_lds_f64(int epl, int nr, size_t bytes);
 hipError_t launch_pack_rhs_batch_f32(const XferArgs<float> *tab, const int *active, int count,
                                      int gx, int epl, hipStream_t s);
 hipError_t launch_pack_rhs_batch_f64(const XferArgs<double> *tab, const int *active, int count,

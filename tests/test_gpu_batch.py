@@ -278,3 +278,73 @@ def test_batch_tune_sweeps_picks_a_supported_group(systems):
             B2.set_sweep_group(2)      # 2 does not divide 3 right-hand sides
         finally:
             B2.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_batch_plane_lds_matches_memory_bitwise(systems, prec):
+    """The line sweeps keeping each plane in LDS (the default where every
+    workgroup fits at once, as these small systems do) give the results of the
+    sweeps through memory bit for bit: apply, and PCG through the graph; also
+    with 2 and 4 right-hand sides per wavefront pair."""
+    nrhs = 4
+    B = make_batch(systems, nrhs, prec, "newton")
+    assert B.set_plane_lds(True)
+    rs = [G(r) for r in rhs_list(systems, nrhs, 51)]
+    z_lds = [C(z) for z in B.apply(rs)]
+    assert not B.set_plane_lds(False)
+    z_mem = [C(z) for z in B.apply(rs)]
+    for e, (a, b) in enumerate(zip(z_lds, z_mem)):
+        assert np.array_equal(a, b), "entry %d" % e
+    bs = [G(b) for b in rhs_list(systems, nrhs, 52)]
+    x0, i0, r0, s0 = B.pcg(bs, tol=1e-8, maxit=500, graph=True)
+    assert B.set_plane_lds(True)
+    x1, i1, r1, s1 = B.pcg(bs, tol=1e-8, maxit=500, graph=True)
+    assert i0 == i1 and s0 == s1
+    for e, (a, b) in enumerate(zip(x0, x1)):
+        assert np.array_equal(C(a), C(b)), "entry %d" % e
+    # several right-hand sides per wavefront pair: one plane buffer each
+    import paper_1909_09771_amd as P
+    for nr in (2, 4):
+        if nr > nrhs:
+            continue
+        try:
+            B.set_sweep_group(nr)
+        except P.NTDError as e:   # not built for this precision and line length
+            assert e.status == P.EINVAL
+            continue
+        assert B.set_plane_lds(True)
+        z_lds = [C(z) for z in B.apply(rs)]
+        B.set_plane_lds(False)
+        z_mem2 = [C(z) for z in B.apply(rs)]
+        for e, (a, b, c) in enumerate(zip(z_lds, z_mem2, z_mem)):
+            assert np.array_equal(a, b) and np.array_equal(a, c), "nr %d entry %d" % (nr, e)
+    B.close()
+
+
+# degenerate level-3 and level-2 chains: one plane, two planes (no interior
+# plane on either side of the twist), one line per plane, and four planes
+EDGE_SYSTEMS = [((1, 6, 9), "rand", 11), ((2, 5, 17), "rand", 12), ((6, 1, 30), "layers", 13),
+                ((4, 3, 64), "rand", 14)]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("mixed", 1e-5)])
+def test_batch_plane_lds_edge_shapes(prec, tol):
+    """Degenerate shapes through the LDS-plane sweeps: oracle parity element by
+    element, and bitwise the sweeps through memory."""
+    syst = []
+    for shape, kind, seed in EDGE_SYSTEMS:
+        kappa, bc = build(kind, shape, seed)
+        syst.append(dict(shape=shape, kappa=kappa, bc=bc, bands=O.assemble(kappa, bc)))
+    nrhs = 2
+    B = make_batch(syst, nrhs, prec, "newton")
+    assert B.set_plane_lds(True)
+    rs = rhs_list(syst, nrhs, 53)
+    z_lds = [C(z) for z in B.apply([G(r) for r in rs])]
+    B.set_plane_lds(False)
+    z_mem = [C(z) for z in B.apply([G(r) for r in rs])]
+    for e, (r, a, b) in enumerate(zip(rs, z_lds, z_mem)):
+        s = syst[e // nrhs]
+        assert np.array_equal(a, b), "entry %d" % e
+        want = O.apply(O.setup(s["bands"], mode="newton"), r)
+        assert relelem(a, want) <= tol, "entry %d" % e
+    B.close()
