@@ -99,20 +99,79 @@ __global__ void __launch_bounds__(kBlock) k_spmv(Grid g, const double *__restric
         int i = (int)(p % g.nx);
         int j = (int)((p / g.nx) % g.ny);
         int k = (int)(p / g.nxy);
+        // every neighbour term is one fused multiply-add onto the running sum
+        // (written out, so that no contraction choice can reorder it)
         double xp = x[p];
         double s = d[p] * xp;
-        if (i > 0) s += ax[p - 1] * x[p - 1];
-        if (i < g.nx - 1) s += ax[p] * x[p + 1];
-        if (j > 0) s += ay[p - g.nx] * x[p - g.nx];
-        if (j < g.ny - 1) s += ay[p] * x[p + g.nx];
-        if (k > 0) s += az[p - g.nxy] * x[p - g.nxy];
-        if (k < g.nz - 1) s += az[p] * x[p + g.nxy];
+        if (i > 0) s = fma(ax[p - 1], x[p - 1], s);
+        if (i < g.nx - 1) s = fma(ax[p], x[p + 1], s);
+        if (j > 0) s = fma(ay[p - g.nx], x[p - g.nx], s);
+        if (j < g.ny - 1) s = fma(ay[p], x[p + g.nx], s);
+        if (k > 0) s = fma(az[p - g.nxy], x[p - g.nxy], s);
+        if (k < g.nz - 1) s = fma(az[p], x[p + g.nxy], s);
         y[p] = s;
         acc += xp * s;
     }
     if (partials) {
         double t = block_sum(acc);
         if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    }
+}
+
+// y = A x for two consecutive points of a line per thread, with 16-byte loads
+// of every pair (nx even, all arrays 16-byte aligned, N < 2^31), one pair per
+// thread.  The stencil is bound by the load instructions it issues, not by its
+// bytes, and a pair needs 14 where two single points need 28.  Each point's sum
+// is formed in k_spmv's order, so y is bitwise k_spmv's.  It serves the
+// products without a dot partial; the PCG's q = A p keeps k_spmv, whose fixed
+// grid also fixes the summation order of p.q.
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ dbl2 ld2(const double *p) { return *(const dbl2 *)p; }
+
+__global__ void __launch_bounds__(kBlock) k_spmv2(Grid g, const double *__restrict__ d,
+                                                  const double *__restrict__ ax,
+                                                  const double *__restrict__ ay,
+                                                  const double *__restrict__ az,
+                                                  const double *__restrict__ x,
+                                                  double *__restrict__ y) {
+    const unsigned nx = (unsigned)g.nx, ny = (unsigned)g.ny, nz = (unsigned)g.nz;
+    const unsigned nxy = (unsigned)g.nxy, P = (unsigned)(g.N / 2);
+    for (unsigned q = blockIdx.x * (unsigned)kBlock + threadIdx.x; q < P;
+         q += gridDim.x * (unsigned)kBlock) {
+        const unsigned p = 2 * q;
+        const unsigned line = p / nx;
+        const unsigned i = p - line * nx, j = line % ny, k = line / ny;
+        const dbl2 xv = ld2(x + p), dv = ld2(d + p), axv = ld2(ax + p);
+        const dbl2 ayv = ld2(ay + p), azv = ld2(az + p);
+        double s0 = dv.x * xv.x, s1 = dv.y * xv.y;
+        if (i > 0) s0 = fma(ax[p - 1], x[p - 1], s0);
+        s0 = fma(axv.x, xv.y, s0);  // i + 1 < nx: the pair never ends a line
+        s1 = fma(axv.x, xv.x, s1);
+        if (i + 1 < nx - 1) s1 = fma(axv.y, x[p + 2], s1);
+        if (j > 0) {
+            const dbl2 a = ld2(ay + p - nx), v = ld2(x + p - nx);
+            s0 = fma(a.x, v.x, s0);
+            s1 = fma(a.y, v.y, s1);
+        }
+        if (j < ny - 1) {
+            const dbl2 v = ld2(x + p + nx);
+            s0 = fma(ayv.x, v.x, s0);
+            s1 = fma(ayv.y, v.y, s1);
+        }
+        if (k > 0) {
+            const dbl2 a = ld2(az + p - nxy), v = ld2(x + p - nxy);
+            s0 = fma(a.x, v.x, s0);
+            s1 = fma(a.y, v.y, s1);
+        }
+        if (k < nz - 1) {
+            const dbl2 v = ld2(x + p + nxy);
+            s0 = fma(azv.x, v.x, s0);
+            s1 = fma(azv.y, v.y, s1);
+        }
+        dbl2 o;
+        o.x = s0;
+        o.y = s1;
+        *(dbl2 *)(y + p) = o;
     }
 }
 
@@ -257,6 +316,15 @@ hipError_t launch_assemble(const Grid &g, const double *kappa, const int *bc, do
 hipError_t launch_spmv(const Grid &g, const double *d, const double *ax, const double *ay,
                        const double *az, const double *x, double *y, double *partials,
                        int *nparts, hipStream_t s) {
+    const uintptr_t al = (uintptr_t)d | (uintptr_t)ax | (uintptr_t)ay | (uintptr_t)az |
+                         (uintptr_t)x | (uintptr_t)y;
+    if (!partials && g.nx % 2 == 0 && g.N < (1LL << 31) && (al & 15) == 0) {
+        long long nb = (g.N / 2 + kBlock - 1) / kBlock;  // one pair per thread
+        if (nb < 1) nb = 1;
+        if (nparts) *nparts = 0;
+        hipLaunchKernelGGL(k_spmv2, dim3((unsigned)nb), dim3(kBlock), 0, s, g, d, ax, ay, az, x, y);
+        return hipGetLastError();
+    }
     int nb = blocks_for(g.N);
     if (nparts) *nparts = nb;
     hipLaunchKernelGGL(k_spmv, dim3(nb), dim3(kBlock), 0, s, g, d, ax, ay, az, x, y, partials);

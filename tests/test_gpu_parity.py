@@ -71,7 +71,8 @@ def test_assemble_parity(shape):
         np.testing.assert_allclose(got, want, rtol=1e-15, atol=0, err_msg=name)
 
 
-@pytest.mark.parametrize("shape", [(32, 32, 32), (7, 11, 37), (1, 1, 5), (3, 1, 350)])
+@pytest.mark.parametrize("shape", [(32, 32, 32), (7, 11, 37), (1, 1, 5), (3, 1, 350),
+                                   (5, 6, 2), (1, 1, 2), (4, 3, 64)])
 def test_spmv_and_dot_parity(shape):
     kappa, bc = case(shape, "rand", seed=3)
     S = ntd().Solver(G(kappa), bc, prec="fp64", schur="diag")
@@ -84,6 +85,26 @@ def test_spmv_and_dot_parity(shape):
     v = np.random.default_rng(2).standard_normal(shape)
     got = S.dot(G(x), G(v))
     assert abs(got - O.dot(x, v)) <= 1e-14 * np.sum(np.abs(x * v))
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (3, 1, 350), (5, 6, 2), (1, 1, 2), (7, 11, 37)])
+def test_spmv_pair_kernel_matches_single_point_kernel_bitwise(shape):
+    """Lines of even length with 16-byte aligned vectors take the SpMV over pairs
+    of points; an x and y 8 bytes off that alignment take the one-point kernel.
+    Both form every point's sum in the same order: y must agree bit for bit (odd
+    lines take the one-point kernel both ways)."""
+    kappa, bc = case(shape, "rand", seed=5)
+    S = ntd().Solver(G(kappa), bc, prec="fp64", schur="diag")
+    x = np.random.default_rng(7).standard_normal(shape)
+    n = x.size
+    y_pair = C(S.spmv(G(x)))
+    xb = torch.zeros(n + 1, dtype=torch.float64, device=DEV)
+    yb = torch.zeros(n + 1, dtype=torch.float64, device=DEV)
+    xb[1:] = G(x).reshape(-1)
+    S.spmv(xb[1:].view(shape), out=yb[1:].view(shape))
+    assert xb[1:].data_ptr() % 16 == 8
+    assert np.array_equal(y_pair, C(yb[1:]).reshape(shape))
+    S.close()
 
 
 @pytest.mark.parametrize("schur", ["newton", "diag"])
