@@ -695,14 +695,15 @@ __device__ __forceinline__ void pack_rhs_body(const XferArgs<T> &x, unsigned blk
         double v = x.r[p];
         if (x.zi) {
             const unsigned jj = line % ny, kk = line / ny;
+            // each neighbour term one fused multiply-add onto the running sum
             const double *z = x.zi;
             double s = x.d[p] * z[p];
-            if (i > 0) s += x.ax[p - 1] * z[p - 1];
-            if (i + 1 < nx) s += x.ax[p] * z[p + 1];
-            if (jj > 0) s += x.ay[p - nx] * z[p - nx];
-            if (jj + 1 < ny) s += x.ay[p] * z[p + nx];
-            if (kk > 0) s += x.az[p - nxy] * z[p - nxy];
-            if (kk + 1 < nz) s += x.az[p] * z[p + nxy];
+            if (i > 0) s = fma(x.ax[p - 1], z[p - 1], s);
+            if (i + 1 < nx) s = fma(x.ax[p], z[p + 1], s);
+            if (jj > 0) s = fma(x.ay[p - nx], z[p - nx], s);
+            if (jj + 1 < ny) s = fma(x.ay[p], z[p + nx], s);
+            if (kk > 0) s = fma(x.az[p - nxy], z[p - nxy], s);
+            if (kk + 1 < nz) s = fma(x.az[p], z[p + nxy], s);
             v -= s;
         }
         x.rp[line * (64u * EPL) + slot_of<EPL>((int)i, (int)nx)] = (T)v;
@@ -712,6 +713,64 @@ __device__ __forceinline__ void pack_rhs_body(const XferArgs<T> &x, unsigned blk
 template <typename T, int EPL>
 __global__ void __launch_bounds__(kBlock) k_pack_rhs(XferArgs<T> x) {
     pack_rhs_body<T, EPL>(x, blockIdx.x, gridDim.x);
+}
+
+// k_pack_rhs for two consecutive points of a line per thread, one pair per
+// thread, with 16-byte loads of every pair (nx even, the FP64 arrays 16-byte
+// aligned): the stencil r - A zi is bound by the load instructions it issues,
+// and a pair needs 16 where two single points need 32.  Each point's value is
+// formed in pack_rhs_body's order (bitwise the same packed right-hand side);
+// the two slots are stored one by one, since the chain split can fall inside a
+// pair (ceil(nx/2) odd).
+template <typename T, int EPL>
+__global__ void __launch_bounds__(kBlock) k_pack_rhs2(XferArgs<T> x) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const unsigned nx = (unsigned)x.nx, ny = (unsigned)x.ny, nz = (unsigned)x.nz;
+    const unsigned nxy = nx * ny, P = nxy * nz / 2;
+    const unsigned q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= P) return;
+    const unsigned p = 2 * q;
+    const unsigned line = p / nx;
+    const unsigned i = p - line * nx;
+    const d2 rv = *(const d2 *)(x.r + p);
+    double v0 = rv.x, v1 = rv.y;
+    if (x.zi) {
+        const unsigned jj = line % ny, kk = line / ny;
+        const double *z = x.zi;
+        const d2 zv = *(const d2 *)(z + p), dv = *(const d2 *)(x.d + p);
+        const d2 axv = *(const d2 *)(x.ax + p), ayv = *(const d2 *)(x.ay + p);
+        const d2 azv = *(const d2 *)(x.az + p);
+        double s0 = dv.x * zv.x, s1 = dv.y * zv.y;
+        if (i > 0) s0 = fma(x.ax[p - 1], z[p - 1], s0);
+        s0 = fma(axv.x, zv.y, s0);  // i + 1 < nx: the pair never ends a line
+        s1 = fma(axv.x, zv.x, s1);
+        if (i + 2 < nx) s1 = fma(axv.y, z[p + 2], s1);
+        if (jj > 0) {
+            const d2 a = *(const d2 *)(x.ay + p - nx), w = *(const d2 *)(z + p - nx);
+            s0 = fma(a.x, w.x, s0);
+            s1 = fma(a.y, w.y, s1);
+        }
+        if (jj + 1 < ny) {
+            const d2 w = *(const d2 *)(z + p + nx);
+            s0 = fma(ayv.x, w.x, s0);
+            s1 = fma(ayv.y, w.y, s1);
+        }
+        if (kk > 0) {
+            const d2 a = *(const d2 *)(x.az + p - nxy), w = *(const d2 *)(z + p - nxy);
+            s0 = fma(a.x, w.x, s0);
+            s1 = fma(a.y, w.y, s1);
+        }
+        if (kk + 1 < nz) {
+            const d2 w = *(const d2 *)(z + p + nxy);
+            s0 = fma(azv.x, w.x, s0);
+            s1 = fma(azv.y, w.y, s1);
+        }
+        v0 -= s0;
+        v1 -= s1;
+    }
+    T *row = x.rp + line * (64u * EPL);
+    row[slot_of<EPL>((int)i, (int)nx)] = (T)v0;
+    row[slot_of<EPL>((int)i + 1, (int)nx)] = (T)v1;
 }
 
 // Fixed-order block reduction of one double per thread; thread 0 gets the sum.
@@ -848,6 +907,16 @@ hipError_t pack_impl(const PackArgs &p, hipStream_t s) {
 template <typename T, int EPL>
 hipError_t pack_rhs_impl(const XferArgs<T> &x, hipStream_t s) {
     const long long N = (long long)x.nx * x.ny * x.nz;
+    uintptr_t al = (uintptr_t)x.r;
+    if (x.zi)
+        al |= (uintptr_t)x.zi | (uintptr_t)x.d | (uintptr_t)x.ax | (uintptr_t)x.ay |
+              (uintptr_t)x.az;
+    if (x.nx % 2 == 0 && N < (1LL << 31) && (al & 15) == 0) {
+        const long long nb = (N / 2 + kBlock - 1) / kBlock;  // one pair per thread
+        hipLaunchKernelGGL((k_pack_rhs2<T, EPL>), dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kBlock),
+                           0, s, x);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_pack_rhs<T, EPL>), dim3(xfer_blocks(N)), dim3(kBlock), 0, s, x);
     return hipGetLastError();
 }

@@ -107,6 +107,29 @@ def test_spmv_pair_kernel_matches_single_point_kernel_bitwise(shape):
     S.close()
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("smoother", ["none", "ilu0", "ilu0sym"])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (5, 7, 350), (3, 4, 37)])
+def test_pack_pair_kernel_matches_single_point_kernel_bitwise(shape, smoother, prec):
+    """The packing of the right-hand side (r, or r - A zi with the smoother)
+    takes pairs of points for lines of even length and a 16-byte aligned r, one
+    point per thread for an r 8 bytes off that alignment.  The preconditioner's
+    output must agree bit for bit (nx = 350 puts the chain split inside a pair;
+    nx = 37 takes the one-point kernel both ways)."""
+    kappa, bc = case(shape, "rand", seed=9)
+    S = ntd().Solver(G(kappa), bc, prec=prec, schur="newton", smoother=smoother)
+    r = np.random.default_rng(11).uniform(-1.0, 1.0, shape)
+    z_pair = C(S.apply(G(r)))
+    n = r.size
+    rb = torch.zeros(n + 1, dtype=torch.float64, device=DEV)
+    zb = torch.zeros(n + 1, dtype=torch.float64, device=DEV)
+    rb[1:] = G(r).reshape(-1)
+    assert rb[1:].data_ptr() % 16 == 8
+    S.apply(rb[1:].view(shape), out=zb[1:].view(shape))
+    assert np.array_equal(z_pair, C(zb[1:]).reshape(shape))
+    S.close()
+
+
 @pytest.mark.parametrize("schur", ["newton", "diag"])
 @pytest.mark.parametrize("shape,kind", [((16, 16, 16), "jump"), ((7, 11, 37), "rand"),
                                         ((9, 8, 3), "poisson"), ((1, 9, 65), "rand"),
