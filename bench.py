@@ -30,6 +30,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -159,11 +160,19 @@ def log(msg: str):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
+def _code_only(text: str) -> str:
+    """The source without comments and blank space: the recorded byte counts
+    hold for the compiled code, which comments do not change."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def sweep_hash() -> str:
     h = hashlib.sha256()
     for path in SWEEP_SRCS:
-        with open(path, "rb") as f:
-            h.update(f.read())
+        with open(path, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -2,14 +2,15 @@
 // system per wavefront.
 //
 // In a batch every right-hand side of a system reads the same line records.
-// With one right-hand side per wavefront each of them fetches every record
-// again, and the batched sweeps become bound by that traffic.  Here one
-// wavefront pair runs NR right-hand sides of one system (and level-3 half)
-// through the same chain: each line step loads the line's record once and
-// runs NR independent twisted solves with it, interleaved, so the record is
-// read once per NR right-hand sides and the NR dependency chains fill each
-// other's latency.  The steps, the twists and the memory layouts are those of
-// ntd_apply.h.
+// With one right-hand side per wavefront pair each of them loads every record
+// itself.  Here one wavefront pair runs NR right-hand sides of one system (and
+// level-3 half) through the same chain: each line step loads the line's record
+// once and runs NR independent twisted solves with it, interleaved, so the
+// record is loaded once per NR right-hand sides and the NR dependency chains
+// fill each other's latency.  The pairs of one system mostly share their record
+// reads in L2 already, so this pays only where the steps are short next to the
+// loads; the batch's tuner chooses.  The steps, the twists and the memory
+// layouts are those of ntd_apply.h.
 #pragma once
 
 #include "ntd_apply.h"

@@ -84,7 +84,8 @@ struct ApplyArgs {
     const void *rec;              // line records (rec_bytes each)
     const T *rp;                  // packed right-hand side
     T *Z;                         // packed intermediate, then final result
-    T *scratch;                   // two packed plane buffers (one per half chain)
+    T *scratch;                   // two packed plane buffers (one per half chain) for the
+                                  // upper sweep's level-2 lower results, unless in LDS
 };
 
 // Arguments of the moves between the natural FP64 layout and the packed one.
