@@ -348,3 +348,28 @@ def test_batch_plane_lds_edge_shapes(prec, tol):
         want = O.apply(O.setup(s["bands"], mode="newton"), r)
         assert relelem(a, want) <= tol, "entry %d" % e
     B.close()
+
+
+def test_batch_plane_lds_at_the_benchmark_plane_size():
+    """The LDS-plane sweeps at the batch benchmark's plane size (128^2 lines,
+    two values per lane, 65 KB of LDS per workgroup, two workgroups per CU):
+    eight 128^3 systems of the batch workload with two right-hand sides each,
+    bitwise equal to the sweeps through memory, and two entries against the
+    oracle element by element (MIXED bar)."""
+    syst = W.batch_systems(count=8, nrhs=2, n_fixed=128)
+    nrhs = 2
+    import paper_1909_09771_amd as P
+    B = P.Batch([G(s["kappa"]) for s in syst], [s["bc"] for s in syst], nrhs=nrhs,
+                prec="mixed", schur="diag")
+    assert B.set_plane_lds(True)
+    rs = [G(b) for s in syst for b in s["bs"]]
+    z_lds = [C(z) for z in B.apply(rs)]
+    assert not B.set_plane_lds(False)
+    z_mem = [C(z) for z in B.apply(rs)]
+    for e, (a, b) in enumerate(zip(z_lds, z_mem)):
+        assert np.array_equal(a, b), "entry %d" % e
+    B.close()
+    for e in (0, 13):
+        s = syst[e // nrhs]
+        want = O.apply(O.setup(O.assemble(s["kappa"], s["bc"]), mode="diag"), s["bs"][e % nrhs])
+        assert relelem(z_lds[e], want) <= 1e-5, "entry %d" % e
