@@ -872,7 +872,8 @@ hipError_t apply_batch_impl(const ApplyArgs<T> *tab, const int *active, int coun
     return hipGetLastError();
 }
 
-// Allow the LDS-plane sweeps `bytes` of dynamic LDS.
+// Allow the LDS-plane sweeps up to `bytes` of dynamic LDS (a limit of the
+// kernels, shared by every batch: the callers pass the device's maximum).
 template <typename T, int EPL>
 hipError_t apply_batch_lds_impl(size_t bytes) {
     hipError_t e = hipFuncSetAttribute((const void *)&k_apply_lower_bl<T, EPL>,

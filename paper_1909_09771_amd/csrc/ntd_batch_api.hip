@@ -294,13 +294,17 @@ size_t plane_lds_fit(int count, const int *dims, int nrhs, int prec, int epl, in
     const long long per = (long long)((size_t)per_cu / bytes);  // workgroups per CU
     const long long wgs = 2LL * count * (nrhs / nr);            // two level-3 halves each
     if (per * cus < wgs) return 0;
+    // The limit belongs to the kernel, not to this batch: allow the device's
+    // maximum, so that a later batch with smaller planes cannot lower it below
+    // what an earlier one launches with.
     hipError_t e;
     if (nr == 1)
-        e = prec == NTD_PREC_MIXED ? ntd::allow_apply_batch_lds_f32(epl, bytes)
-                                   : ntd::allow_apply_batch_lds_f64(epl, bytes);
+        e = prec == NTD_PREC_MIXED ? ntd::allow_apply_batch_lds_f32(epl, (size_t)per_block)
+                                   : ntd::allow_apply_batch_lds_f64(epl, (size_t)per_block);
     else
-        e = prec == NTD_PREC_MIXED ? ntd::allow_apply_batch_multi_lds_f32(epl, nr, bytes)
-                                   : ntd::allow_apply_batch_multi_lds_f64(epl, nr, bytes);
+        e = prec == NTD_PREC_MIXED
+                ? ntd::allow_apply_batch_multi_lds_f32(epl, nr, (size_t)per_block)
+                : ntd::allow_apply_batch_multi_lds_f64(epl, nr, (size_t)per_block);
     return e == hipSuccess ? bytes : 0;
 }
 

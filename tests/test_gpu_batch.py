@@ -373,3 +373,33 @@ def test_batch_plane_lds_at_the_benchmark_plane_size():
         s = syst[e // nrhs]
         want = O.apply(O.setup(O.assemble(s["kappa"], s["bc"]), mode="diag"), s["bs"][e % nrhs])
         assert relelem(z_lds[e], want) <= 1e-5, "entry %d" % e
+
+
+def test_batch_plane_lds_survives_a_later_smaller_batch():
+    """The dynamic-LDS limit of the LDS-plane kernels is shared by every batch:
+    a batch with small planes set up after one with 128-line planes must not
+    lower it below what the first one launches with."""
+    import paper_1909_09771_amd as P
+    big = [((8, 128, 128), "layers", 21), ((6, 128, 128), "rand", 22)]
+    small = [((5, 10, 33), "layers", 23)]
+    def mk(spec):
+        out = []
+        for shape, kind, seed in spec:
+            kappa, bc = build(kind, shape, seed)
+            out.append(dict(shape=shape, kappa=kappa, bc=bc))
+        return out
+    sb, ss = mk(big), mk(small)
+    A = P.Batch([G(s["kappa"]) for s in sb], [s["bc"] for s in sb], nrhs=1, prec="mixed",
+                schur="diag")
+    assert A.set_plane_lds(True)
+    rs = [G(r) for r in rhs_list(sb, 1, 71)]
+    z1 = [C(z) for z in A.apply(rs)]
+    Bs = P.Batch([G(s["kappa"]) for s in ss], [s["bc"] for s in ss], nrhs=1, prec="mixed",
+                 schur="diag")
+    assert Bs.set_plane_lds(True)
+    Bs.apply([G(r) for r in rhs_list(ss, 1, 72)])
+    z2 = [C(z) for z in A.apply(rs)]
+    for e, (a, b) in enumerate(zip(z1, z2)):
+        assert np.array_equal(a, b), "entry %d" % e
+    Bs.close()
+    A.close()
